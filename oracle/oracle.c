@@ -1,0 +1,310 @@
+/*
+ * oracle.c -- plain FP64 CPU reference for the PACO transform.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  The GPU library
+ * never includes, links or calls anything here, and nothing here includes or
+ * calls the GPU library: the two share no code, tables or constants.
+ *
+ * Every routine is the plain definition of what the paper computes, written
+ * for a reader to check by eye: no blocking, no fusion, no reordering beyond
+ * what the cited definition states.  Complex values are interleaved
+ * (re, im) pairs of double.  All index arithmetic is exact int64.
+ *
+ * Sign and scale (paper, section 2 "Model and Main Result"): the forward DFT
+ *   y = Omega_N x,  (Omega_N)_{k,j} = w_N^{-kj},  w_N = exp(2*pi*i/N),
+ * negative exponent, no normalisation.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* ------------------------------------------------------------------ */
+/* roots of unity                                                       */
+/* ------------------------------------------------------------------ */
+
+/* w_N^{-r} = exp(-2*pi*i*r/N) for an exactly reduced integer r in [0,N).
+ * One libm cos/sin call per value, no recurrence. */
+static void root_neg(int64_t r, int64_t N, double *re, double *im)
+{
+    double a = 2.0 * M_PI * ((double)r / (double)N);
+    *re = cos(a);
+    *im = -sin(a);
+}
+
+/* Exact power table for w_N^{-r}, r in [0,N).  Up to 2^22 entries every
+ * value is one direct libm call; above that a two-level split
+ * r = hi*L + lo is used, w^{-r} = w^{-hi*L} * w^{-lo}, both factors direct
+ * libm values, product in FP64 (about 1 ulp of FP64). */
+typedef struct {
+    int64_t N, L;      /* L == 0: direct table of N entries */
+    double *hi, *lo;   /* hi: N/L entries (or N if direct), lo: L entries */
+} roots_t;
+
+static int roots_init(roots_t *t, int64_t N)
+{
+    memset(t, 0, sizeof(*t));
+    t->N = N;
+    if (N <= ((int64_t)1 << 22)) {
+        t->hi = (double *)malloc(sizeof(double) * 2 * (size_t)N);
+        if (!t->hi) return -1;
+        for (int64_t r = 0; r < N; ++r) root_neg(r, N, &t->hi[2 * r], &t->hi[2 * r + 1]);
+        return 0;
+    }
+    int64_t L = 1;
+    while (L * L < N) L <<= 1;            /* N is a power of two here */
+    t->L = L;
+    int64_t H = N / L;
+    t->hi = (double *)malloc(sizeof(double) * 2 * (size_t)H);
+    t->lo = (double *)malloc(sizeof(double) * 2 * (size_t)L);
+    if (!t->hi || !t->lo) { free(t->hi); free(t->lo); return -1; }
+    for (int64_t h = 0; h < H; ++h) root_neg(h * L, N, &t->hi[2 * h], &t->hi[2 * h + 1]);
+    for (int64_t l = 0; l < L; ++l) root_neg(l, N, &t->lo[2 * l], &t->lo[2 * l + 1]);
+    return 0;
+}
+
+static void roots_free(roots_t *t) { free(t->hi); free(t->lo); memset(t, 0, sizeof(*t)); }
+
+/* w_N^{-r} for r in [0,N). */
+static inline void roots_get(const roots_t *t, int64_t r, double *re, double *im)
+{
+    if (t->L == 0) { *re = t->hi[2 * r]; *im = t->hi[2 * r + 1]; return; }
+    int64_t h = r / t->L, l = r % t->L;
+    double ar = t->hi[2 * h], ai = t->hi[2 * h + 1];
+    double br = t->lo[2 * l], bi = t->lo[2 * l + 1];
+    *re = ar * br - ai * bi;
+    *im = ar * bi + ai * br;
+}
+
+/* ------------------------------------------------------------------ */
+/* base-b digit reversal (appendix A.1)                                 */
+/* ------------------------------------------------------------------ */
+
+/* pi_ell(i): write i as ell base-b digits d_{ell-1} .. d_0 (most significant
+ * first), reverse the digit string, read it back.  Brute force on the digit
+ * list, for any b >= 2 (not only powers of two).  Returns -1 on bad input. */
+int64_t oracle_digit_reverse(int64_t i, int64_t b, int32_t ell)
+{
+    if (b < 2 || ell < 0 || ell > 62 || i < 0) return -1;
+    int64_t digits[64];
+    int64_t v = i;
+    for (int32_t r = 0; r < ell; ++r) { digits[r] = v % b; v /= b; } /* digits[r] = d_r */
+    if (v != 0) return -1;                                           /* i >= b^ell */
+    int64_t out = 0;
+    /* reversed string d_0 .. d_{ell-1}, d_0 most significant */
+    for (int32_t r = 0; r < ell; ++r) out = out * b + digits[r];
+    return out;
+}
+
+/* ------------------------------------------------------------------ */
+/* the DFT itself (section 2)                                           */
+/* ------------------------------------------------------------------ */
+
+/* y[k] = sum_j x[j] w_N^{-(k*j mod N)}, O(N^2).  Intended for small N. */
+int oracle_dft_naive(const double *x, double *y, int64_t N)
+{
+    if (N < 1) return -1;
+    roots_t t;
+    if (roots_init(&t, N)) return -2;
+    for (int64_t k = 0; k < N; ++k) {
+        double sr = 0.0, si = 0.0;
+        for (int64_t j = 0; j < N; ++j) {
+            int64_t r = (k * j) % N;
+            double wr, wi;
+            roots_get(&t, r, &wr, &wi);
+            double xr = x[2 * j], xi = x[2 * j + 1];
+            sr += xr * wr - xi * wi;
+            si += xr * wi + xi * wr;
+        }
+        y[2 * k] = sr;
+        y[2 * k + 1] = si;
+    }
+    roots_free(&t);
+    return 0;
+}
+
+/* Selected outputs of the same definition: y[ks[i]] for i < nk, O(N) each.
+ * Used to check single outputs of transforms too large for a full run. */
+int oracle_dft_at(const double *x, int64_t N, const int64_t *ks, int64_t nk, double *y)
+{
+    if (N < 1) return -1;
+    roots_t t;
+    if (roots_init(&t, N)) return -2;
+    for (int64_t i = 0; i < nk; ++i) {
+        int64_t k = ks[i] % N;
+        double sr = 0.0, si = 0.0;
+        for (int64_t j = 0; j < N; ++j) {
+            int64_t r = (int64_t)(((unsigned __int128)k * (unsigned __int128)j) % (unsigned __int128)N);
+            double wr, wi;
+            roots_get(&t, r, &wr, &wi);
+            double xr = x[2 * j], xi = x[2 * j + 1];
+            sr += xr * wr - xi * wi;
+            si += xr * wi + xi * wr;
+        }
+        y[2 * i] = sr;
+        y[2 * i + 1] = si;
+    }
+    roots_free(&t);
+    return 0;
+}
+
+/* Textbook recursive radix-2 decimation-in-time FFT (N a power of two):
+ * the even- and odd-indexed halves are transformed, then combined with
+ * w_n^{-k} = w_N^{-k*(N/n)}.  x is read with stride `xs` (in complex items),
+ * y is written contiguously. */
+static void fft_r2_rec(const double *x, int64_t xs, double *y, int64_t n, int64_t N, const roots_t *t)
+{
+    if (n == 1) { y[0] = x[0]; y[1] = x[1]; return; }
+    int64_t h = n / 2;
+    fft_r2_rec(x, 2 * xs, y, h, N, t);             /* even samples -> y[0..h)   */
+    fft_r2_rec(x + 2 * xs, 2 * xs, y + 2 * h, h, N, t); /* odd samples -> y[h..n) */
+    for (int64_t k = 0; k < h; ++k) {
+        double wr, wi;
+        roots_get(t, k * (N / n), &wr, &wi);
+        double er = y[2 * k], ei = y[2 * k + 1];
+        double orr = y[2 * (k + h)], oi = y[2 * (k + h) + 1];
+        double tr = orr * wr - oi * wi, ti = orr * wi + oi * wr;
+        y[2 * k] = er + tr;
+        y[2 * k + 1] = ei + ti;
+        y[2 * (k + h)] = er - tr;
+        y[2 * (k + h) + 1] = ei - ti;
+    }
+}
+
+int oracle_fft_radix2(const double *x, double *y, int64_t N)
+{
+    if (N < 1 || (N & (N - 1))) return -1;
+    roots_t t;
+    if (roots_init(&t, N)) return -2;
+    fft_r2_rec(x, 1, y, N, N, &t);
+    roots_free(&t);
+    return 0;
+}
+
+/* y = Omega_N x: the naive definition for small N, the radix-2 FFT above. */
+int oracle_dft(const double *x, double *y, int64_t N)
+{
+    if (N <= 1024 || (N & (N - 1))) return oracle_dft_naive(x, y, N);
+    return oracle_fft_radix2(x, y, N);
+}
+
+/* ------------------------------------------------------------------ */
+/* stage-wise references (sections 3.1-3.4, 4.2)                       */
+/* ------------------------------------------------------------------ */
+
+static int ilog(int64_t n, int64_t b)
+{
+    int e = 0;
+    while (n > 1) { if (n % b) return -1; n /= b; ++e; }
+    return n == 1 ? e : -1;
+}
+
+/* Phase I, output layout A_{m1} (x) I_{N2} (Lemma 1; section 3.4):
+ *   A[k1,c] = sum_{j1} X[j1,c] w_{N1}^{-k1*j1}  (inner sum of the
+ *   two-factor Cooley-Tukey identity, section 3.1), and the buffer holds
+ *   Atilde[a,c] = A[pi_{m1}(a), c]  (digit-reversed rows).
+ * x: N1 x N2 row-major.  Only the ncols columns listed in cols are formed
+ * (cols == NULL: all N2 columns, ncols ignored); out is N1 x ncols
+ * row-major, out[a*ncols + i] = Atilde[a, cols[i]]. */
+int oracle_phase1(const double *x, int64_t N1, int64_t N2, int64_t b,
+                  const int64_t *cols, int64_t ncols, double *out)
+{
+    int m1 = ilog(N1, b);
+    if (m1 < 0 || N2 < 1) return -1;
+    if (!cols) ncols = N2;
+    double *col = (double *)malloc(sizeof(double) * 2 * (size_t)N1);
+    double *dft = (double *)malloc(sizeof(double) * 2 * (size_t)N1);
+    if (!col || !dft) { free(col); free(dft); return -2; }
+    int rc = 0;
+    for (int64_t i = 0; i < ncols && rc == 0; ++i) {
+        int64_t c = cols ? cols[i] : i;
+        if (c < 0 || c >= N2) { rc = -1; break; }
+        for (int64_t j1 = 0; j1 < N1; ++j1) {
+            col[2 * j1] = x[2 * (j1 * N2 + c)];
+            col[2 * j1 + 1] = x[2 * (j1 * N2 + c) + 1];
+        }
+        rc = oracle_dft(col, dft, N1);
+        for (int64_t a = 0; a < N1; ++a) {
+            int64_t k1 = oracle_digit_reverse(a, b, m1);
+            out[2 * (a * ncols + i)] = dft[2 * k1];
+            out[2 * (a * ncols + i) + 1] = dft[2 * k1 + 1];
+        }
+    }
+    free(col);
+    free(dft);
+    return rc;
+}
+
+/* Phase II, the fused middle permutation with the top-level twiddle
+ * (section 3.3, eq. full-middle-digit-reversal; section 4.2, eq.
+ * unpacked-phase-three-layout; appendix C.2 destination-indexed twiddle):
+ * the item at Phase-I physical (a,c) represents k1 = pi_{m1}(a), is scaled
+ * by w_N^{-k1*c} (c the global column) and lands at
+ *   (u,v) = (pi_{m2}(c), pi_{m1}(a))  of the N2 x N1 output.
+ * twiddle == 0 gives the bare permutation (values moved, not scaled). */
+int oracle_phase2(const double *ws, double *z, int64_t N1, int64_t N2, int64_t b, int twiddle)
+{
+    int m1 = ilog(N1, b), m2 = ilog(N2, b);
+    if (m1 < 0 || m2 < 0) return -1;
+    int64_t N = N1 * N2;
+    roots_t t;
+    if (twiddle && roots_init(&t, N)) return -2;
+    for (int64_t a = 0; a < N1; ++a) {
+        int64_t v = oracle_digit_reverse(a, b, m1);
+        for (int64_t c = 0; c < N2; ++c) {
+            int64_t u = oracle_digit_reverse(c, b, m2);
+            double xr = ws[2 * (a * N2 + c)], xi = ws[2 * (a * N2 + c) + 1];
+            double outr = xr, outi = xi;
+            if (twiddle) {
+                double wr, wi;
+                roots_get(&t, (v * c) % N, &wr, &wi);
+                outr = xr * wr - xi * wi;
+                outi = xr * wi + xi * wr;
+            }
+            z[2 * (u * N1 + v)] = outr;
+            z[2 * (u * N1 + v) + 1] = outi;
+        }
+    }
+    if (twiddle) roots_free(&t);
+    return 0;
+}
+
+/* Phase III, input layout B_{m2} (x) I_{N1} (Lemma 1; appendix A.8):
+ * physical row u of column v holds logical input j2 = pi_{m2}(u);
+ *   Y[k2,v] = sum_{j2} Zhat[pi_{m2}(j2), v] w_{N2}^{-k2*j2},
+ * natural-order output.  z: N2 x N1 row-major.  Only the ncols columns v
+ * listed in cols are formed (cols == NULL: all N1); out is N2 x ncols
+ * row-major, out[k2*ncols + i] = Y[k2, cols[i]]. */
+int oracle_phase3(const double *z, int64_t N1, int64_t N2, int64_t b,
+                  const int64_t *cols, int64_t ncols, double *out)
+{
+    int m2 = ilog(N2, b);
+    if (m2 < 0 || N1 < 1) return -1;
+    if (!cols) ncols = N1;
+    double *col = (double *)malloc(sizeof(double) * 2 * (size_t)N2);
+    double *dft = (double *)malloc(sizeof(double) * 2 * (size_t)N2);
+    if (!col || !dft) { free(col); free(dft); return -2; }
+    int rc = 0;
+    for (int64_t i = 0; i < ncols && rc == 0; ++i) {
+        int64_t v = cols ? cols[i] : i;
+        if (v < 0 || v >= N1) { rc = -1; break; }
+        for (int64_t j2 = 0; j2 < N2; ++j2) {
+            int64_t u = oracle_digit_reverse(j2, b, m2);
+            col[2 * j2] = z[2 * (u * N1 + v)];
+            col[2 * j2 + 1] = z[2 * (u * N1 + v) + 1];
+        }
+        rc = oracle_dft(col, dft, N2);
+        for (int64_t k2 = 0; k2 < N2; ++k2) {
+            out[2 * (k2 * ncols + i)] = dft[2 * k2];
+            out[2 * (k2 * ncols + i) + 1] = dft[2 * k2 + 1];
+        }
+    }
+    free(col);
+    free(dft);
+    return rc;
+}
