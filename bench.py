@@ -1,0 +1,201 @@
+"""Benchmark of the PACO hot path on one MI355X.
+
+One step = one complete transform (Phase I LocalFFT -> Phase II fused
+permutation -> Phase III LocalFFT) of the N = 2^24 complex64 workload
+(N1 = N2 = 4096, p = 64 slabs, b = 16, N(0,1) inputs, seed 2) through the C
+ABI.  Inputs are resident in HBM before the timed region.  Prints one JSON
+line: GFLOP/s = 5 N log2 N / t, plus the dominant kernel's roofline (HIP
+events on the stream the kernels run on) and the CPU oracle baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "FFT GFLOP/s (5N·log2N/t) + % HBM roofline, N=2^24 c64; MFMA-split vs FP32"
+WORKLOAD = dict(name="c2", N1=4096, N2=4096, p=64, b=16, gen="normal", seed=2)
+KERNEL_SOURCES = ["paper_2609_06449_amd/csrc/local_fft.hip", "paper_2609_06449_amd/csrc/middle.hip"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_c2.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    return k.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(x, N: int, budget_s: float):
+    """The FP64 oracle (recursive radix-2, single thread) on whole N-point
+    transforms of the same input, repeated until ~budget_s of CPU work."""
+    import numpy as np
+    import oracle
+
+    xs = x.astype(np.complex128)
+    times = []
+    ref = None
+    t_all = time.perf_counter()
+    while True:
+        t0 = time.perf_counter()
+        ref = oracle.fft_radix2(xs)
+        times.append(time.perf_counter() - t0)
+        if time.perf_counter() - t_all > budget_s or len(times) >= 20:
+            break
+    t = sorted(times)[len(times) // 2]
+    return ref, dict(value=round(5.0 * N * math.log2(N) / t / 1e9, 3), unit="GFLOP/s", cores=1,
+                     kind="oracle",
+                     sample=f"{len(times)} full N=2^{int(math.log2(N))} transforms of the bench input "
+                            f"(median {t:.3f} s each, {sum(times):.1f} s total); FP64 recursive radix-2, one thread")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--skip-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run plain 256 MiB device copies (traffic-counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "sharding of the path is described, not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2609_06449_amd import inputs, paco
+
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    N1, N2, p, b = WORKLOAD["N1"], WORKLOAD["N2"], WORKLOAD["p"], WORKLOAD["b"]
+    N = N1 * N2
+    x = inputs.make(WORKLOAD["gen"], N, WORKLOAD["seed"])
+    xd = torch.from_numpy(x).to(dev)
+    out = torch.empty(N, dtype=torch.complex64, device=dev)
+    ws = torch.empty(N, dtype=torch.complex64, device=dev)
+    plan = paco.Plan(N1, N2, p, b)
+    stream = torch.cuda.current_stream()
+    sh = stream.cuda_stream
+
+    def step():
+        plan.execute(xd.data_ptr(), out.data_ptr(), ws.data_ptr(), sh)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # ---- headline: K back-to-back transforms -------------------------------
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    gflops = 5.0 * N * math.log2(N) / (ms_per_step * 1e-3) / 1e9
+
+    # ---- per-phase durations with HIP events on the same stream ------------
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    for i in range(args.steps):
+        e = ev[i]
+        e[0].record(stream)
+        plan.execute_stage(1, xd.data_ptr(), ws.data_ptr(), sh)
+        e[1].record(stream)
+        plan.execute_stage(2, ws.data_ptr(), out.data_ptr(), sh)
+        e[2].record(stream)
+        plan.execute_stage(3, out.data_ptr(), out.data_ptr(), sh)
+        e[3].record(stream)
+    torch.cuda.synchronize()
+    ph = np.array([[ev[i][k].elapsed_time(ev[i][k + 1]) for k in range(3)] for i in range(args.steps)])
+    ph_us = ph.mean(axis=0) * 1e3
+
+    # ---- cold: a 1 GiB scratch write between transforms flushes the 256 MB MALL
+    flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    cold = []
+    for i in range(min(args.steps, 50)):
+        flush.fill_(float(i))
+        a = torch.cuda.Event(enable_timing=True)
+        z = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        step()
+        z.record(stream)
+        torch.cuda.synchronize()
+        cold.append(a.elapsed_time(z))
+    del flush
+    cold_ms = float(np.median(cold))
+
+    if args.calibrate_copy:
+        src = torch.empty(1 << 25, dtype=torch.complex64, device=dev)
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    y = out.cpu().numpy()
+
+    # the dominant kernel: the slowest of the three phases (each one launch)
+    names = ["phase1 local_fft_kernel<12>", "phase2 middle_kernel", "phase3 local_fft_kernel<12>"]
+    dom = int(np.argmax(ph_us))
+    alg_bytes = 16.0 * N  # each phase reads and writes N complex64 items once
+    achieved = alg_bytes / (ph_us[dom] * 1e-6) / 1e9
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=load_traffic(names[dom]),
+                    kernel=names[dom], alg_bytes_per_launch=int(alg_bytes))
+
+    rec = dict(metric=METRIC, value=round(gflops, 1), unit="GFLOP/s", n_gpus=1, steps=args.steps,
+               warmup=args.warmup, ms_per_step=round(ms_per_step, 5), higher_is_better=True,
+               scaling="weak", vs_baseline=None, dtype="f32", data="synthetic",
+               config=dict(workload="single 1D complex64 DFT, N=2^24 as N1=N2=4096, p=64 slabs, b=16, "
+                                    "N(0,1) inputs (seed 2), plain FP32 path",
+                           N=N, N1=N1, N2=N2, p=p, b=b, precision="fp32", parallelism="1 GPU, 64 HBM slabs"),
+               roofline=roofline,
+               hbm_frac_3pass=round(48.0 * N / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+               phase_us=[round(float(v), 2) for v in ph_us],
+               cold_ms_per_step=round(cold_ms, 5),
+               cold_hbm_frac_3pass=round(48.0 * N / (cold_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+               plan=plan.description)
+
+    if not args.skip_cpu_baseline:
+        import oracle
+
+        ref, cb = cpu_baseline(x, N, args.cpu_budget)
+        rec["cpu_baseline"] = cb
+        rec["rel_l2_vs_oracle"] = float(oracle.rel_l2(y, ref))
+    else:
+        rec["cpu_baseline"] = None
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,116 @@
+/*
+ * paco.h -- C ABI of the MI355X (gfx950) PACO transform library.
+ *
+ * PACO computes the canonical forward DFT
+ *     y = Omega_N x,   (Omega_N)_{k,j} = w_N^{-kj},   w_N = exp(2*pi*i/N)
+ * (paper, section 2: negative exponent, no normalisation) as three phases
+ * (section 3, eq. paco-composite-op):
+ *     Phase I   LocalFFT in output layout  A_{m1} (x) I_{N2},  A = P_pi Omega
+ *     Phase II  one fused permutation pi_m(a ++ c) = pi_{m2}(c) ++ pi_{m1}(a)
+ *               with the top-level twiddle w_N^{-pi_{m1}(a) c}
+ *     Phase III LocalFFT in input layout   B_{m2} (x) I_{N1},  B = Omega P_pi
+ * On one GPU the paper's p processors are p column slabs of the matrices
+ * below, all resident in the same HBM.
+ *
+ * Data layout (section 2, eqs. input-slab-owner, factor-swapped-output-view,
+ * output-slab-owner):
+ *   in   N1 x N2 row-major complex64 (interleaved float re, im):
+ *        in[j1*N2 + j2] = x[j1*N2 + j2]  -- i.e. simply x.
+ *        Source slab q = columns [q*N2/p, (q+1)*N2/p).
+ *   out  N2 x N1 row-major complex64:  out[k2*N1 + k1] = y[k1 + k2*N1]
+ *        -- i.e. simply y in natural order.
+ *        Target slab q' = columns [q'*N1/p, (q'+1)*N1/p).
+ *   workspace  N1*N2 complex64 (N*8 bytes) of device memory.
+ *
+ * Ownership: the caller allocates and owns in, out, workspace (device
+ * memory) and the stream.  A plan owns only its small device tables
+ * (digit-reversal maps and twiddle tables generated in FP64 on the host and
+ * rounded once to FP32), allocated by paco_plan_create and released by
+ * paco_plan_destroy.  A plan is immutable after creation and may be shared
+ * by threads; executions that share a workspace must not overlap.
+ *
+ * Errors: every call returns paco_status (0 == PACO_OK); no exception
+ * crosses the ABI.  On failure out-parameters are set to NULL/0 and nothing
+ * leaks; paco_last_error() returns a thread-local detail string.  Execute
+ * calls only enqueue work on the given stream and never synchronise: a
+ * device fault surfaces at the caller's next synchronisation.  Arguments
+ * are checked (null or misaligned pointers, undersized workspace) before
+ * anything is enqueued.
+ */
+#ifndef PACO_H
+#define PACO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PACO_OK = 0,
+    PACO_ERR_INVALID_ARG = 1,   /* null/misaligned pointer, bad stage, p < 2 ... */
+    PACO_ERR_NOT_POWER_OF_B = 2,/* N1 or N2 not a power of b, or b not 2^t >= 2 */
+    PACO_ERR_DIVISIBILITY = 3,  /* p does not divide N1 and N2                   */
+    PACO_ERR_UNSUPPORTED = 4,   /* valid for the paper, not built here (size)    */
+    PACO_ERR_WORKSPACE = 5,     /* workspace smaller than paco_plan_workspace_size */
+    PACO_ERR_ALLOC = 6,         /* device or host allocation failed              */
+    PACO_ERR_HIP = 7            /* a HIP runtime call failed (detail in last_error) */
+} paco_status;
+
+typedef enum {
+    PACO_C64 = 0                /* complex64 I/O, FP32 arithmetic on the vector ALUs */
+} paco_dtype;
+
+/* paco_execute_stage flags */
+#define PACO_NO_TWIDDLE 1       /* stage 2 only: apply the bare permutation pi_m */
+
+typedef struct paco_plan_s paco_plan;
+
+/* Checks the problem contract of section 2 with the proofs' divisibility
+ * condition (eq. exact-divisibility): b = 2^t with t >= 1; N1 = b^m1 and
+ * N2 = b^m2 with m1, m2 >= 1; p >= 2 with p | N1 and p | N2 (p itself need
+ * not be a power of b; the balance argument of section 4.2 uses only the
+ * divisibility).  Pure host code: no HIP call, usable without a GPU.
+ * Returns PACO_ERR_UNSUPPORTED for sizes this build has no kernels for
+ * (N1 or N2 above 2^16, or N1*N2 above 2^30). */
+paco_status paco_plan_validate(int64_t N1, int64_t N2, int64_t p, int32_t b, paco_dtype dt);
+
+/* Validates, builds the pass plan and uploads the plan's tables to the
+ * current HIP device.  *plan is NULL on failure. */
+paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int32_t b,
+                             paco_dtype dt);
+
+/* Bytes of device workspace paco_execute needs (N1*N2*8 for PACO_C64). */
+paco_status paco_plan_workspace_size(const paco_plan *plan, size_t *bytes);
+
+/* Runs Phase I (in -> workspace), Phase II (workspace -> out) and Phase III
+ * (out -> out, in place) on `stream` (a hipStream_t; NULL = default stream).
+ * in == out is allowed.  in, out and workspace are device pointers, 8-byte
+ * aligned, of N1*N2 complex64 each (workspace: at least the reported size). */
+paco_status paco_execute(const paco_plan *plan, const void *in, void *out, void *workspace,
+                         size_t workspace_bytes, void *stream);
+
+/* Runs one phase alone, for stage-wise checks and per-phase timing:
+ *   stage 1: src (N1 x N2, x) -> dst (N1 x N2, Phase-I layout Atilde)
+ *   stage 2: src (N1 x N2, Atilde) -> dst (N2 x N1, Zhat); flags may hold
+ *            PACO_NO_TWIDDLE; src and dst must not overlap
+ *   stage 3: src (N2 x N1, Zhat) -> dst (N2 x N1, Y); src == dst allowed
+ * Stage 1 also allows src == dst. */
+paco_status paco_execute_stage(const paco_plan *plan, int stage, int flags, const void *src,
+                               void *dst, void *stream);
+
+/* Number of device kernel launches paco_execute enqueues for this plan, and
+ * a short human-readable description of the pass plan. */
+paco_status paco_plan_describe(const paco_plan *plan, int32_t *launches, char *buf, size_t buflen);
+
+paco_status paco_plan_destroy(paco_plan *plan);
+
+const char *paco_status_string(paco_status st);
+const char *paco_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PACO_H */

@@ -138,8 +138,8 @@ int oracle_dft_at(const double *x, int64_t N, const int64_t *ks, int64_t nk, dou
     for (int64_t i = 0; i < nk; ++i) {
         int64_t k = ks[i] % N;
         double sr = 0.0, si = 0.0;
-        for (int64_t j = 0; j < N; ++j) {
-            int64_t r = (int64_t)(((unsigned __int128)k * (unsigned __int128)j) % (unsigned __int128)N);
+        int64_t r = 0;                          /* r = (k*j) mod N, kept exact */
+        for (int64_t j = 0; j < N; ++j, r = (r + k >= N) ? r + k - N : r + k) {
             double wr, wi;
             roots_get(&t, r, &wr, &wi);
             double xr = x[2 * j], xi = x[2 * j + 1];

@@ -1,0 +1,434 @@
+// C ABI of the PACO library: validation, planning and execution on the
+// caller's stream.  Host code only; the kernels live in local_fft.hip and
+// middle.hip.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "paco.h"
+#include "paco_internal.h"
+
+using paco::LocalPass;
+using paco::MiddlePass;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+paco_status fail(paco_status st, const std::string &msg)
+{
+    g_last_error = msg;
+    return st;
+}
+
+paco_status hip_fail(hipError_t e, const char *what)
+{
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return PACO_ERR_HIP;
+}
+
+int ilog2_exact(int64_t n)
+{
+    if (n < 1 || (n & (n - 1))) return -1;
+    int l = 0;
+    while ((int64_t(1) << l) < n) ++l;
+    return l;
+}
+
+// pi_ell in base b = 2^t: the ell groups of t bits in the opposite order
+// (appendix A.1).
+int32_t digit_reverse(int64_t i, int t, int ell)
+{
+    int64_t r = 0;
+    for (int g = 0; g < ell; ++g) {
+        r = (r << t) | (i & ((int64_t(1) << t) - 1));
+        i >>= t;
+    }
+    return int32_t(r);
+}
+
+// w_M^{-r} = exp(-2 pi i r / M), evaluated in FP64 from the exact integer r
+// and rounded once to FP32.
+float2 root_neg(int64_t r, int64_t M)
+{
+    const double a = 2.0 * M_PI * (double(r) / double(M));
+    return make_float2(float(std::cos(a)), float(-std::sin(a)));
+}
+
+constexpr int kMaxLocalLog2 = 16;  // N1, N2 <= 2^16 (at most two on-chip passes)
+constexpr int kMaxTotalLog2 = 32;  // N1*N2 <= 2^32
+
+}  // namespace
+
+struct paco_plan_s {
+    int64_t N1 = 0, N2 = 0, p = 0;
+    int32_t b = 0;
+    paco_dtype dt = PACO_C64;
+    int t = 0, m1 = 0, m2 = 0, l1 = 0, l2 = 0, lN = 0, lL = 0, lLo = 0;
+    int device = 0;
+    void *dev_tables = nullptr;
+    std::vector<LocalPass> phase1, phase3;  // src/dst filled per execution
+    MiddlePass mid{};
+    std::string desc;
+};
+
+extern "C" {
+
+const char *paco_status_string(paco_status st)
+{
+    switch (st) {
+    case PACO_OK: return "ok";
+    case PACO_ERR_INVALID_ARG: return "invalid argument";
+    case PACO_ERR_NOT_POWER_OF_B: return "N1/N2 not a power of b (or b not a power of two >= 2)";
+    case PACO_ERR_DIVISIBILITY: return "p must satisfy p >= 2, p | N1 and p | N2";
+    case PACO_ERR_UNSUPPORTED: return "size not supported by this build";
+    case PACO_ERR_WORKSPACE: return "workspace too small";
+    case PACO_ERR_ALLOC: return "allocation failed";
+    case PACO_ERR_HIP: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+const char *paco_last_error(void) { return g_last_error.c_str(); }
+
+paco_status paco_plan_validate(int64_t N1, int64_t N2, int64_t p, int32_t b, paco_dtype dt)
+{
+    if (dt != PACO_C64) return fail(PACO_ERR_INVALID_ARG, "unknown dtype");
+    const int t = ilog2_exact(b);
+    if (b < 2 || t < 1) return fail(PACO_ERR_NOT_POWER_OF_B, "b must be 2^t with t >= 1");
+    const int l1 = ilog2_exact(N1), l2 = ilog2_exact(N2);
+    if (N1 < 2 || N2 < 2 || l1 < 0 || l2 < 0 || l1 % t || l2 % t)
+        return fail(PACO_ERR_NOT_POWER_OF_B, "N1 and N2 must be powers of b (b^m with m >= 1)");
+    if (p < 2 || N1 % p || N2 % p) return fail(PACO_ERR_DIVISIBILITY, "need p >= 2, p | N1, p | N2");
+    if (l1 > kMaxLocalLog2 || l2 > kMaxLocalLog2 || l1 + l2 > kMaxTotalLog2)
+        return fail(PACO_ERR_UNSUPPORTED, "this build supports N1, N2 <= 2^16 and N1*N2 <= 2^32");
+    if (N1 / p < 16 || N2 / p < 16)
+        g_last_error = "note: slab width N1/p or N2/p below 16 items (one 128-byte line)";
+    else
+        g_last_error.clear();
+    return PACO_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Digit-aligned split of a local transform of 2^l = b^m items into on-chip
+// passes: one pass up to 2^12 items, otherwise two passes n1 * n2 with
+// n1 = b^ceil(m/2) (the balanced split of section 4.1).
+void split_local(int l, int t, int &la, int &lb)
+{
+    if (l <= paco::kMaxOnChipLog2) {
+        la = l;
+        lb = 0;
+        return;
+    }
+    const int m = l / t;
+    la = ((m + 1) / 2) * t;
+    lb = l - la;
+}
+
+}  // namespace
+
+extern "C" {
+
+paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int32_t b,
+                             paco_dtype dt)
+{
+    if (!plan) return fail(PACO_ERR_INVALID_ARG, "plan out-pointer is NULL");
+    *plan = nullptr;
+    paco_status st = paco_plan_validate(N1, N2, p, b, dt);
+    if (st != PACO_OK) return st;
+
+    paco_plan_s *P = new (std::nothrow) paco_plan_s();
+    if (!P) return fail(PACO_ERR_ALLOC, "host allocation failed");
+    P->N1 = N1;
+    P->N2 = N2;
+    P->p = p;
+    P->b = b;
+    P->dt = dt;
+    P->t = ilog2_exact(b);
+    P->l1 = ilog2_exact(N1);
+    P->l2 = ilog2_exact(N2);
+    P->m1 = P->l1 / P->t;
+    P->m2 = P->l2 / P->t;
+    P->lN = P->l1 + P->l2;
+    P->lL = P->l1 > P->l2 ? P->l1 : P->l2;
+    P->lLo = (P->lN + 1) / 2;
+
+    int a1, b1, a3, b3;
+    split_local(P->l1, P->t, a1, b1);
+    split_local(P->l2, P->t, a3, b3);
+    if (a1 > paco::kMaxOnChipLog2 || b1 > paco::kMaxOnChipLog2 || a3 > paco::kMaxOnChipLog2 ||
+        b3 > paco::kMaxOnChipLog2) {
+        delete P;
+        return fail(PACO_ERR_UNSUPPORTED, "local transform needs more than two on-chip passes");
+    }
+
+    // ---- host tables -------------------------------------------------------
+    const int64_t L = int64_t(1) << P->lL, Lo = int64_t(1) << P->lLo, Hi = (int64_t(1) << P->lN) >> P->lLo;
+    std::vector<int32_t> pi1(N1), pi2(N2), sa1(int64_t(1) << a1), sb1(int64_t(1) << b1),
+        sa3(int64_t(1) << a3), sb3(int64_t(1) << b3);
+    for (int64_t i = 0; i < N1; ++i) pi1[i] = digit_reverse(i, P->t, P->m1);
+    for (int64_t i = 0; i < N2; ++i) pi2[i] = digit_reverse(i, P->t, P->m2);
+    for (size_t i = 0; i < sa1.size(); ++i) sa1[i] = digit_reverse(i, P->t, a1 / P->t);
+    for (size_t i = 0; i < sb1.size(); ++i) sb1[i] = digit_reverse(i, P->t, b1 / P->t);
+    for (size_t i = 0; i < sa3.size(); ++i) sa3[i] = digit_reverse(i, P->t, a3 / P->t);
+    for (size_t i = 0; i < sb3.size(); ++i) sb3[i] = digit_reverse(i, P->t, b3 / P->t);
+    std::vector<float2> tw(L), thi(Hi), tlo(Lo);
+    for (int64_t r = 0; r < L; ++r) tw[r] = root_neg(r, L);
+    const int64_t N = int64_t(1) << P->lN;
+    for (int64_t h = 0; h < Hi; ++h) thi[h] = root_neg(h * Lo, N);
+    for (int64_t l = 0; l < Lo; ++l) tlo[l] = root_neg(l, N);
+
+    // one device allocation, 256-byte aligned pieces
+    struct Piece { const void *src; size_t bytes; size_t off; };
+    std::vector<Piece> pieces = {
+        {pi1.data(), pi1.size() * 4, 0}, {pi2.data(), pi2.size() * 4, 0},
+        {sa1.data(), sa1.size() * 4, 0}, {sb1.data(), sb1.size() * 4, 0},
+        {sa3.data(), sa3.size() * 4, 0}, {sb3.data(), sb3.size() * 4, 0},
+        {tw.data(), tw.size() * 8, 0},   {thi.data(), thi.size() * 8, 0},
+        {tlo.data(), tlo.size() * 8, 0}};
+    size_t total = 0;
+    for (auto &pc : pieces) {
+        pc.off = total;
+        total += (pc.bytes + 255) & ~size_t(255);
+    }
+    hipError_t e = hipGetDevice(&P->device);
+    if (e != hipSuccess) { delete P; return hip_fail(e, "hipGetDevice"); }
+    e = paco::local_fft_prepare();
+    if (e != hipSuccess) { delete P; return hip_fail(e, "hipFuncSetAttribute"); }
+    e = hipMalloc(&P->dev_tables, total);
+    if (e != hipSuccess) { P->dev_tables = nullptr; delete P; return fail(PACO_ERR_ALLOC, std::string("hipMalloc: ") + hipGetErrorString(e)); }
+    std::vector<unsigned char> staging(total, 0);
+    for (auto &pc : pieces) std::memcpy(staging.data() + pc.off, pc.src, pc.bytes);
+    e = hipMemcpy(P->dev_tables, staging.data(), total, hipMemcpyHostToDevice);
+    if (e != hipSuccess) { (void)hipFree(P->dev_tables); delete P; return hip_fail(e, "hipMemcpy"); }
+    auto at = [&](int i) { return static_cast<unsigned char *>(P->dev_tables) + pieces[i].off; };
+    const int32_t *d_pi1 = reinterpret_cast<const int32_t *>(at(0));
+    const int32_t *d_pi2 = reinterpret_cast<const int32_t *>(at(1));
+    const int32_t *d_sa1 = reinterpret_cast<const int32_t *>(at(2));
+    const int32_t *d_sb1 = reinterpret_cast<const int32_t *>(at(3));
+    const int32_t *d_sa3 = reinterpret_cast<const int32_t *>(at(4));
+    const int32_t *d_sb3 = reinterpret_cast<const int32_t *>(at(5));
+    const float2 *d_tw = reinterpret_cast<const float2 *>(at(6));
+    const float2 *d_thi = reinterpret_cast<const float2 *>(at(7));
+    const float2 *d_tlo = reinterpret_cast<const float2 *>(at(8));
+
+    auto base_pass = [&](int64_t ld, int64_t ncols) {
+        LocalPass q{};
+        q.ld = ld;
+        q.ncols = ncols;
+        q.tw = d_tw;
+        q.log2L = P->lL;
+        q.n_outer = 1;
+        return q;
+    };
+    char buf[512];
+    std::string desc;
+
+    // ---- Phase I: A_{m1} (x) I_{N2}, output layout (Lemma 1) -------------
+    if (b1 == 0) {
+        LocalPass q = base_pass(N2, N2);
+        q.log2n = a1;
+        q.j_in = 1;
+        q.k_out = 1;
+        q.perm_out = d_pi1;                 // logical k1 -> row pi_{m1}(k1)
+        q.log2T = paco::choose_log2T(a1, N2);
+        P->phase1.push_back(q);
+    } else {
+        // first child: length n1 = 2^a1 over j1 (row stride n2), batch j2;
+        // its frequency k1 lands at physical row field pi(k1)
+        const int64_t n2 = int64_t(1) << b1;
+        LocalPass A = base_pass(N2, N2);
+        A.log2n = a1;
+        A.n_outer = n2;
+        A.o_in = 1;
+        A.j_in = n2;
+        A.o_out = 1;
+        A.k_out = n2;
+        A.perm_out = d_sa1;
+        A.log2T = paco::choose_log2T(a1, N2);
+        // second child: length n2 over j2 for each physical a, twiddle
+        // w_{N1}^{-pi(a) j2} from the represented k1 = pi(a) (appendix A.2)
+        LocalPass B = base_pass(N2, N2);
+        B.log2n = b1;
+        B.n_outer = int64_t(1) << a1;
+        B.o_in = n2;
+        B.j_in = 1;
+        B.o_out = n2;
+        B.k_out = 1;
+        B.perm_out = d_sb1;
+        B.pre_tw = 1;
+        B.log2M = P->l1;
+        B.tw_perm = d_sa1;
+        B.log2T = paco::choose_log2T(b1, N2);
+        P->phase1.push_back(A);
+        P->phase1.push_back(B);
+    }
+    // ---- Phase III: B_{m2} (x) I_{N1}, input layout ----------------------
+    if (b3 == 0) {
+        LocalPass q = base_pass(N1, N1);
+        q.log2n = a3;
+        q.j_in = 1;
+        q.k_out = 1;
+        q.perm_in = d_pi2;                  // logical j2 read from row pi_{m2}(j2)
+        q.log2T = paco::choose_log2T(a3, N1);
+        P->phase3.push_back(q);
+    } else {
+        // logical j = j1*s2 + j2 sits at row pi(j2)*s1 + pi(j1)
+        const int64_t s1 = int64_t(1) << a3, s2 = int64_t(1) << b3;
+        LocalPass A = base_pass(N1, N1);
+        A.log2n = a3;
+        A.n_outer = s2;
+        A.o_in = s1;
+        A.j_in = 1;
+        A.perm_in = d_sa3;
+        A.o_out = s1;
+        A.k_out = 1;
+        A.log2T = paco::choose_log2T(a3, N1);
+        LocalPass B = base_pass(N1, N1);
+        B.log2n = b3;
+        B.n_outer = s1;
+        B.o_in = 1;
+        B.j_in = s1;
+        B.perm_in = d_sb3;
+        B.pre_tw = 1;
+        B.log2M = P->l2;
+        B.o_out = 1;
+        B.k_out = s1;
+        B.log2T = paco::choose_log2T(b3, N1);
+        P->phase3.push_back(A);
+        P->phase3.push_back(B);
+    }
+    // ---- Phase II ---------------------------------------------------------
+    P->mid.N1 = N1;
+    P->mid.N2 = N2;
+    P->mid.pi1 = d_pi1;
+    P->mid.pi2 = d_pi2;
+    P->mid.tw_hi = d_thi;
+    P->mid.tw_lo = d_tlo;
+    P->mid.log2N = P->lN;
+    P->mid.log2Lo = P->lLo;
+    P->mid.twiddle = 1;
+
+    for (auto *ph : {&P->phase1, &P->phase3}) {
+        desc += ph == &P->phase1 ? "phase1[" : " phase2[tile64x64] phase3[";
+        for (const auto &q : *ph) {
+            const paco::LocalLaunch g = paco::local_fft_geometry(q);
+            std::snprintf(buf, sizeof buf, " n=2^%d T=%d outer=%lld wg=%lld thr=%d lds=%zu", q.log2n, 1 << q.log2T,
+                          (long long)q.n_outer, (long long)g.groups, g.threads, g.lds_bytes);
+            desc += buf;
+        }
+        desc += " ]";
+    }
+    P->desc = desc;
+    *plan = P;
+    return PACO_OK;
+}
+
+paco_status paco_plan_workspace_size(const paco_plan *plan, size_t *bytes)
+{
+    if (!bytes) return fail(PACO_ERR_INVALID_ARG, "bytes out-pointer is NULL");
+    *bytes = 0;
+    if (!plan) return fail(PACO_ERR_INVALID_ARG, "plan is NULL");
+    *bytes = size_t(plan->N1) * size_t(plan->N2) * 8;
+    return PACO_OK;
+}
+
+paco_status paco_plan_describe(const paco_plan *plan, int32_t *launches, char *buf, size_t buflen)
+{
+    if (!plan) return fail(PACO_ERR_INVALID_ARG, "plan is NULL");
+    if (launches) *launches = int32_t(plan->phase1.size() + 1 + plan->phase3.size());
+    if (buf && buflen) {
+        std::strncpy(buf, plan->desc.c_str(), buflen - 1);
+        buf[buflen - 1] = 0;
+    }
+    return PACO_OK;
+}
+
+paco_status paco_plan_destroy(paco_plan *plan)
+{
+    if (!plan) return PACO_OK;
+    if (plan->dev_tables) (void)hipFree(plan->dev_tables);
+    delete plan;
+    return PACO_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+bool bad_ptr(const void *p) { return !p || (reinterpret_cast<uintptr_t>(p) & 7); }
+
+paco_status run_local(const std::vector<LocalPass> &passes, const void *src, void *dst, hipStream_t s)
+{
+    for (size_t i = 0; i < passes.size(); ++i) {
+        LocalPass q = passes[i];
+        q.src = static_cast<const float2 *>(i == 0 ? src : dst);
+        q.dst = static_cast<float2 *>(dst);
+        hipError_t e = paco::launch_local_fft(q, s);
+        if (e != hipSuccess) return hip_fail(e, "local FFT launch");
+    }
+    return PACO_OK;
+}
+
+paco_status run_middle(const paco_plan *plan, const void *src, void *dst, int twiddle, hipStream_t s)
+{
+    MiddlePass m = plan->mid;
+    m.ws = static_cast<const float2 *>(src);
+    m.out = static_cast<float2 *>(dst);
+    m.twiddle = twiddle;
+    hipError_t e = paco::launch_middle(m, s);
+    if (e != hipSuccess) return hip_fail(e, "phase II launch");
+    return PACO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+paco_status paco_execute(const paco_plan *plan, const void *in, void *out, void *workspace,
+                         size_t workspace_bytes, void *stream)
+{
+    if (!plan) return fail(PACO_ERR_INVALID_ARG, "plan is NULL");
+    if (bad_ptr(in) || bad_ptr(out) || bad_ptr(workspace))
+        return fail(PACO_ERR_INVALID_ARG, "in/out/workspace must be non-NULL and 8-byte aligned");
+    const size_t need = size_t(plan->N1) * size_t(plan->N2) * 8;
+    if (workspace_bytes < need) return fail(PACO_ERR_WORKSPACE, "workspace smaller than N1*N2*8 bytes");
+    const size_t wb = reinterpret_cast<uintptr_t>(workspace), ib = reinterpret_cast<uintptr_t>(in),
+                 ob = reinterpret_cast<uintptr_t>(out);
+    if ((wb < ib + need && ib < wb + need) || (wb < ob + need && ob < wb + need))
+        return fail(PACO_ERR_INVALID_ARG, "workspace overlaps in or out");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    paco_status st = run_local(plan->phase1, in, workspace, s);
+    if (st != PACO_OK) return st;
+    st = run_middle(plan, workspace, out, 1, s);
+    if (st != PACO_OK) return st;
+    return run_local(plan->phase3, out, out, s);
+}
+
+paco_status paco_execute_stage(const paco_plan *plan, int stage, int flags, const void *src, void *dst,
+                               void *stream)
+{
+    if (!plan) return fail(PACO_ERR_INVALID_ARG, "plan is NULL");
+    if (bad_ptr(src) || bad_ptr(dst)) return fail(PACO_ERR_INVALID_ARG, "src/dst must be non-NULL and 8-byte aligned");
+    if (flags & ~PACO_NO_TWIDDLE) return fail(PACO_ERR_INVALID_ARG, "unknown flags");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    switch (stage) {
+    case 1: return run_local(plan->phase1, src, dst, s);
+    case 2: {
+        const size_t need = size_t(plan->N1) * size_t(plan->N2) * 8;
+        const uintptr_t a = reinterpret_cast<uintptr_t>(src), b = reinterpret_cast<uintptr_t>(dst);
+        if (a < b + need && b < a + need) return fail(PACO_ERR_INVALID_ARG, "stage 2 src and dst overlap");
+        return run_middle(plan, src, dst, (flags & PACO_NO_TWIDDLE) ? 0 : 1, s);
+    }
+    case 3: return run_local(plan->phase3, src, dst, s);
+    default: return fail(PACO_ERR_INVALID_ARG, "stage must be 1, 2 or 3");
+    }
+}
+
+}  // extern "C"

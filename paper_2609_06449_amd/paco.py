@@ -1,0 +1,154 @@
+"""Thin ctypes binding of libpaco.so, with the C ABI's names (include/paco.h).
+
+Argument marshalling only: every step of the transform runs in the HIP
+kernels of the library.  There is no fallback -- if the library is missing
+the import fails loudly.  Device pointers and streams are plain integers
+(e.g. ``tensor.data_ptr()`` and ``torch.cuda.current_stream().cuda_stream``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpaco.so")
+
+PACO_OK = 0
+PACO_ERR_INVALID_ARG = 1
+PACO_ERR_NOT_POWER_OF_B = 2
+PACO_ERR_DIVISIBILITY = 3
+PACO_ERR_UNSUPPORTED = 4
+PACO_ERR_WORKSPACE = 5
+PACO_ERR_ALLOC = 6
+PACO_ERR_HIP = 7
+
+PACO_C64 = 0
+
+PACO_NO_TWIDDLE = 1
+
+# every symbol include/paco.h declares
+EXPORTED = (
+    "paco_plan_validate", "paco_plan_create", "paco_plan_workspace_size", "paco_execute",
+    "paco_execute_stage", "paco_plan_describe", "paco_plan_destroy", "paco_status_string",
+    "paco_last_error",
+)
+
+
+class PacoError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status} ({detail})")
+        self.status = status
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is not built; run `python -m paper_2609_06449_amd.build`")
+    # PyTorch-ROCm ships its own libamdhip64 (same soname).  Loading torch first
+    # makes the dynamic linker resolve libpaco.so's HIP runtime to that copy, so
+    # the process holds one HIP runtime and torch tensors/streams are valid in
+    # the library.  Without torch the system ROCm runtime is used.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(_LIB_PATH)
+    i64, i32, P, sz = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t
+    st = ctypes.c_int
+    sig = {
+        "paco_plan_validate": (st, [i64, i64, i64, i32, st]),
+        "paco_plan_create": (st, [ctypes.POINTER(P), i64, i64, i64, i32, st]),
+        "paco_plan_workspace_size": (st, [P, ctypes.POINTER(sz)]),
+        "paco_execute": (st, [P, P, P, P, sz, P]),
+        "paco_execute_stage": (st, [P, st, st, P, P, P]),
+        "paco_plan_describe": (st, [P, ctypes.POINTER(i32), ctypes.c_char_p, sz]),
+        "paco_plan_destroy": (st, [P]),
+        "paco_status_string": (ctypes.c_char_p, [st]),
+        "paco_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def lib() -> ctypes.CDLL:
+    return _lib
+
+
+def paco_status_string(status: int) -> str:
+    return _lib.paco_status_string(status).decode()
+
+
+def paco_last_error() -> str:
+    return _lib.paco_last_error().decode()
+
+
+def _check(status: int, where: str):
+    if status != PACO_OK:
+        raise PacoError(status, where, f"{paco_status_string(status)}: {paco_last_error()}")
+
+
+def paco_plan_validate(N1: int, N2: int, p: int, b: int, dt: int = PACO_C64) -> int:
+    """Returns the status code (no exception): pure host check, no GPU needed."""
+    return int(_lib.paco_plan_validate(N1, N2, p, b, dt))
+
+
+def paco_plan_create(N1: int, N2: int, p: int, b: int, dt: int = PACO_C64) -> int:
+    h = ctypes.c_void_p()
+    _check(_lib.paco_plan_create(ctypes.byref(h), N1, N2, p, b, dt), "paco_plan_create")
+    return h.value
+
+
+def paco_plan_workspace_size(plan: int) -> int:
+    n = ctypes.c_size_t()
+    _check(_lib.paco_plan_workspace_size(plan, ctypes.byref(n)), "paco_plan_workspace_size")
+    return n.value
+
+
+def paco_execute(plan: int, src: int, dst: int, workspace: int, workspace_bytes: int, stream: int = 0):
+    _check(_lib.paco_execute(plan, src, dst, workspace, workspace_bytes, stream), "paco_execute")
+
+
+def paco_execute_stage(plan: int, stage: int, flags: int, src: int, dst: int, stream: int = 0):
+    _check(_lib.paco_execute_stage(plan, stage, flags, src, dst, stream), "paco_execute_stage")
+
+
+def paco_plan_describe(plan: int):
+    n = ctypes.c_int32()
+    buf = ctypes.create_string_buffer(1024)
+    _check(_lib.paco_plan_describe(plan, ctypes.byref(n), buf, 1024), "paco_plan_describe")
+    return n.value, buf.value.decode()
+
+
+def paco_plan_destroy(plan: int):
+    _check(_lib.paco_plan_destroy(plan), "paco_plan_destroy")
+
+
+class Plan:
+    """Owns one paco_plan handle (created on the current HIP device)."""
+
+    def __init__(self, N1: int, N2: int, p: int, b: int, dt: int = PACO_C64):
+        self.N1, self.N2, self.p, self.b, self.dt = N1, N2, p, b, dt
+        self.handle = paco_plan_create(N1, N2, p, b, dt)
+        self.workspace_bytes = paco_plan_workspace_size(self.handle)
+        self.launches, self.description = paco_plan_describe(self.handle)
+
+    def execute(self, src: int, dst: int, workspace: int, stream: int = 0):
+        paco_execute(self.handle, src, dst, workspace, self.workspace_bytes, stream)
+
+    def execute_stage(self, stage: int, src: int, dst: int, stream: int = 0, flags: int = 0):
+        paco_execute_stage(self.handle, stage, flags, src, dst, stream)
+
+    def close(self):
+        if self.handle:
+            paco_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

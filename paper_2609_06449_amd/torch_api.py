@@ -1,0 +1,53 @@
+"""torch-tensor convenience over the C ABI: allocation and stream plumbing only."""
+from __future__ import annotations
+
+import torch
+
+from . import paco
+
+_plans = {}
+
+
+def get_plan(N1: int, N2: int, p: int, b: int, dt: int = paco.PACO_C64) -> paco.Plan:
+    key = (torch.cuda.current_device(), N1, N2, p, b, dt)
+    plan = _plans.get(key)
+    if plan is None:
+        plan = _plans[key] = paco.Plan(N1, N2, p, b, dt)
+    return plan
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _check_tensor(x: torch.Tensor, n: int, name: str):
+    if not x.is_cuda or x.dtype != torch.complex64 or not x.is_contiguous() or x.numel() != n:
+        raise ValueError(f"{name} must be a contiguous complex64 CUDA tensor of {n} items")
+
+
+def fft(x: torch.Tensor, N1: int, N2: int, p: int, b: int, out: torch.Tensor | None = None,
+        workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """y = Omega_N x for x of N = N1*N2 items (viewed N1 x N2); returns y
+    (the N2 x N1 factor-swapped view, flattened, is y in natural order)."""
+    N = N1 * N2
+    _check_tensor(x, N, "x")
+    plan = get_plan(N1, N2, p, b)
+    if out is None:
+        out = torch.empty(N, dtype=torch.complex64, device=x.device)
+    _check_tensor(out, N, "out")
+    if workspace is None:
+        workspace = torch.empty(N, dtype=torch.complex64, device=x.device)
+    plan.execute(x.data_ptr(), out.data_ptr(), workspace.data_ptr(), _stream())
+    return out
+
+
+def stage(x: torch.Tensor, N1: int, N2: int, p: int, b: int, stage: int, flags: int = 0,
+          out: torch.Tensor | None = None) -> torch.Tensor:
+    """One phase alone (paco_execute_stage)."""
+    N = N1 * N2
+    _check_tensor(x, N, "x")
+    plan = get_plan(N1, N2, p, b)
+    if out is None:
+        out = torch.empty(N, dtype=torch.complex64, device=x.device)
+    plan.execute_stage(stage, x.data_ptr(), out.data_ptr(), _stream(), flags)
+    return out

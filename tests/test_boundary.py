@@ -1,0 +1,88 @@
+"""The C-ABI boundary without a GPU: the library loads, exports every symbol
+include/paco.h declares, and rejects every contract violation of the
+problem statement (paper, section 2 and eq. exact-divisibility) on the host,
+before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2609_06449_amd import paco
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "paco.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(paco_\w+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert _declared_symbols() == sorted(paco.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(paco._LIB_PATH)
+    for name in _declared_symbols():
+        assert hasattr(lib, name), name
+
+
+@pytest.mark.parametrize("N1,N2,p,b", [
+    (64, 64, 4, 4), (4096, 4096, 64, 16), (4, 4, 2, 2), (1 << 14, 1 << 14, 256, 4),
+    (1 << 13, 1 << 15, 128, 2), (4096, 1 << 14, 64, 4), (16, 16, 16, 16), (1 << 16, 1 << 16, 2, 16),
+])
+def test_validate_accepts_contract(N1, N2, p, b):
+    assert paco.paco_plan_validate(N1, N2, p, b) == paco.PACO_OK
+
+
+@pytest.mark.parametrize("N1,N2,p,b,status", [
+    (64, 64, 4, 3, paco.PACO_ERR_NOT_POWER_OF_B),      # b not a power of two
+    (64, 64, 4, 1, paco.PACO_ERR_NOT_POWER_OF_B),      # b < 2
+    (64, 64, 4, 0, paco.PACO_ERR_NOT_POWER_OF_B),
+    (64, 32, 4, 4, paco.PACO_ERR_NOT_POWER_OF_B),      # 32 is not a power of 4
+    (1 << 14, 1 << 14, 256, 16, paco.PACO_ERR_NOT_POWER_OF_B),  # 2^14 not a power of 16
+    (1 << 13, 1 << 15, 128, 8, paco.PACO_ERR_NOT_POWER_OF_B),   # 2^13 not a power of 8 (2^15 is)
+    (48, 64, 4, 4, paco.PACO_ERR_NOT_POWER_OF_B),      # not a power of two at all
+    (1, 64, 2, 4, paco.PACO_ERR_NOT_POWER_OF_B),       # m1 = 0
+    (64, 64, 1, 4, paco.PACO_ERR_DIVISIBILITY),        # p = 1
+    (64, 64, 0, 4, paco.PACO_ERR_DIVISIBILITY),
+    (64, 64, -4, 4, paco.PACO_ERR_DIVISIBILITY),
+    (64, 64, 3, 4, paco.PACO_ERR_DIVISIBILITY),        # p does not divide
+    (64, 16, 32, 4, paco.PACO_ERR_DIVISIBILITY),       # p | N1 but not N2
+    (1 << 18, 4, 2, 2, paco.PACO_ERR_UNSUPPORTED),     # N1 above 2^16
+    (1 << 20, 1 << 20, 2, 16, paco.PACO_ERR_UNSUPPORTED),
+])
+def test_validate_rejects(N1, N2, p, b, status):
+    assert paco.paco_plan_validate(N1, N2, p, b) == status
+    assert paco.paco_last_error()
+
+
+def test_validate_rejects_unknown_dtype():
+    assert paco.paco_plan_validate(64, 64, 4, 4, 99) == paco.PACO_ERR_INVALID_ARG
+
+
+def test_plan_create_rejects_before_touching_the_device():
+    with pytest.raises(paco.PacoError) as e:
+        paco.paco_plan_create(64, 64, 3, 4)
+    assert e.value.status == paco.PACO_ERR_DIVISIBILITY
+    lib = paco.lib()
+    assert lib.paco_plan_create(None, 64, 64, 4, 4, 0) == paco.PACO_ERR_INVALID_ARG
+
+
+def test_null_plan_and_pointer_errors():
+    lib = paco.lib()
+    sz = ctypes.c_size_t(123)
+    assert lib.paco_plan_workspace_size(None, ctypes.byref(sz)) == paco.PACO_ERR_INVALID_ARG
+    assert sz.value == 0
+    assert lib.paco_execute(None, 8, 8, 8, 1 << 20, None) == paco.PACO_ERR_INVALID_ARG
+    assert lib.paco_execute_stage(None, 1, 0, 8, 8, None) == paco.PACO_ERR_INVALID_ARG
+    assert lib.paco_plan_describe(None, None, None, 0) == paco.PACO_ERR_INVALID_ARG
+    assert lib.paco_plan_destroy(None) == paco.PACO_OK
+
+
+def test_status_strings():
+    for st in range(8):
+        assert paco.paco_status_string(st)
+    assert paco.paco_status_string(0) == "ok"

@@ -1,0 +1,246 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerance: rel-L2 <= 1e-6 against the FP64 oracle for the complex64 FP32 path
+at every size up to 2^24 (the stated accuracy target); the bare permutation is
+compared bit for bit.  Inputs are seeded complex64 values; the oracle sees
+the same values promoted to complex128, so only transform error is measured.
+
+Sizes follow the contract N1 = b^m1, N2 = b^m2, so there is no ragged tail in
+the usual sense; the edge cases are the smallest transforms (2 x 2), extreme
+aspect ratios, fewer columns than a workgroup's tile, single-stage
+(n <= 16) kernels, mixed-radix stage plans and the two-pass local FFTs
+(N1 or N2 above 2^12).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2609_06449_amd import inputs, paco
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-6
+
+
+def _dev(x: np.ndarray):
+    return torch.from_numpy(np.ascontiguousarray(x.astype(np.complex64).ravel())).to("cuda")
+
+
+def _host(t) -> np.ndarray:
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _run(plan, x_dev):
+    N = plan.N1 * plan.N2
+    out = torch.empty(N, dtype=torch.complex64, device="cuda")
+    ws = torch.empty(N, dtype=torch.complex64, device="cuda")
+    plan.execute(x_dev.data_ptr(), out.data_ptr(), ws.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    return out
+
+
+def _stage(plan, stage, x_dev, flags=0, out=None):
+    N = plan.N1 * plan.N2
+    if out is None:
+        out = torch.empty(N, dtype=torch.complex64, device="cuda")
+    plan.execute_stage(stage, x_dev.data_ptr(), out.data_ptr(), torch.cuda.current_stream().cuda_stream, flags)
+    return out
+
+
+def test_single_hip_runtime_loaded():
+    # torch's bundled HIP runtime and the library must be the same copy
+    torch.zeros(1, device="cuda")
+    paco.paco_plan_destroy(paco.paco_plan_create(16, 16, 2, 4))
+    maps = open("/proc/self/maps").read().splitlines()
+    hip = {ln.split()[-1] for ln in maps if "libamdhip64" in ln}
+    assert len(hip) == 1, hip
+    assert any(ln.split()[-1].endswith("libpaco.so") for ln in maps)
+
+
+END_TO_END = [
+    # (N1, N2, p, b)
+    (2, 2, 2, 2), (4, 4, 2, 2), (2, 64, 2, 2), (64, 2, 2, 2), (16, 16, 2, 4), (64, 64, 4, 4),
+    (8, 8, 2, 8), (32, 128, 4, 2), (256, 16, 4, 16), (16, 256, 4, 16), (512, 512, 8, 8),
+    (4096, 16, 16, 16), (16, 4096, 16, 16), (1024, 2048, 8, 2), (4096, 256, 64, 16),
+    (8192, 16, 2, 2), (16, 8192, 2, 2), (1 << 14, 64, 4, 4), (64, 1 << 14, 4, 4),
+    (1 << 16, 16, 16, 16), (16, 1 << 16, 16, 16), (1 << 15, 32, 32, 2),
+]
+
+
+@pytest.mark.parametrize("N1,N2,p,b", END_TO_END)
+def test_end_to_end_matches_oracle(N1, N2, p, b):
+    N = N1 * N2
+    x = inputs.normal(N, seed=N1 * 7 + N2)
+    plan = paco.Plan(N1, N2, p, b)
+    y = _host(_run(plan, _dev(x)))
+    ref = oracle.dft(x.astype(np.complex128))
+    err = oracle.rel_l2(y, ref)
+    print(f"N1={N1} N2={N2} p={p} b={b} rel_l2={err:.3e}", flush=True)
+    assert err <= TOL
+
+
+def test_c1_config_and_stages():
+    # N = 2^12 viewed 64 x 64, p = 4 slabs, b = 4, uniform[-1,1] inputs, seed 1
+    N1, N2, p, b = 64, 64, 4, 4
+    x = inputs.uniform(N1 * N2, seed=1)
+    plan = paco.Plan(N1, N2, p, b)
+    xd = _dev(x)
+    y = _host(_run(plan, xd))
+    assert oracle.rel_l2(y, oracle.dft(x)) <= TOL
+    # stage by stage against the stage references, each fed the same seeded input
+    s1 = _host(_stage(plan, 1, xd)).reshape(N1, N2)
+    assert oracle.rel_l2(s1, oracle.phase1(x, N1, N2, b)) <= TOL
+    s2 = _host(_stage(plan, 2, xd)).reshape(N2, N1)
+    assert oracle.rel_l2(s2, oracle.phase2(x, N1, N2, b)) <= TOL
+    s3 = _host(_stage(plan, 3, xd)).reshape(N2, N1)
+    assert oracle.rel_l2(s3, oracle.phase3(x, N1, N2, b)) <= TOL
+
+
+@pytest.mark.parametrize("N1,N2,p,b", [(4, 4, 2, 2), (64, 64, 4, 4), (4096, 4096, 64, 16), (16, 256, 4, 16),
+                                       (1 << 14, 64, 4, 4), (8, 1 << 13, 2, 2)])
+def test_permutation_bit_exact(N1, N2, p, b):
+    # stage 2 without the twiddle is a pure permutation of complex64 items
+    N = N1 * N2
+    x = inputs.normal(N, seed=11)
+    plan = paco.Plan(N1, N2, p, b)
+    got = _host(_stage(plan, 2, _dev(x), flags=paco.PACO_NO_TWIDDLE))
+    want = oracle.phase2(x, N1, N2, b, twiddle=False).astype(np.complex64).ravel()
+    assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+
+
+@pytest.mark.parametrize("N1,N2,p,b", [(64, 64, 4, 4), (256, 4096, 16, 16), (1 << 14, 16, 16, 4)])
+def test_middle_twiddle_elementwise(N1, N2, p, b):
+    N = N1 * N2
+    x = inputs.normal(N, seed=12)
+    plan = paco.Plan(N1, N2, p, b)
+    got = _host(_stage(plan, 2, _dev(x))).astype(np.complex128)
+    want = oracle.phase2(x, N1, N2, b, twiddle=True).ravel()
+    rel = np.abs(got - want) / np.maximum(np.abs(want), 1e-30)
+    assert np.max(rel) < 1e-6          # a few FP32 ulps per item
+    assert oracle.rel_l2(got, want) < 3e-7
+
+
+@pytest.mark.parametrize("N1,N2,p,b", [(4096, 256, 4, 16), (256, 4096, 4, 16), (1 << 14, 32, 2, 2),
+                                       (32, 1 << 14, 2, 2), (1 << 16, 16, 16, 16)])
+def test_stage_wise_local_ffts(N1, N2, p, b):
+    N = N1 * N2
+    x = inputs.normal(N, seed=13)
+    plan = paco.Plan(N1, N2, p, b)
+    xd = _dev(x)
+    s1 = _host(_stage(plan, 1, xd)).reshape(N1, N2)
+    assert oracle.rel_l2(s1, oracle.phase1(x, N1, N2, b)) <= TOL
+    s3 = _host(_stage(plan, 3, xd)).reshape(N2, N1)
+    assert oracle.rel_l2(s3, oracle.phase3(x, N1, N2, b)) <= TOL
+    # in place
+    buf = _dev(x)
+    _stage(plan, 3, buf, out=buf)
+    assert np.array_equal(_host(buf), _host(_stage(plan, 3, xd)))
+    buf = _dev(x)
+    _stage(plan, 1, buf, out=buf)
+    assert np.array_equal(_host(buf), _host(_stage(plan, 1, xd)))
+
+
+def test_output_independent_of_p():
+    # p does not enter the permutation or the per-column arithmetic
+    N1, N2, b = 256, 256, 4
+    x = _dev(inputs.normal(N1 * N2, seed=14))
+    outs = [_host(_run(paco.Plan(N1, N2, p, b), x)) for p in (2, 4, 16, 64, 256)]
+    for o in outs[1:]:
+        assert np.array_equal(o.view(np.uint64), outs[0].view(np.uint64))
+
+
+def test_in_place_execute():
+    N1, N2, p, b = 256, 512, 4, 2
+    x = inputs.normal(N1 * N2, seed=15)
+    plan = paco.Plan(N1, N2, p, b)
+    buf = _dev(x)
+    ws = torch.empty_like(buf)
+    plan.execute(buf.data_ptr(), buf.data_ptr(), ws.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    assert oracle.rel_l2(_host(buf), oracle.dft(x)) <= TOL
+
+
+def test_deterministic_repeat():
+    N1, N2, p, b = 4096, 1024, 16, 4
+    x = _dev(inputs.normal(N1 * N2, seed=16))
+    plan = paco.Plan(N1, N2, p, b)
+    a = _host(_run(plan, x))
+    c = _host(_run(plan, x))
+    assert np.array_equal(a.view(np.uint64), c.view(np.uint64))
+
+
+def test_execute_argument_errors_on_device():
+    plan = paco.Plan(64, 64, 4, 4)
+    buf = torch.empty(4096, dtype=torch.complex64, device="cuda")
+    ws = torch.empty(4096, dtype=torch.complex64, device="cuda")
+    lib = paco.lib()
+    s = torch.cuda.current_stream().cuda_stream
+    assert lib.paco_execute(plan.handle, buf.data_ptr(), buf.data_ptr(), ws.data_ptr(), 100, s) == paco.PACO_ERR_WORKSPACE
+    assert lib.paco_execute(plan.handle, buf.data_ptr() + 4, buf.data_ptr(), ws.data_ptr(), 1 << 20, s) == paco.PACO_ERR_INVALID_ARG
+    assert lib.paco_execute(plan.handle, buf.data_ptr(), buf.data_ptr(), buf.data_ptr(), 1 << 20, s) == paco.PACO_ERR_INVALID_ARG
+    assert lib.paco_execute_stage(plan.handle, 4, 0, buf.data_ptr(), ws.data_ptr(), s) == paco.PACO_ERR_INVALID_ARG
+    assert lib.paco_execute_stage(plan.handle, 2, 0, buf.data_ptr(), buf.data_ptr(), s) == paco.PACO_ERR_INVALID_ARG
+    assert lib.paco_execute_stage(plan.handle, 2, 8, buf.data_ptr(), ws.data_ptr(), s) == paco.PACO_ERR_INVALID_ARG
+
+
+# ---------------------------------------------------------------------------
+# full-size configurations
+# ---------------------------------------------------------------------------
+
+def test_c2_full_size_against_oracle():
+    # N = 2^24 as 4096 x 4096, p = 64, b = 16, N(0,1) inputs, seed 2: the
+    # complete output against the FP64 radix-2 oracle
+    N1, N2, p, b = 4096, 4096, 64, 16
+    N = N1 * N2
+    x = inputs.normal(N, seed=2)
+    plan = paco.Plan(N1, N2, p, b)
+    xd = _dev(x)
+    y = _host(_run(plan, xd))
+    ref = oracle.fft_radix2(x)
+    err = oracle.rel_l2(y, ref)
+    print(f"c2 rel_l2={err:.3e}", flush=True)
+    assert err <= TOL
+    # sampled single outputs by the O(N) definition, per-item bound
+    ks = np.array([0, 1, 4095, 4096, N // 2, N - 1, 12345678, 9876543])
+    yk = oracle.dft_at(x, ks)
+    rms = np.sqrt(np.mean(np.abs(ref) ** 2))
+    assert np.max(np.abs(y[ks] - yk)) < 1e-5 * rms
+    # stage-wise on sampled columns
+    s1 = _host(_stage(plan, 1, xd)).reshape(N1, N2)
+    cols = np.array([0, 1, 63, 64, 2047, 4095])
+    assert oracle.rel_l2(s1[:, cols], oracle.phase1(x, N1, N2, b, cols=cols)) <= TOL
+    s3 = _host(_stage(plan, 3, xd)).reshape(N2, N1)
+    assert oracle.rel_l2(s3[:, cols], oracle.phase3(x, N1, N2, b, cols=cols)) <= TOL
+
+
+def _round_trip_error(plan, xd):
+    # F(conj(F x)) = N conj(x): holds at any size without a reference output
+    N = plan.N1 * plan.N2
+    y = _run(plan, xd)
+    z = _run(plan, torch.conj(y).resolve_conj().contiguous())
+    back = torch.conj(z).resolve_conj() / N
+    num = torch.linalg.vector_norm((back - xd).to(torch.complex128))
+    den = torch.linalg.vector_norm(xd.to(torch.complex128))
+    return float(num / den), y
+
+
+@pytest.mark.parametrize("name", ["c3s", "c3n"])
+def test_c3_full_size_sampled(name):
+    cfg = inputs.CONFIGS[name]
+    N1, N2, p, b = cfg["N1"], cfg["N2"], cfg["p"], cfg["b"]
+    N = N1 * N2
+    x = inputs.make(cfg["gen"], N, cfg["seed"])
+    plan = paco.Plan(N1, N2, p, b)
+    xd = _dev(x)
+    rt, yd = _round_trip_error(plan, xd)
+    print(f"{name} round-trip rel_l2={rt:.3e}", flush=True)
+    assert rt <= 2 * TOL
+    y = _host(yd)
+    # Parseval in FP64 on the host
+    ex = float(np.sum(np.abs(x.astype(np.complex128)) ** 2))
+    ey = float(np.sum(np.abs(y.astype(np.complex128)) ** 2))
+    assert abs(ey - N * ex) <= 2e-6 * N * ex
+    ks = np.array([0, 1, N1 - 1, N1, N // 2 + 3, N - 1])
+    yk = oracle.dft_at(x, ks)
+    rms_y = np.sqrt(ex)            # mean |y|^2 = ||x||^2 by Parseval
+    assert np.max(np.abs(y[ks] - yk)) < 1e-5 * rms_y
