@@ -73,7 +73,8 @@ typedef struct paco_plan_s paco_plan;
  * not be a power of b; the balance argument of section 4.2 uses only the
  * divisibility).  Pure host code: no HIP call, usable without a GPU.
  * Returns PACO_ERR_UNSUPPORTED for sizes this build has no kernels for
- * (N1 or N2 above 2^16, or N1*N2 above 2^30). */
+ * (N1 or N2 above 2^16, or N1*N2 above 2^28: every buffer stays below
+ * 4 GiB, so the kernels address it with 32-bit byte offsets). */
 paco_status paco_plan_validate(int64_t N1, int64_t N2, int64_t p, int32_t b, paco_dtype dt);
 
 /* Validates, builds the pass plan and uploads the plan's tables to the

@@ -1,18 +1,28 @@
 // LocalFFT passes (paper, section 4.1 and appendix A) for gfx950.
 //
-// One workgroup transforms T contiguous columns of an n-row tile (n <= 4096)
+// A workgroup transforms T contiguous columns of an n-row tile (n <= 4096)
 // entirely on chip.  The transform is a radix-16 Stockham sequence (one
 // radix-2/4/8 stage when log2 n is not a multiple of 4): every thread holds
 // E = min(16, n) items in registers; the first stage reads its operands
 // straight from HBM rows, the last stage writes its results straight to HBM
 // rows, and only the exchanges between stages go through LDS.
 //
-// The arithmetic order inside a workgroup is free (paper, Lemma 1 holds for
-// any digit-aligned split); what the paper fixes is the layout at the HBM
+// The arithmetic order inside a workgroup is free (Lemma 1 of the paper holds
+// for any digit-aligned split); what the paper fixes is the layout at the HBM
 // boundary, which the pass descriptor states: Phase I writes the item of
-// logical frequency k to row pi(k) (output layout P_pi Omega), Phase III
-// reads logical input j from row pi(j) (input layout Omega P_pi).  Rows are
+// logical frequency k to row pi(k) (output layout P_pi Omega), Phase III reads
+// logical input j from row pi(j) (input layout Omega P_pi).  Rows are
 // contiguous runs of T items, so a digit-reversed row order costs nothing.
+//
+// Two launch shapes.  Short transforms: one tile per workgroup of up to 1024
+// threads with 16 items each.  Long transforms (n >= 2^9): persistent
+// workgroups of 512 threads with 32 items each (two waves per SIMD, 256
+// VGPRs of budget) that walk a sequence of tiles and load the next tile's
+// first-stage operands into registers before computing the current one, so
+// the HBM traffic of neighbouring tiles overlaps the arithmetic and LDS
+// exchanges of the current one.  Stage twiddles come from small factor
+// tables copied to LDS once per workgroup (broadcast or contiguous reads);
+// row digit reversals are computed with bit operations.
 #include "paco_internal.h"
 
 namespace paco {
@@ -85,69 +95,58 @@ __device__ __forceinline__ void dft_regs(float2 *v)
     for (int k = 0; k < R; ++k) v[k] = t[k];
 }
 
-template <int LOG2N>
-struct StagePlan {
-    static constexpr int nfull = LOG2N / 4;
-    static constexpr int rem = LOG2N % 4;
-    static constexpr int count = nfull + (rem ? 1 : 0);
-    static constexpr int log2radix(int s) { return s < nfull ? 4 : rem; }
-    static constexpr int log2ns(int s)
-    {
-        int a = 0;
-        for (int i = 0; i < s; ++i) a += log2radix(i);
-        return a;
-    }
-    static constexpr int E = LOG2N < 4 ? (1 << LOG2N) : 16;
-};
-
-// LDS index with one pad item per 32 (spreads strided stage writes over banks).
-__device__ __forceinline__ int lpad(int e) { return e + (e >> 5); }
+// LDS index with 4 pad items per 64: the radix-16 first-stage writes (row
+// stride 16*T items) land on distinct banks.
+__device__ __forceinline__ int lpad(int e) { return e + ((e >> 6) << 2); }
 
 struct Ctx {
     float2 *lds;
-    const float2 *tw;
-    int tid, nt, log2T, log2L;
-    float2 *dst;
-    int64_t ld, orow_out, k_out;
-    const int32_t *perm_out;
+    const float2 *twl;
+    int tid, nt, log2T;
+    char *dst;                 // tile base (column col0 of row 0)
+    uint32_t ld8;              // row length in bytes
+    uint32_t orow_out, k_out;  // output row = orow_out + pi_out(k) * k_out
+    int out_t, out_ell;
 };
 
-template <int LOG2N, int S>
-__device__ __forceinline__ void run_stage(float2 (&v)[StagePlan<LOG2N>::E], const Ctx &c)
+// Stage S of the Stockham sequence.  v[i*R + r] is operand r of butterfly i;
+// butterfly id g = tid + i*nt covers column g mod T and index j = g / T.
+template <int LOG2N, int S, bool GEN, int EG>
+__device__ __forceinline__ void run_stage(float2 (&v)[EG], const Ctx &c)
 {
-    using SP = StagePlan<LOG2N>;
-    constexpr int E = SP::E;
-    constexpr int LR = SP::log2radix(S);
+    constexpr int LR = stage_log2radix(LOG2N, S);
     constexpr int R = 1 << LR;
-    constexpr int LNS = SP::log2ns(S);
-    constexpr int NB = E / R;
-    constexpr int LNR = LOG2N - LR;
-    constexpr bool last = (S + 1 == SP::count);
+    constexpr int LNS = stage_log2ns(LOG2N, S);
+    constexpr int NB = EG / R;
+    constexpr bool last = (S + 1 == stage_count(LOG2N));
     const int Tm = (1 << c.log2T) - 1;
 
-    if constexpr (S > 0) {
-#pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            const int g = c.tid + i * c.nt;
-            const int t = g & Tm, j = g >> c.log2T;
-#pragma unroll
-            for (int r = 0; r < R; ++r) v[i * R + r] = c.lds[lpad(((j + (r << LNR)) << c.log2T) + t)];
-        }
-    }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
         const int g = c.tid + i * c.nt;
         const int j = g >> c.log2T;
+        float2 *u = &v[i * R];
         if constexpr (LNS > 0) {
+            constexpr int LOW = stage_lo_width(LOG2N, S);
+            constexpr int HIW = stage_hi_width(LOG2N, S);
+            constexpr int OFF = stage_tw_offset(LOG2N, S);
             const int k = j & ((1 << LNS) - 1);
-            const int sh = c.log2L - (LNS + LR);
+            const int kl = k & (LOW - 1), kh = k >> 4;
 #pragma unroll
-            for (int r = 1; r < R; ++r) v[i * R + r] = cmul(v[i * R + r], c.tw[(k * r) << sh]);
+            for (int r = 1; r < R; ++r) {
+                float2 w = c.twl[OFF + (r - 1) * LOW + kl];
+                if constexpr (HIW > 0) w = cmul(w, c.twl[OFF + (R - 1) * LOW + (r - 1) * HIW + kh]);
+                u[r] = cmul(u[r], w);
+            }
         }
-        dft_regs<LR>(&v[i * R]);
+        dft_regs<LR>(u);
     }
     if constexpr (!last) {
-        if constexpr (S > 0) __syncthreads();  // all stage-S operands read before overwriting
+        constexpr int LR2 = stage_log2radix(LOG2N, S + 1);
+        constexpr int R2 = 1 << LR2;
+        constexpr int NB2 = EG / R2;
+        constexpr int LNR2 = LOG2N - LR2;
+        if constexpr (S > 0) __syncthreads();  // all stage-S operands were read
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             const int g = c.tid + i * c.nt;
@@ -157,7 +156,14 @@ __device__ __forceinline__ void run_stage(float2 (&v)[StagePlan<LOG2N>::E], cons
             for (int r = 0; r < R; ++r) c.lds[lpad(((idxD + (r << LNS)) << c.log2T) + t)] = v[i * R + r];
         }
         __syncthreads();
-        run_stage<LOG2N, S + 1>(v, c);
+#pragma unroll
+        for (int i = 0; i < NB2; ++i) {
+            const int g = c.tid + i * c.nt;
+            const int t = g & Tm, j = g >> c.log2T;
+#pragma unroll
+            for (int r = 0; r < R2; ++r) v[i * R2 + r] = c.lds[lpad(((j + (r << LNR2)) << c.log2T) + t)];
+        }
+        run_stage<LOG2N, S + 1, GEN, EG>(v, c);
     } else {
         // last stage: j < n/R = 2^LNS, outputs are the natural-order rows k = j + r*2^LNS
 #pragma unroll
@@ -166,110 +172,220 @@ __device__ __forceinline__ void run_stage(float2 (&v)[StagePlan<LOG2N>::E], cons
             const int t = g & Tm, j = g >> c.log2T;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const int k = j + (r << LNS);
-                const int64_t m = c.perm_out ? (int64_t)c.perm_out[k] : (int64_t)k;
-                c.dst[(c.orow_out + m * c.k_out) * c.ld + t] = v[i * R + r];
+                const uint32_t k = j + (r << LNS);
+                const uint32_t m = uint32_t(digrev<GEN>(k, c.out_t, c.out_ell));
+                const uint32_t off = (c.orow_out + m * c.k_out) * c.ld8 + uint32_t(t) * 8u;
+                *reinterpret_cast<float2 *>(c.dst + off) = v[i * R + r];
             }
         }
     }
 }
 
-// Workgroup order: the hardware deals consecutive workgroup ids to the 8 XCDs
-// in turn; renumber so that the groups one XCD receives back to back own
-// neighbouring column tiles and share that XCD's L2 lines.
-__device__ __forceinline__ int64_t xcd_order(int64_t i, int64_t G)
+// Tile order: the hardware deals consecutive workgroup ids to the 8 XCDs in
+// turn, and a workgroup stays on its XCD.  Renumber so that the tiles one
+// XCD works on at the same time are neighbouring column tiles, which share
+// 128-byte lines in that XCD's L2.  i runs over rounds of `grid` tiles.
+__device__ __forceinline__ int64_t tile_order(int64_t i, int64_t G, int64_t grid)
 {
-    if (G & 7) return i;
-    return (i & 7) * (G >> 3) + (i >> 3);
+    const int64_t s = i / grid, b = i - s * grid;
+    if ((grid & 7) || (s + 1) * grid > G) return i;
+    return s * grid + (b & 7) * (grid >> 3) + (b >> 3);
 }
 
-template <int LOG2N>
-__global__ __launch_bounds__(1024) void local_fft_kernel(LocalPass P)
+// First-stage operands of one tile: rows o*o_in + pi_in(jj)*j_in, jj = j +
+// r*2^LNR0, column col0 + t.  Byte offsets are 32-bit (buffers < 4 GiB).
+template <int LOG2N, bool GEN, int EG>
+__device__ __forceinline__ void load_tile(const LocalPass &P, const char *src, uint32_t orow, int tid, int nt,
+                                          int log2T, float2 (&v)[EG])
 {
-    using SP = StagePlan<LOG2N>;
-    constexpr int E = SP::E;
-    constexpr int LR0 = SP::log2radix(0);
+    constexpr int LR0 = stage_log2radix(LOG2N, 0);
     constexpr int R0 = 1 << LR0;
-    constexpr int NB0 = E / R0;
+    constexpr int NB0 = EG / R0;
     constexpr int LNR0 = LOG2N - LR0;
-    extern __shared__ float2 lds[];
-
-    const int log2T = P.log2T;
     const int Tm = (1 << log2T) - 1;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int64_t ntiles = P.ncols >> log2T;
-    const int64_t wg = xcd_order(blockIdx.x, gridDim.x);
-    const int64_t o = wg / ntiles;
-    const int64_t col0 = (wg - o * ntiles) << log2T;
-    const float2 *__restrict__ src = P.src + col0;
-
-    float2 v[E];
-    const int64_t orow_in = o * P.o_in;
-    int64_t f = 0;
-    if (P.pre_tw) f = P.tw_perm ? (int64_t)P.tw_perm[o] : o;
-    const int64_t Mm = (int64_t(1) << P.log2M) - 1;
-    const int shM = P.log2L - P.log2M;
+    const uint32_t ld8 = uint32_t(P.ld) * 8u, j_in = uint32_t(P.j_in);
 #pragma unroll
-    for (int i = 0; i < NB0; ++i) {
-        const int g = tid + i * nt;
+    for (int q = 0; q < NB0; ++q) {
+        const int g = tid + q * nt;
         const int t = g & Tm, j = g >> log2T;
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
-            const int jj = j + (r << LNR0);
-            const int64_t m = P.perm_in ? (int64_t)P.perm_in[jj] : (int64_t)jj;
-            v[i * R0 + r] = src[(orow_in + m * P.j_in) * P.ld + t];
+            const uint32_t jj = j + (r << LNR0);
+            const uint32_t m = uint32_t(digrev<GEN>(jj, P.in_t, P.in_ell));
+            v[q * R0 + r] = *reinterpret_cast<const float2 *>(src + ((orow + m * j_in) * ld8 + uint32_t(t) * 8u));
         }
     }
-    if (P.pre_tw) {
+}
+
+template <int LOG2N, bool GEN, int EG>
+__device__ __forceinline__ void pre_twiddle(const LocalPass &P, int64_t o, int tid, int nt, int log2T,
+                                            float2 (&v)[EG])
+{
+    constexpr int LR0 = stage_log2radix(LOG2N, 0);
+    constexpr int R0 = 1 << LR0;
+    constexpr int NB0 = EG / R0;
+    constexpr int LNR0 = LOG2N - LR0;
+    const int64_t f = digrev<GEN>(o, P.tw_t, P.tw_ell);
+    const int64_t Mm = (int64_t(1) << P.log2M) - 1;
+    const int shM = P.log2L - P.log2M;
 #pragma unroll
-        for (int i = 0; i < NB0; ++i) {
-            const int g = tid + i * nt;
-            const int j = g >> log2T;
+    for (int q = 0; q < NB0; ++q) {
+        const int j = (tid + q * nt) >> log2T;
 #pragma unroll
-            for (int r = 0; r < R0; ++r) {
-                const int64_t jj = j + (r << LNR0);
-                v[i * R0 + r] = cmul(v[i * R0 + r], P.tw[((f * jj) & Mm) << shM]);
-            }
-        }
+        for (int r = 0; r < R0; ++r) v[q * R0 + r] = cmul(v[q * R0 + r], P.tw[((f * (j + (r << LNR0))) & Mm) << shM]);
     }
+}
+
+// One tile per workgroup.
+template <int LOG2N, bool PRE, bool GEN, int EG>
+__global__ __launch_bounds__(1024) void local_fft_kernel(LocalPass P)
+{
+    constexpr int TWN = stage_tw_total(LOG2N);
+    extern __shared__ float2 smem[];
+    const int log2T = P.log2T;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    float2 *twl = smem;
+    float2 *lds = smem + ((TWN + 63) & ~63);
+    for (int e = tid; e < TWN; e += nt) twl[e] = P.stw[e];  // first read after a barrier
+
+    const int64_t ntc = P.ncols >> log2T;
+    const int64_t tile = tile_order(blockIdx.x, gridDim.x, gridDim.x);
+    const int64_t o = tile / ntc;
+    const int64_t col0 = (tile - o * ntc) << log2T;
+
+    float2 v[EG];
+    load_tile<LOG2N, GEN, EG>(P, reinterpret_cast<const char *>(P.src + col0), uint32_t(o * P.o_in), tid, nt,
+                              log2T, v);
+    if constexpr (PRE) pre_twiddle<LOG2N, GEN, EG>(P, o, tid, nt, log2T, v);
     Ctx c;
     c.lds = lds;
-    c.tw = P.tw;
+    c.twl = twl;
     c.tid = tid;
     c.nt = nt;
     c.log2T = log2T;
-    c.log2L = P.log2L;
-    c.dst = P.dst + col0;
-    c.ld = P.ld;
-    c.orow_out = o * P.o_out;
-    c.k_out = P.k_out;
-    c.perm_out = P.perm_out;
-    run_stage<LOG2N, 0>(v, c);
+    c.dst = reinterpret_cast<char *>(P.dst + col0);
+    c.ld8 = uint32_t(P.ld) * 8u;
+    c.orow_out = uint32_t(o * P.o_out);
+    c.k_out = uint32_t(P.k_out);
+    c.out_t = P.out_t;
+    c.out_ell = P.out_ell;
+    run_stage<LOG2N, 0, GEN, EG>(v, c);
 }
 
-template <int LOG2N>
-const void *kernel_ptr()
+// Persistent workgroups with a one-tile register prefetch (no pre-twiddle).
+template <int LOG2N, bool GEN>
+__global__ __launch_bounds__(512) void local_fft_persistent_kernel(LocalPass P)
 {
-    return reinterpret_cast<const void *>(&local_fft_kernel<LOG2N>);
+    constexpr int EG = 32;
+    constexpr int TWN = stage_tw_total(LOG2N);
+    extern __shared__ float2 smem[];
+    const int log2T = P.log2T;
+    const int nt = blockDim.x;
+    float2 *twl = smem;
+    float2 *lds = smem + ((TWN + 63) & ~63);
+    for (int e = threadIdx.x; e < TWN; e += nt) twl[e] = P.stw[e];
+
+    const int64_t ntc = P.ncols >> log2T;
+    const int64_t G = P.n_outer * ntc;
+    const int64_t grid = gridDim.x;
+    int64_t i = blockIdx.x;
+    if (i >= G) return;
+
+    float2 cur[EG], nxt[EG];
+    {
+        const int64_t tile = tile_order(i, G, grid);
+        const int64_t o = tile / ntc, col0 = (tile - o * ntc) << log2T;
+        load_tile<LOG2N, GEN, EG>(P, reinterpret_cast<const char *>(P.src + col0), uint32_t(o * P.o_in),
+                                  threadIdx.x, nt, log2T, cur);
+    }
+    for (; i < G; i += grid) {
+        // An opaque copy of the thread index per tile keeps thread-invariant
+        // addresses and twiddles from being hoisted out of the loop and held
+        // in registers across it.
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        const int64_t tile = tile_order(i, G, grid);
+        const int64_t o = tile / ntc, col0 = (tile - o * ntc) << log2T;
+        if (i + grid < G) {
+            const int64_t tn = tile_order(i + grid, G, grid);
+            const int64_t on = tn / ntc, cn = (tn - on * ntc) << log2T;
+            load_tile<LOG2N, GEN, EG>(P, reinterpret_cast<const char *>(P.src + cn), uint32_t(on * P.o_in), tid, nt,
+                                      log2T, nxt);
+        }
+        if (i != blockIdx.x) __syncthreads();  // the previous tile's last LDS reads are done
+        Ctx c;
+        c.lds = lds;
+        c.twl = twl;
+        c.tid = tid;
+        c.nt = nt;
+        c.log2T = log2T;
+        c.dst = reinterpret_cast<char *>(P.dst + col0);
+        c.ld8 = uint32_t(P.ld) * 8u;
+        c.orow_out = uint32_t(o * P.o_out);
+        c.k_out = uint32_t(P.k_out);
+        c.out_t = P.out_t;
+        c.out_ell = P.out_ell;
+        run_stage<LOG2N, 0, GEN, EG>(cur, c);
+#pragma unroll
+        for (int e = 0; e < EG; ++e) cur[e] = nxt[e];
+    }
 }
 
-const void *kernel_for(int log2n)
+template <int L, bool PRE, bool GEN>
+const void *kptr()
+{
+    return reinterpret_cast<const void *>(&local_fft_kernel<L, PRE, GEN, (L < 4 ? (1 << L) : 16)>);
+}
+
+template <int L, bool GEN>
+const void *pptr()
+{
+    return reinterpret_cast<const void *>(&local_fft_persistent_kernel<L, GEN>);
+}
+
+template <bool PRE, bool GEN>
+const void *kernel_for_pre(int log2n)
 {
     switch (log2n) {
-    case 1: return kernel_ptr<1>();
-    case 2: return kernel_ptr<2>();
-    case 3: return kernel_ptr<3>();
-    case 4: return kernel_ptr<4>();
-    case 5: return kernel_ptr<5>();
-    case 6: return kernel_ptr<6>();
-    case 7: return kernel_ptr<7>();
-    case 8: return kernel_ptr<8>();
-    case 9: return kernel_ptr<9>();
-    case 10: return kernel_ptr<10>();
-    case 11: return kernel_ptr<11>();
-    case 12: return kernel_ptr<12>();
+    case 1: return kptr<1, PRE, GEN>();
+    case 2: return kptr<2, PRE, GEN>();
+    case 3: return kptr<3, PRE, GEN>();
+    case 4: return kptr<4, PRE, GEN>();
+    case 5: return kptr<5, PRE, GEN>();
+    case 6: return kptr<6, PRE, GEN>();
+    case 7: return kptr<7, PRE, GEN>();
+    case 8: return kptr<8, PRE, GEN>();
+    case 9: return kptr<9, PRE, GEN>();
+    case 10: return kptr<10, PRE, GEN>();
+    case 11: return kptr<11, PRE, GEN>();
+    case 12: return kptr<12, PRE, GEN>();
     default: return nullptr;
     }
+}
+
+template <bool GEN>
+const void *persistent_for(int log2n)
+{
+    switch (log2n) {
+    case 9: return pptr<9, GEN>();
+    case 10: return pptr<10, GEN>();
+    case 11: return pptr<11, GEN>();
+    case 12: return pptr<12, GEN>();
+    default: return nullptr;
+    }
+}
+
+const void *kernel_for(int log2n, bool pre, bool gen, bool persist)
+{
+    if (persist) return pre ? nullptr : (gen ? persistent_for<true>(log2n) : persistent_for<false>(log2n));
+    if (gen) return pre ? kernel_for_pre<true, true>(log2n) : kernel_for_pre<false, true>(log2n);
+    return pre ? kernel_for_pre<true, false>(log2n) : kernel_for_pre<false, false>(log2n);
+}
+
+bool pass_needs_gen(const LocalPass &p)
+{
+    return (p.in_ell && !digrev_fast(p.in_t)) || (p.out_ell && !digrev_fast(p.out_t)) ||
+           (p.tw_ell && !digrev_fast(p.tw_t));
 }
 
 }  // namespace
@@ -285,33 +401,53 @@ int32_t choose_log2T(int32_t log2n, int64_t ncols)
     return lt < lc ? lt : lc;
 }
 
+bool local_fft_has_persistent(int32_t log2n) { return kernel_for(log2n, false, false, true) != nullptr; }
+
 LocalLaunch local_fft_geometry(const LocalPass &p)
 {
-    const int E = p.log2n < 4 ? (1 << p.log2n) : 16;
+    const int EG = p.persist ? 32 : (p.log2n < 4 ? (1 << p.log2n) : 16);
     const int64_t items = int64_t(1) << (p.log2n + p.log2T);
+    const int64_t twn = (stage_tw_total(p.log2n) + 63) & ~63;
     LocalLaunch g;
-    g.threads = int(items / E);
-    g.lds_bytes = size_t(items + (items >> 5) + 1) * sizeof(float2);
-    g.groups = p.n_outer * (p.ncols >> p.log2T);
+    g.threads = int(items / EG);
+    g.lds_bytes = size_t(twn + items + ((items >> 6) << 2) + 4) * sizeof(float2);
+    g.tiles = p.n_outer * (p.ncols >> p.log2T);
     return g;
 }
 
 hipError_t local_fft_prepare()
 {
     for (int l = 1; l <= kMaxOnChipLog2; ++l) {
-        hipError_t e = hipFuncSetAttribute(kernel_for(l), hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
+        for (int v = 0; v < 8; ++v) {
+            const void *k = kernel_for(l, v & 1, v & 2, v & 4);
+            if (!k) continue;
+            hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+            if (e != hipSuccess) return e;
+        }
     }
     return hipSuccess;
 }
 
+int local_fft_occupancy(const LocalPass &p)
+{
+    const void *k = kernel_for(p.log2n, p.pre_tw != 0, pass_needs_gen(p), p.persist != 0);
+    if (!k) return 0;
+    const LocalLaunch g = local_fft_geometry(p);
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, g.threads, g.lds_bytes) != hipSuccess) return 0;
+    return nb;
+}
+
 hipError_t launch_local_fft(const LocalPass &p, hipStream_t s)
 {
-    const void *k = kernel_for(p.log2n);
+    const void *k = kernel_for(p.log2n, p.pre_tw != 0, pass_needs_gen(p), p.persist != 0);
     if (!k) return hipErrorInvalidValue;
     const LocalLaunch g = local_fft_geometry(p);
+    if (g.tiles < 1 || g.tiles > 0x7fffffff) return hipErrorInvalidValue;
+    int64_t grid = g.tiles;
+    if (p.persist && p.grid > 0 && p.grid < grid) grid = p.grid;
     void *args[] = {const_cast<LocalPass *>(&p)};
-    return hipLaunchKernel(k, dim3(unsigned(g.groups)), dim3(unsigned(g.threads)), args, g.lds_bytes, s);
+    return hipLaunchKernel(k, dim3(unsigned(grid)), dim3(unsigned(g.threads)), args, g.lds_bytes, s);
 }
 
 }  // namespace paco

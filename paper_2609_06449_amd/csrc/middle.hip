@@ -8,29 +8,37 @@
 // coordinate map (a, c) -> (pi_{m2}(c), pi_{m1}(a)) with the twiddle, and on
 // one device every step is an address: a workgroup owns a TV x TC tile of
 // logical (v, c) coordinates, reads rows a = pi_{m1}(v) (contiguous runs of
-// TC items), scales each item by its destination-indexed twiddle,
-// transposes the tile in LDS and writes rows u = pi_{m2}(c) (contiguous runs
-// of TV items).  With TV | N1/p and TC | N2/p every tile lies inside one
+// TC items), scales each item by its destination-indexed twiddle, transposes
+// the tile in LDS and writes rows u = pi_{m2}(c) (contiguous runs of TV
+// items).  When TV | N1/p and TC | N2/p every tile lies inside one
 // source/destination slab pair (q, q'), so the launch is the paper's block
 // exchange cut into equal tiles.
+//
+// The twiddle of item (v0 + vi, c0 + ci) is assembled from three factors,
+//   w_N^{-v c} = w_N^{-v0 c} * w_N^{-vi c0} * w_N^{-vi ci},
+// a per-thread value, a per-row value shared through LDS and a fixed
+// TV x TC table read with the same coalesced pattern as the data, so no
+// lane-divergent table gather sits on the per-item path.
 #include "paco_internal.h"
 
 namespace paco {
 namespace {
 
-constexpr int kTile = 64;
 constexpr int kThreads = 256;
+constexpr int kPerThread = kMidTile * kMidTile / kThreads;  // 16
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b)
 {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+template <bool GEN>
 __global__ __launch_bounds__(kThreads) void middle_kernel(MiddlePass P)
 {
-    __shared__ float2 tile[kTile * (kTile + 1)];
-    const int lTV = P.N1 < kTile ? __builtin_ctzll(P.N1) : 6;
-    const int lTC = P.N2 < kTile ? __builtin_ctzll(P.N2) : 6;
+    __shared__ float2 tile[kMidTile * (kMidTile + 1)];
+    __shared__ float2 rowtw[kMidTile];
+    const int lTV = P.N1 < kMidTile ? __builtin_ctzll(P.N1) : 6;
+    const int lTC = P.N2 < kMidTile ? __builtin_ctzll(P.N2) : 6;
     const int TV = 1 << lTV, TC = 1 << lTC;
     const int64_t nct = P.N2 >> lTC;
     const int64_t vt = blockIdx.x / nct;
@@ -40,23 +48,52 @@ __global__ __launch_bounds__(kThreads) void middle_kernel(MiddlePass P)
     const int64_t Lm = (int64_t(1) << P.log2Lo) - 1;
     const int tid = threadIdx.x;
 
-    for (int e = tid; e < TV * TC; e += kThreads) {
-        const int vi = e >> lTC, ci = e & (TC - 1);
-        const int64_t v = v0 + vi, c = c0 + ci;
-        const int64_t a = P.pi1[v];
-        float2 x = P.ws[a * P.N2 + c];
-        if (P.twiddle) {
-            const int64_t r = (v * c) & Nm;
-            x = cmul(x, cmul(P.tw_hi[r >> P.log2Lo], P.tw_lo[r & Lm]));
+    // read side: thread owns column ci and rows rg + q*rstep
+    const int ci = tid & (TC - 1);
+    const int rg = tid >> lTC;
+    const int rstep = kThreads >> lTC;
+    const int64_t c = c0 + ci;
+    float2 x[kPerThread], t4[kPerThread];
+#pragma unroll
+    for (int q = 0; q < kPerThread; ++q) {
+        const int vi = rg + q * rstep;
+        if (vi < TV) {
+            const int64_t a = digrev<GEN>(v0 + vi, P.t, P.m1);
+            x[q] = P.ws[a * P.N2 + c];
+            if (P.twiddle) t4[q] = P.tw_tile[vi * TC + ci];
         }
-        tile[ci * (kTile + 1) + vi] = x;
+    }
+    float2 wc = make_float2(1.f, 0.f);
+    if (P.twiddle) {
+        const int64_t r = (v0 * c) & Nm;
+        wc = cmul(P.tw_hi[r >> P.log2Lo], P.tw_lo[r & Lm]);
+        if (tid < TV) {
+            const int64_t rr = (int64_t(tid) * c0) & Nm;
+            rowtw[tid] = cmul(P.tw_hi[rr >> P.log2Lo], P.tw_lo[rr & Lm]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < kPerThread; ++q) {
+        const int vi = rg + q * rstep;
+        if (vi < TV) {
+            float2 y = x[q];
+            if (P.twiddle) y = cmul(y, cmul(cmul(wc, rowtw[vi]), t4[q]));
+            tile[ci * (kMidTile + 1) + vi] = y;
+        }
     }
     __syncthreads();
-    for (int e = tid; e < TV * TC; e += kThreads) {
-        const int ci = e >> lTV, vi = e & (TV - 1);
-        const int64_t c = c0 + ci;
-        const int64_t u = P.pi2[c];
-        P.out[u * P.N1 + v0 + vi] = tile[ci * (kTile + 1) + vi];
+    // write side: thread owns tile column vi and output rows cg + q*cstep
+    const int vi = tid & (TV - 1);
+    const int cg = tid >> lTV;
+    const int cstep = kThreads >> lTV;
+#pragma unroll
+    for (int q = 0; q < kPerThread; ++q) {
+        const int cj = cg + q * cstep;
+        if (cj < TC) {
+            const int64_t u = digrev<GEN>(c0 + cj, P.t, P.m2);
+            P.out[u * P.N1 + v0 + vi] = tile[cj * (kMidTile + 1) + vi];
+        }
     }
 }
 
@@ -64,9 +101,12 @@ __global__ __launch_bounds__(kThreads) void middle_kernel(MiddlePass P)
 
 hipError_t launch_middle(const MiddlePass &p, hipStream_t s)
 {
-    const int64_t TV = p.N1 < kTile ? p.N1 : kTile, TC = p.N2 < kTile ? p.N2 : kTile;
+    const int64_t TV = p.N1 < kMidTile ? p.N1 : kMidTile, TC = p.N2 < kMidTile ? p.N2 : kMidTile;
     const int64_t groups = (p.N1 / TV) * (p.N2 / TC);
-    hipLaunchKernelGGL(middle_kernel, dim3(unsigned(groups)), dim3(kThreads), 0, s, p);
+    if (digrev_fast(p.t))
+        hipLaunchKernelGGL(middle_kernel<false>, dim3(unsigned(groups)), dim3(kThreads), 0, s, p);
+    else
+        hipLaunchKernelGGL(middle_kernel<true>, dim3(unsigned(groups)), dim3(kThreads), 0, s, p);
     return hipGetLastError();
 }
 

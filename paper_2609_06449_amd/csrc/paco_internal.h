@@ -10,18 +10,96 @@ namespace paco {
 // Largest transform length one local pass keeps on chip (LDS + registers).
 constexpr int kMaxOnChipLog2 = 12;
 
+// ---------------------------------------------------------------------------
+// Stage plan of an on-chip transform of length n = 2^l: radix-16 Stockham
+// stages, then one radix-2^(l mod 4) stage when l is not a multiple of 4.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int stage_count(int l) { return l / 4 + (l % 4 ? 1 : 0); }
+__host__ __device__ constexpr int stage_log2radix(int l, int s) { return s < l / 4 ? 4 : l % 4; }
+__host__ __device__ constexpr int stage_log2ns(int l, int s)
+{
+    int a = 0;
+    for (int i = 0; i < s; ++i) a += stage_log2radix(l, i);
+    return a;
+}
+
+// Stage twiddles w_M^{-k r} (M = Ns*R, k < Ns, 1 <= r < R) are stored as two
+// factor tables per stage S >= 1, indexed (r-1, .):
+//   lo[r-1][kl] = w_M^{-kl*r},       kl < min(Ns, 16)
+//   hi[r-1][kh] = w_M^{-16*kh*r},    kh < Ns/16        (only when Ns > 16)
+// with k = 16*kh + kl, so w_M^{-k r} = hi * lo.  Lanes of a wave hold
+// consecutive k, so every table read is a broadcast or a contiguous run.
+__host__ __device__ constexpr int stage_lo_width(int l, int s)
+{
+    return (1 << stage_log2ns(l, s)) < 16 ? (1 << stage_log2ns(l, s)) : 16;
+}
+__host__ __device__ constexpr int stage_hi_width(int l, int s)
+{
+    return (1 << stage_log2ns(l, s)) > 16 ? (1 << stage_log2ns(l, s)) / 16 : 0;
+}
+__host__ __device__ constexpr int stage_tw_size(int l, int s)
+{
+    return s == 0 ? 0 : ((1 << stage_log2radix(l, s)) - 1) * (stage_lo_width(l, s) + stage_hi_width(l, s));
+}
+__host__ __device__ constexpr int stage_tw_offset(int l, int s)
+{
+    int a = 0;
+    for (int i = 1; i < s; ++i) a += stage_tw_size(l, i);
+    return a;
+}
+__host__ __device__ constexpr int stage_tw_total(int l) { return stage_tw_offset(l, stage_count(l)); }
+
+// pi_ell in base b = 2^t (appendix A.1): the ell groups of t bits of x in
+// the opposite order.  ell == 0 is the identity.
+__host__ __device__ inline int64_t digit_reverse_bits(int64_t x, int t, int ell)
+{
+    if (ell == 0) return x;
+    int64_t r = 0;
+    const int64_t m = (int64_t(1) << t) - 1;
+    for (int g = 0; g < ell; ++g) {
+        r = (r << t) | (x & m);
+        x >>= t;
+    }
+    return r;
+}
+
+// The same permutation on the device for b = 2^t with t in {1, 2, 4, 8}
+// (t*ell <= 32): reverse all t*ell bits, then restore the bit order inside
+// each t-bit digit with up to three mask swaps.  Branch-free; GEN selects the
+// digit-by-digit loop for other t.
+template <bool GEN = false>
+__device__ __forceinline__ int64_t digrev(int64_t x, int t, int ell)
+{
+    if constexpr (GEN) {
+        return digit_reverse_bits(x, t, ell);
+    } else {
+        const int nb = t * ell;
+        uint32_t r = __builtin_bitreverse32(uint32_t(x)) >> ((32 - nb) & 31);
+        const uint32_t s1 = ((r & 0x55555555u) << 1) | ((r >> 1) & 0x55555555u);
+        r = t >= 2 ? s1 : r;
+        const uint32_t s2 = ((r & 0x33333333u) << 2) | ((r >> 2) & 0x33333333u);
+        r = t >= 4 ? s2 : r;
+        const uint32_t s3 = ((r & 0x0F0F0F0Fu) << 4) | ((r >> 4) & 0x0F0F0F0Fu);
+        r = t >= 8 ? s3 : r;
+        return nb == 0 ? x : int64_t(r);
+    }
+}
+
+// True when the branch-free device digit reversal covers digit width t.
+__host__ __device__ constexpr bool digrev_fast(int t) { return t == 1 || t == 2 || t == 4 || t == 8; }
+
 // One HBM pass of a batched local FFT: the GPU form of a digit-field view
-// (paper, appendix A.3-A.4).  The pass runs n_outer * (ncols / T) independent
-// groups; group (o, tile) transforms the T contiguous columns
-// [tile*T, tile*T + T) of the rows
-//     input  row of logical j : o*o_in  + map_in(j)  * j_in
-//     output row of logical k : o*o_out + map_out(k) * k_out
-// where map_in / map_out are the identity or a base-b digit reversal table.
-// A row is ld complex64 items long; the column field C of the paper's view is
-// the contiguous run of T items that every access reads or writes whole.
-// Before the length-n DFT the input j of group o is scaled by the
-// Cooley-Tukey twiddle w_M^{-f(o)*j}, f(o) = o or tw_perm[o] (the
-// layout-aware twiddle of appendix A.2), when pre_tw is set.
+// (paper, appendix A.3-A.4).  The pass has n_outer * (ncols / T) independent
+// tiles; tile (o, c) transforms the T contiguous columns [c*T, c*T + T) of
+// the rows
+//     input  row of logical j : o*o_in  + pi_in(j)  * j_in
+//     output row of logical k : o*o_out + pi_out(k) * k_out
+// where pi_in / pi_out are base-2^t digit reversals over ell digits
+// (ell = 0: identity).  A row is ld complex64 items long; the column field C
+// of the paper's view is the run of T items every access reads or writes
+// whole.  With pre_tw set, input j of tile o is first scaled by the
+// Cooley-Tukey twiddle w_M^{-f(o)*j}, f(o) = pi_tw(o) (the layout-aware
+// twiddle of appendix A.2).
 struct LocalPass {
     const float2 *src;
     float2 *dst;
@@ -32,34 +110,43 @@ struct LocalPass {
     int64_t n_outer;       // outer batch count
     int64_t o_in, j_in;    // input row strides
     int64_t o_out, k_out;  // output row strides
-    const int32_t *perm_in;   // nullable
-    const int32_t *perm_out;  // nullable
-    const float2 *tw;         // w_L^{-r}, r < L = 2^log2L (FP64-generated)
+    int32_t in_t, in_ell;  // pi_in
+    int32_t out_t, out_ell;  // pi_out
+    const float2 *stw;     // stage twiddle tables of length n (stage_tw_total entries)
+    const float2 *tw;      // w_L^{-r}, r < L = 2^log2L (pre-twiddle)
     int32_t log2L;
-    int32_t pre_tw;           // 0: none; 1: w_M^{-f(o) j} before the DFT
-    int32_t log2M;            // M of the pre-twiddle (M <= L)
-    const int32_t *tw_perm;   // nullable: f(o) = tw_perm[o], else f(o) = o
+    int32_t pre_tw;        // 0: none; 1: w_M^{-f(o) j} before the DFT
+    int32_t log2M;         // M of the pre-twiddle (M <= L)
+    int32_t tw_t, tw_ell;  // f(o) = pi_tw(o)
+    int32_t persist;       // 1: persistent 512-thread workgroups with register prefetch
+    int32_t grid;          // persistent launch: workgroups resident at once
 };
 
-// Phase II: out[pi2[c]*N1 + v] = ws[pi1[v]*N2 + c] * w_N^{-(v*c mod N)}, the
-// fused middle permutation (section 3.3) written by v = pi_{m1}(a).
+// Phase II: out[pi2(c)*N1 + v] = ws[pi1(v)*N2 + c] * w_N^{-(v*c mod N)}, the
+// fused middle permutation (section 3.3) indexed by v = pi_{m1}(a).  With
+// v = v0 + vi and c = c0 + ci inside a TV x TC tile,
+//   w_N^{-v c} = w_N^{-v0 c} * w_N^{-vi c0} * w_N^{-vi ci}
+// the first factor per thread (tw_hi/tw_lo two-level table), the second per
+// tile row, the third from a fixed TV x TC table (tw_tile).
 struct MiddlePass {
     const float2 *ws;
     float2 *out;
     int64_t N1, N2;
-    const int32_t *pi1;       // pi_{m1} over [N1]
-    const int32_t *pi2;       // pi_{m2} over [N2]
+    int32_t t, m1, m2;        // b = 2^t, N1 = b^m1, N2 = b^m2
     const float2 *tw_hi;      // w_N^{-h*Lo}, h < N/Lo
     const float2 *tw_lo;      // w_N^{-l}, l < Lo
+    const float2 *tw_tile;    // [vi][ci] = w_N^{-(vi*ci mod N)}, TV x TC
     int32_t log2N, log2Lo;
     int32_t twiddle;          // 0: bare permutation
 };
+
+constexpr int kMidTile = 64;
 
 // Workgroup geometry a local pass is launched with.
 struct LocalLaunch {
     int threads;       // per workgroup
     size_t lds_bytes;  // dynamic LDS per workgroup
-    int64_t groups;    // workgroups
+    int64_t tiles;     // column tiles in the pass
 };
 
 LocalLaunch local_fft_geometry(const LocalPass &p);
@@ -69,5 +156,9 @@ hipError_t launch_middle(const MiddlePass &p, hipStream_t s);
 
 // Columns per workgroup for an on-chip pass of length 2^log2n over ncols.
 int32_t choose_log2T(int32_t log2n, int64_t ncols);
+// Whether the persistent kernel exists for this length.
+bool local_fft_has_persistent(int32_t log2n);
+// Workgroups of this pass one CU holds at once (0 on error).
+int local_fft_occupancy(const LocalPass &p);
 
 }  // namespace paco

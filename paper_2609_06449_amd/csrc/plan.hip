@@ -3,6 +3,7 @@
 // middle.hip.
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -38,18 +39,6 @@ int ilog2_exact(int64_t n)
     return l;
 }
 
-// pi_ell in base b = 2^t: the ell groups of t bits in the opposite order
-// (appendix A.1).
-int32_t digit_reverse(int64_t i, int t, int ell)
-{
-    int64_t r = 0;
-    for (int g = 0; g < ell; ++g) {
-        r = (r << t) | (i & ((int64_t(1) << t) - 1));
-        i >>= t;
-    }
-    return int32_t(r);
-}
-
 // w_M^{-r} = exp(-2 pi i r / M), evaluated in FP64 from the exact integer r
 // and rounded once to FP32.
 float2 root_neg(int64_t r, int64_t M)
@@ -59,7 +48,7 @@ float2 root_neg(int64_t r, int64_t M)
 }
 
 constexpr int kMaxLocalLog2 = 16;  // N1, N2 <= 2^16 (at most two on-chip passes)
-constexpr int kMaxTotalLog2 = 32;  // N1*N2 <= 2^32
+constexpr int kMaxTotalLog2 = 28;  // N1*N2 <= 2^28: every buffer < 4 GiB (32-bit byte offsets)
 
 }  // namespace
 
@@ -104,7 +93,7 @@ paco_status paco_plan_validate(int64_t N1, int64_t N2, int64_t p, int32_t b, pac
         return fail(PACO_ERR_NOT_POWER_OF_B, "N1 and N2 must be powers of b (b^m with m >= 1)");
     if (p < 2 || N1 % p || N2 % p) return fail(PACO_ERR_DIVISIBILITY, "need p >= 2, p | N1, p | N2");
     if (l1 > kMaxLocalLog2 || l2 > kMaxLocalLog2 || l1 + l2 > kMaxTotalLog2)
-        return fail(PACO_ERR_UNSUPPORTED, "this build supports N1, N2 <= 2^16 and N1*N2 <= 2^32");
+        return fail(PACO_ERR_UNSUPPORTED, "this build supports N1, N2 <= 2^16 and N1*N2 <= 2^28");
     if (N1 / p < 16 || N2 / p < 16)
         g_last_error = "note: slab width N1/p or N2/p below 16 items (one 128-byte line)";
     else
@@ -168,30 +157,42 @@ paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p
         return fail(PACO_ERR_UNSUPPORTED, "local transform needs more than two on-chip passes");
     }
 
-    // ---- host tables -------------------------------------------------------
-    const int64_t L = int64_t(1) << P->lL, Lo = int64_t(1) << P->lLo, Hi = (int64_t(1) << P->lN) >> P->lLo;
-    std::vector<int32_t> pi1(N1), pi2(N2), sa1(int64_t(1) << a1), sb1(int64_t(1) << b1),
-        sa3(int64_t(1) << a3), sb3(int64_t(1) << b3);
-    for (int64_t i = 0; i < N1; ++i) pi1[i] = digit_reverse(i, P->t, P->m1);
-    for (int64_t i = 0; i < N2; ++i) pi2[i] = digit_reverse(i, P->t, P->m2);
-    for (size_t i = 0; i < sa1.size(); ++i) sa1[i] = digit_reverse(i, P->t, a1 / P->t);
-    for (size_t i = 0; i < sb1.size(); ++i) sb1[i] = digit_reverse(i, P->t, b1 / P->t);
-    for (size_t i = 0; i < sa3.size(); ++i) sa3[i] = digit_reverse(i, P->t, a3 / P->t);
-    for (size_t i = 0; i < sb3.size(); ++i) sb3[i] = digit_reverse(i, P->t, b3 / P->t);
-    std::vector<float2> tw(L), thi(Hi), tlo(Lo);
-    for (int64_t r = 0; r < L; ++r) tw[r] = root_neg(r, L);
+    // ---- host tables (FP64-generated, rounded once to FP32) ----------------
     const int64_t N = int64_t(1) << P->lN;
+    const int64_t L = int64_t(1) << P->lL, Lo = int64_t(1) << P->lLo, Hi = N >> P->lLo;
+    const int64_t TV = N1 < paco::kMidTile ? N1 : paco::kMidTile, TC = N2 < paco::kMidTile ? N2 : paco::kMidTile;
+    std::vector<float2> tw(L), thi(Hi), tlo(Lo), ttile(TV * TC);
+    for (int64_t r = 0; r < L; ++r) tw[r] = root_neg(r, L);
     for (int64_t h = 0; h < Hi; ++h) thi[h] = root_neg(h * Lo, N);
     for (int64_t l = 0; l < Lo; ++l) tlo[l] = root_neg(l, N);
+    for (int64_t vi = 0; vi < TV; ++vi)
+        for (int64_t ci = 0; ci < TC; ++ci) ttile[vi * TC + ci] = root_neg((vi * ci) % N, N);
+    // stage twiddle factor tables of every on-chip length 2^1 .. 2^12
+    std::vector<float2> stw;
+    int64_t stw_off[paco::kMaxOnChipLog2 + 1] = {0};
+    for (int l = 1; l <= paco::kMaxOnChipLog2; ++l) {
+        stw_off[l] = int64_t(stw.size());
+        for (int S = 1; S < paco::stage_count(l); ++S) {
+            const int R = 1 << paco::stage_log2radix(l, S);
+            const int64_t Ns = int64_t(1) << paco::stage_log2ns(l, S), M = Ns * R;
+            const int LOW = paco::stage_lo_width(l, S), HIW = paco::stage_hi_width(l, S);
+            for (int r = 1; r < R; ++r)
+                for (int kl = 0; kl < LOW; ++kl) stw.push_back(root_neg((int64_t(kl) * r) % M, M));
+            for (int r = 1; r < R; ++r)
+                for (int kh = 0; kh < HIW; ++kh) stw.push_back(root_neg((int64_t(16) * kh * r) % M, M));
+        }
+        if (int64_t(stw.size()) - stw_off[l] != paco::stage_tw_total(l)) {
+            delete P;
+            return fail(PACO_ERR_INVALID_ARG, "internal: stage twiddle layout mismatch");
+        }
+    }
+    stw.push_back(make_float2(0.f, 0.f));  // never empty
 
     // one device allocation, 256-byte aligned pieces
     struct Piece { const void *src; size_t bytes; size_t off; };
-    std::vector<Piece> pieces = {
-        {pi1.data(), pi1.size() * 4, 0}, {pi2.data(), pi2.size() * 4, 0},
-        {sa1.data(), sa1.size() * 4, 0}, {sb1.data(), sb1.size() * 4, 0},
-        {sa3.data(), sa3.size() * 4, 0}, {sb3.data(), sb3.size() * 4, 0},
-        {tw.data(), tw.size() * 8, 0},   {thi.data(), thi.size() * 8, 0},
-        {tlo.data(), tlo.size() * 8, 0}};
+    std::vector<Piece> pieces = {{tw.data(), tw.size() * 8, 0},       {thi.data(), thi.size() * 8, 0},
+                                 {tlo.data(), tlo.size() * 8, 0},     {ttile.data(), ttile.size() * 8, 0},
+                                 {stw.data(), stw.size() * 8, 0}};
     size_t total = 0;
     for (auto &pc : pieces) {
         pc.off = total;
@@ -208,119 +209,141 @@ paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p
     e = hipMemcpy(P->dev_tables, staging.data(), total, hipMemcpyHostToDevice);
     if (e != hipSuccess) { (void)hipFree(P->dev_tables); delete P; return hip_fail(e, "hipMemcpy"); }
     auto at = [&](int i) { return static_cast<unsigned char *>(P->dev_tables) + pieces[i].off; };
-    const int32_t *d_pi1 = reinterpret_cast<const int32_t *>(at(0));
-    const int32_t *d_pi2 = reinterpret_cast<const int32_t *>(at(1));
-    const int32_t *d_sa1 = reinterpret_cast<const int32_t *>(at(2));
-    const int32_t *d_sb1 = reinterpret_cast<const int32_t *>(at(3));
-    const int32_t *d_sa3 = reinterpret_cast<const int32_t *>(at(4));
-    const int32_t *d_sb3 = reinterpret_cast<const int32_t *>(at(5));
-    const float2 *d_tw = reinterpret_cast<const float2 *>(at(6));
-    const float2 *d_thi = reinterpret_cast<const float2 *>(at(7));
-    const float2 *d_tlo = reinterpret_cast<const float2 *>(at(8));
+    const float2 *d_tw = reinterpret_cast<const float2 *>(at(0));
+    const float2 *d_thi = reinterpret_cast<const float2 *>(at(1));
+    const float2 *d_tlo = reinterpret_cast<const float2 *>(at(2));
+    const float2 *d_ttile = reinterpret_cast<const float2 *>(at(3));
+    const float2 *d_stw = reinterpret_cast<const float2 *>(at(4));
 
-    auto base_pass = [&](int64_t ld, int64_t ncols) {
+    auto base_pass = [&](int64_t ld, int64_t ncols, int log2n) {
         LocalPass q{};
         q.ld = ld;
         q.ncols = ncols;
+        q.log2n = log2n;
+        q.log2T = paco::choose_log2T(log2n, ncols);
+        // Long transforms: persistent workgroups with register prefetch.
+        const char *pe = std::getenv("PACO_PERSIST");
+        if (!(pe && pe[0] == '0') && paco::local_fft_has_persistent(log2n) && (int64_t(1) << (14 - log2n)) <= ncols) {
+            q.persist = 1;
+            q.log2T = 14 - log2n;  // 2^14 items per tile
+        }
+        // tuning knob: columns per workgroup for long single-group transforms
+        if (const char *ev = std::getenv("PACO_LOG2T_LONG")) {
+            const int want = std::atoi(ev);
+            if (!q.persist && log2n >= 10 && want >= 0 && (int64_t(1) << want) <= ncols) q.log2T = want;
+        }
+        q.stw = d_stw + stw_off[log2n];
         q.tw = d_tw;
         q.log2L = P->lL;
         q.n_outer = 1;
         return q;
     };
-    char buf[512];
-    std::string desc;
+    const int t = P->t;
 
     // ---- Phase I: A_{m1} (x) I_{N2}, output layout (Lemma 1) -------------
     if (b1 == 0) {
-        LocalPass q = base_pass(N2, N2);
-        q.log2n = a1;
+        LocalPass q = base_pass(N2, N2, a1);
         q.j_in = 1;
         q.k_out = 1;
-        q.perm_out = d_pi1;                 // logical k1 -> row pi_{m1}(k1)
-        q.log2T = paco::choose_log2T(a1, N2);
+        q.out_t = t;                        // logical k1 -> row pi_{m1}(k1)
+        q.out_ell = P->m1;
         P->phase1.push_back(q);
     } else {
         // first child: length n1 = 2^a1 over j1 (row stride n2), batch j2;
         // its frequency k1 lands at physical row field pi(k1)
         const int64_t n2 = int64_t(1) << b1;
-        LocalPass A = base_pass(N2, N2);
-        A.log2n = a1;
+        LocalPass A = base_pass(N2, N2, a1);
         A.n_outer = n2;
         A.o_in = 1;
         A.j_in = n2;
         A.o_out = 1;
         A.k_out = n2;
-        A.perm_out = d_sa1;
-        A.log2T = paco::choose_log2T(a1, N2);
+        A.out_t = t;
+        A.out_ell = a1 / t;
         // second child: length n2 over j2 for each physical a, twiddle
         // w_{N1}^{-pi(a) j2} from the represented k1 = pi(a) (appendix A.2)
-        LocalPass B = base_pass(N2, N2);
-        B.log2n = b1;
+        LocalPass B = base_pass(N2, N2, b1);
         B.n_outer = int64_t(1) << a1;
         B.o_in = n2;
         B.j_in = 1;
         B.o_out = n2;
         B.k_out = 1;
-        B.perm_out = d_sb1;
+        B.out_t = t;
+        B.out_ell = b1 / t;
         B.pre_tw = 1;
         B.log2M = P->l1;
-        B.tw_perm = d_sa1;
-        B.log2T = paco::choose_log2T(b1, N2);
+        B.tw_t = t;
+        B.tw_ell = a1 / t;
         P->phase1.push_back(A);
         P->phase1.push_back(B);
     }
     // ---- Phase III: B_{m2} (x) I_{N1}, input layout ----------------------
     if (b3 == 0) {
-        LocalPass q = base_pass(N1, N1);
-        q.log2n = a3;
+        LocalPass q = base_pass(N1, N1, a3);
         q.j_in = 1;
         q.k_out = 1;
-        q.perm_in = d_pi2;                  // logical j2 read from row pi_{m2}(j2)
-        q.log2T = paco::choose_log2T(a3, N1);
+        q.in_t = t;                         // logical j2 read from row pi_{m2}(j2)
+        q.in_ell = P->m2;
         P->phase3.push_back(q);
     } else {
         // logical j = j1*s2 + j2 sits at row pi(j2)*s1 + pi(j1)
-        const int64_t s1 = int64_t(1) << a3, s2 = int64_t(1) << b3;
-        LocalPass A = base_pass(N1, N1);
-        A.log2n = a3;
-        A.n_outer = s2;
+        const int64_t s1 = int64_t(1) << a3;
+        LocalPass A = base_pass(N1, N1, a3);
+        A.n_outer = int64_t(1) << b3;
         A.o_in = s1;
         A.j_in = 1;
-        A.perm_in = d_sa3;
+        A.in_t = t;
+        A.in_ell = a3 / t;
         A.o_out = s1;
         A.k_out = 1;
-        A.log2T = paco::choose_log2T(a3, N1);
-        LocalPass B = base_pass(N1, N1);
-        B.log2n = b3;
+        LocalPass B = base_pass(N1, N1, b3);
         B.n_outer = s1;
         B.o_in = 1;
         B.j_in = s1;
-        B.perm_in = d_sb3;
+        B.in_t = t;
+        B.in_ell = b3 / t;
         B.pre_tw = 1;
         B.log2M = P->l2;
         B.o_out = 1;
         B.k_out = s1;
-        B.log2T = paco::choose_log2T(b3, N1);
         P->phase3.push_back(A);
         P->phase3.push_back(B);
     }
+    int ncu = 0;
+    e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, P->device);
+    if (e != hipSuccess || ncu < 1) { (void)hipFree(P->dev_tables); delete P; return hip_fail(e, "hipDeviceGetAttribute"); }
+    for (auto *ph : {&P->phase1, &P->phase3})
+        for (auto &q : *ph)
+            if (q.persist) q.grid = paco::local_fft_occupancy(q) * ncu;
+    for (auto *ph : {&P->phase1, &P->phase3})
+        for (const auto &q : *ph)
+            if (paco::local_fft_geometry(q).lds_bytes > 160 * 1024 || paco::local_fft_geometry(q).threads > 1024 ||
+                (q.persist && q.grid < 1)) {
+                (void)hipFree(P->dev_tables);
+                delete P;
+                return fail(PACO_ERR_UNSUPPORTED, "local FFT tile does not fit one workgroup");
+            }
     // ---- Phase II ---------------------------------------------------------
     P->mid.N1 = N1;
     P->mid.N2 = N2;
-    P->mid.pi1 = d_pi1;
-    P->mid.pi2 = d_pi2;
+    P->mid.t = t;
+    P->mid.m1 = P->m1;
+    P->mid.m2 = P->m2;
     P->mid.tw_hi = d_thi;
     P->mid.tw_lo = d_tlo;
+    P->mid.tw_tile = d_ttile;
     P->mid.log2N = P->lN;
     P->mid.log2Lo = P->lLo;
     P->mid.twiddle = 1;
 
+    char buf[512];
+    std::string desc;
     for (auto *ph : {&P->phase1, &P->phase3}) {
         desc += ph == &P->phase1 ? "phase1[" : " phase2[tile64x64] phase3[";
         for (const auto &q : *ph) {
             const paco::LocalLaunch g = paco::local_fft_geometry(q);
-            std::snprintf(buf, sizeof buf, " n=2^%d T=%d outer=%lld wg=%lld thr=%d lds=%zu", q.log2n, 1 << q.log2T,
-                          (long long)q.n_outer, (long long)g.groups, g.threads, g.lds_bytes);
+            std::snprintf(buf, sizeof buf, " n=2^%d T=%d%s outer=%lld wg=%lld thr=%d lds=%zu", q.log2n, 1 << q.log2T,
+                          q.persist ? "(persistent)" : "", (long long)q.n_outer, (long long)g.tiles, g.threads, g.lds_bytes);
             desc += buf;
         }
         desc += " ]";

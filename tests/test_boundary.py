@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 
 @pytest.mark.parametrize("N1,N2,p,b", [
     (64, 64, 4, 4), (4096, 4096, 64, 16), (4, 4, 2, 2), (1 << 14, 1 << 14, 256, 4),
-    (1 << 13, 1 << 15, 128, 2), (4096, 1 << 14, 64, 4), (16, 16, 16, 16), (1 << 16, 1 << 16, 2, 16),
+    (1 << 13, 1 << 15, 128, 2), (4096, 1 << 14, 64, 4), (16, 16, 16, 16), (1 << 16, 1 << 12, 2, 16),
 ])
 def test_validate_accepts_contract(N1, N2, p, b):
     assert paco.paco_plan_validate(N1, N2, p, b) == paco.PACO_OK
@@ -53,6 +53,7 @@ def test_validate_accepts_contract(N1, N2, p, b):
     (64, 16, 32, 4, paco.PACO_ERR_DIVISIBILITY),       # p | N1 but not N2
     (1 << 18, 4, 2, 2, paco.PACO_ERR_UNSUPPORTED),     # N1 above 2^16
     (1 << 20, 1 << 20, 2, 16, paco.PACO_ERR_UNSUPPORTED),
+    (1 << 16, 1 << 16, 2, 16, paco.PACO_ERR_UNSUPPORTED),   # N above 2^28
 ])
 def test_validate_rejects(N1, N2, p, b, status):
     assert paco.paco_plan_validate(N1, N2, p, b) == status
