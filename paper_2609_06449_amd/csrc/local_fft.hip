@@ -14,15 +14,15 @@
 // logical input j from row pi(j) (input layout Omega P_pi).  Rows are
 // contiguous runs of T items, so a digit-reversed row order costs nothing.
 //
-// Two launch shapes.  Short transforms: one tile per workgroup of up to 1024
-// threads with 16 items each.  Long transforms (n >= 2^9): persistent
-// workgroups of 512 threads with 32 items each (two waves per SIMD, 256
-// VGPRs of budget) that walk a sequence of tiles and load the next tile's
-// first-stage operands into registers before computing the current one, so
-// the HBM traffic of neighbouring tiles overlaps the arithmetic and LDS
-// exchanges of the current one.  Stage twiddles come from small factor
-// tables copied to LDS once per workgroup (broadcast or contiguous reads);
-// row digit reversals are computed with bit operations.
+// One tile per workgroup of up to 1024 threads.  Stage twiddles come from
+// small factor tables copied to LDS by each workgroup (broadcast or
+// contiguous reads).  Two kernel families share the stage code:
+//  * fast: one HBM pass of a single-pass Phase I or Phase III with b in
+//    {2, 4, 16}; the tile width is a compile-time constant (LDS addresses fold
+//    to immediates) and the digit reversal of the 16 rows a thread touches
+//    costs one reversal per thread, by the composition identity
+//    pi(r*2^L + j) = pi(j)*2^LR + pi(r) (appendix A.8) with pi(r) a constant;
+//  * generic: any pass descriptor (two-pass steps, pre-twiddles, any b).
 #include "paco_internal.h"
 
 namespace paco {
@@ -99,19 +99,41 @@ __device__ __forceinline__ void dft_regs(float2 *v)
 // stride 16*T items) land on distinct banks.
 __device__ __forceinline__ int lpad(int e) { return e + ((e >> 6) << 2); }
 
+// Digit reversal with compile-time digit width TB and digit count ND.
+template <int TB, int ND>
+__device__ __forceinline__ uint32_t drev(uint32_t x)
+{
+    uint32_t r = 0;
+#pragma unroll
+    for (int g = 0; g < ND; ++g) r |= ((x >> (TB * g)) & ((1u << TB) - 1)) << (TB * (ND - 1 - g));
+    return r;
+}
+constexpr int crev(int x, int tb, int nd)
+{
+    int r = 0;
+    for (int g = 0; g < nd; ++g) r |= ((x >> (tb * g)) & ((1 << tb) - 1)) << (tb * (nd - 1 - g));
+    return r;
+}
+
+// Tile width of the fast kernels: 4096 items per workgroup for short
+// transforms, 4 columns (32-byte row runs) for long ones.
+constexpr int fast_log2T(int l) { return l >= 10 ? 2 : 12 - l; }
+
 struct Ctx {
     float2 *lds;
     const float2 *twl;
     int tid, nt, log2T;
     char *dst;                 // tile base (column col0 of row 0)
     uint32_t ld8;              // row length in bytes
-    uint32_t orow_out, k_out;  // output row = orow_out + pi_out(k) * k_out
+    uint32_t orow_out, k_out;  // generic: output row = orow_out + pi_out(k) * k_out
     int out_t, out_ell;
 };
 
 // Stage S of the Stockham sequence.  v[i*R + r] is operand r of butterfly i;
 // butterfly id g = tid + i*nt covers column g mod T and index j = g / T.
-template <int LOG2N, int S, bool GEN, int EG>
+// LT >= 0: compile-time log2 T.  MODE: -1 generic output rows, 0 digit-
+// reversed output rows (Phase I), 1 natural output rows (Phase III).
+template <int LOG2N, int S, int EG, int LT, int MODE, int TB, bool GEN>
 __device__ __forceinline__ void run_stage(float2 (&v)[EG], const Ctx &c)
 {
     constexpr int LR = stage_log2radix(LOG2N, S);
@@ -119,23 +141,26 @@ __device__ __forceinline__ void run_stage(float2 (&v)[EG], const Ctx &c)
     constexpr int LNS = stage_log2ns(LOG2N, S);
     constexpr int NB = EG / R;
     constexpr bool last = (S + 1 == stage_count(LOG2N));
-    const int Tm = (1 << c.log2T) - 1;
+    const int log2T = LT >= 0 ? LT : c.log2T;
+    const int nt = LT >= 0 ? ((1 << (LOG2N + (LT >= 0 ? LT : 0))) / EG) : c.nt;
+    const int Tm = (1 << log2T) - 1;
 
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-        const int g = c.tid + i * c.nt;
-        const int j = g >> c.log2T;
+        const int g = c.tid + i * nt;
+        const int j = g >> log2T;
         float2 *u = &v[i * R];
         if constexpr (LNS > 0) {
             constexpr int LOW = stage_lo_width(LOG2N, S);
             constexpr int HIW = stage_hi_width(LOG2N, S);
             constexpr int OFF = stage_tw_offset(LOG2N, S);
             const int k = j & ((1 << LNS) - 1);
-            const int kl = k & (LOW - 1), kh = k >> 4;
+            const float2 *tlo = c.twl + OFF + (k & (LOW - 1));
+            const float2 *thi = c.twl + OFF + (R - 1) * LOW + (k >> 4);
 #pragma unroll
             for (int r = 1; r < R; ++r) {
-                float2 w = c.twl[OFF + (r - 1) * LOW + kl];
-                if constexpr (HIW > 0) w = cmul(w, c.twl[OFF + (R - 1) * LOW + (r - 1) * HIW + kh]);
+                float2 w = tlo[(r - 1) * LOW];
+                if constexpr (HIW > 0) w = cmul(w, thi[(r - 1) * HIW]);
                 u[r] = cmul(u[r], w);
             }
         }
@@ -149,61 +174,90 @@ __device__ __forceinline__ void run_stage(float2 (&v)[EG], const Ctx &c)
         if constexpr (S > 0) __syncthreads();  // all stage-S operands were read
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
-            const int g = c.tid + i * c.nt;
-            const int t = g & Tm, j = g >> c.log2T;
+            const int g = c.tid + i * nt;
+            const int t = g & Tm, j = g >> log2T;
             const int idxD = ((j >> LNS) << (LNS + LR)) + (j & ((1 << LNS) - 1));
 #pragma unroll
-            for (int r = 0; r < R; ++r) c.lds[lpad(((idxD + (r << LNS)) << c.log2T) + t)] = v[i * R + r];
+            for (int r = 0; r < R; ++r) c.lds[lpad(((idxD + (r << LNS)) << log2T) + t)] = v[i * R + r];
         }
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < NB2; ++i) {
-            const int g = c.tid + i * c.nt;
-            const int t = g & Tm, j = g >> c.log2T;
+            const int g = c.tid + i * nt;
+            const int t = g & Tm, j = g >> log2T;
 #pragma unroll
-            for (int r = 0; r < R2; ++r) v[i * R2 + r] = c.lds[lpad(((j + (r << LNR2)) << c.log2T) + t)];
+            for (int r = 0; r < R2; ++r) v[i * R2 + r] = c.lds[lpad(((j + (r << LNR2)) << log2T) + t)];
         }
-        run_stage<LOG2N, S + 1, GEN, EG>(v, c);
+        run_stage<LOG2N, S + 1, EG, LT, MODE, TB, GEN>(v, c);
     } else {
         // last stage: j < n/R = 2^LNS, outputs are the natural-order rows k = j + r*2^LNS
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
-            const int g = c.tid + i * c.nt;
-            const int t = g & Tm, j = g >> c.log2T;
+            const int g = c.tid + i * nt;
+            const int t = g & Tm, j = g >> log2T;
+            if constexpr (MODE == 0) {
+                // row pi(k) = pi(j)*2^LR + pi(r)
+                const uint32_t base = ((drev<TB, LNS / TB>(j) << LR) * c.ld8) + uint32_t(t) * 8u;
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const uint32_t k = j + (r << LNS);
-                const uint32_t m = uint32_t(digrev<GEN>(k, c.out_t, c.out_ell));
-                const uint32_t off = (c.orow_out + m * c.k_out) * c.ld8 + uint32_t(t) * 8u;
-                *reinterpret_cast<float2 *>(c.dst + off) = v[i * R + r];
+                for (int r = 0; r < R; ++r)
+                    *reinterpret_cast<float2 *>(c.dst + base + uint32_t(crev(r, TB, LR / TB)) * c.ld8) = v[i * R + r];
+            } else if constexpr (MODE == 1) {
+                const uint32_t base = uint32_t(j) * c.ld8 + uint32_t(t) * 8u;
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    *reinterpret_cast<float2 *>(c.dst + base + (uint32_t(r) << LNS) * c.ld8) = v[i * R + r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const uint32_t k = j + (r << LNS);
+                    const uint32_t m = uint32_t(digrev<GEN>(k, c.out_t, c.out_ell));
+                    const uint32_t off = (c.orow_out + m * c.k_out) * c.ld8 + uint32_t(t) * 8u;
+                    *reinterpret_cast<float2 *>(c.dst + off) = v[i * R + r];
+                }
             }
         }
     }
 }
 
 // Tile order: the hardware deals consecutive workgroup ids to the 8 XCDs in
-// turn, and a workgroup stays on its XCD.  Renumber so that the tiles one
-// XCD works on at the same time are neighbouring column tiles, which share
-// 128-byte lines in that XCD's L2.  i runs over rounds of `grid` tiles.
-__device__ __forceinline__ int64_t tile_order(int64_t i, int64_t G, int64_t grid)
+// turn.  Renumber so that the workgroups one XCD receives back to back own
+// neighbouring column tiles, which share 128-byte lines in that XCD's L2.
+__device__ __forceinline__ int64_t tile_order(int64_t i, int64_t G)
 {
-    const int64_t s = i / grid, b = i - s * grid;
-    if ((grid & 7) || (s + 1) * grid > G) return i;
-    return s * grid + (b & 7) * (grid >> 3) + (b >> 3);
+    if (G & 7) return i;
+    return (i & 7) * (G >> 3) + (i >> 3);
 }
 
-// First-stage operands of one tile: rows o*o_in + pi_in(jj)*j_in, jj = j +
-// r*2^LNR0, column col0 + t.  Byte offsets are 32-bit (buffers < 4 GiB).
-template <int LOG2N, bool GEN, int EG>
-__device__ __forceinline__ void load_tile(const LocalPass &P, const char *src, uint32_t orow, int tid, int nt,
-                                          int log2T, float2 (&v)[EG])
+__device__ __forceinline__ void copy_twiddles(float2 *twl, const float2 *stw, int n, int tid, int nt)
 {
+    for (int e = tid; e < n; e += nt) twl[e] = stw[e];  // first read after a barrier
+}
+
+// Generic pass: any descriptor, runtime tile width.
+template <int LOG2N, bool PRE, bool GEN>
+__global__ __launch_bounds__(1024) void local_fft_kernel(LocalPass P)
+{
+    constexpr int EG = LOG2N < 4 ? (1 << LOG2N) : 16;
     constexpr int LR0 = stage_log2radix(LOG2N, 0);
     constexpr int R0 = 1 << LR0;
     constexpr int NB0 = EG / R0;
     constexpr int LNR0 = LOG2N - LR0;
+    constexpr int TWN = stage_tw_total(LOG2N);
+    extern __shared__ float2 smem[];
+    const int log2T = P.log2T;
     const int Tm = (1 << log2T) - 1;
-    const uint32_t ld8 = uint32_t(P.ld) * 8u, j_in = uint32_t(P.j_in);
+    const int tid = threadIdx.x, nt = blockDim.x;
+    float2 *twl = smem;
+    float2 *lds = smem + ((TWN + 63) & ~63);
+
+    const int64_t ntc = P.ncols >> log2T;
+    const int64_t tile = tile_order(blockIdx.x, gridDim.x);
+    const int64_t o = tile / ntc;
+    const int64_t col0 = (tile - o * ntc) << log2T;
+    const char *src = reinterpret_cast<const char *>(P.src + col0);
+    const uint32_t orow = uint32_t(o * P.o_in), ld8 = uint32_t(P.ld) * 8u, j_in = uint32_t(P.j_in);
+
+    float2 v[EG];
 #pragma unroll
     for (int q = 0; q < NB0; ++q) {
         const int g = tid + q * nt;
@@ -215,48 +269,21 @@ __device__ __forceinline__ void load_tile(const LocalPass &P, const char *src, u
             v[q * R0 + r] = *reinterpret_cast<const float2 *>(src + ((orow + m * j_in) * ld8 + uint32_t(t) * 8u));
         }
     }
-}
-
-template <int LOG2N, bool GEN, int EG>
-__device__ __forceinline__ void pre_twiddle(const LocalPass &P, int64_t o, int tid, int nt, int log2T,
-                                            float2 (&v)[EG])
-{
-    constexpr int LR0 = stage_log2radix(LOG2N, 0);
-    constexpr int R0 = 1 << LR0;
-    constexpr int NB0 = EG / R0;
-    constexpr int LNR0 = LOG2N - LR0;
-    const int64_t f = digrev<GEN>(o, P.tw_t, P.tw_ell);
-    const int64_t Mm = (int64_t(1) << P.log2M) - 1;
-    const int shM = P.log2L - P.log2M;
+    // the stage twiddle table is copied after the data loads are issued, so
+    // waiting for it does not delay them
+    copy_twiddles(twl, P.stw, TWN, tid, nt);
+    if constexpr (PRE) {
+        const int64_t f = digrev<GEN>(o, P.tw_t, P.tw_ell);
+        const int64_t Mm = (int64_t(1) << P.log2M) - 1;
+        const int shM = P.log2L - P.log2M;
 #pragma unroll
-    for (int q = 0; q < NB0; ++q) {
-        const int j = (tid + q * nt) >> log2T;
+        for (int q = 0; q < NB0; ++q) {
+            const int j = (tid + q * nt) >> log2T;
 #pragma unroll
-        for (int r = 0; r < R0; ++r) v[q * R0 + r] = cmul(v[q * R0 + r], P.tw[((f * (j + (r << LNR0))) & Mm) << shM]);
+            for (int r = 0; r < R0; ++r)
+                v[q * R0 + r] = cmul(v[q * R0 + r], P.tw[((f * (j + (r << LNR0))) & Mm) << shM]);
+        }
     }
-}
-
-// One tile per workgroup.
-template <int LOG2N, bool PRE, bool GEN, int EG>
-__global__ __launch_bounds__(1024) void local_fft_kernel(LocalPass P)
-{
-    constexpr int TWN = stage_tw_total(LOG2N);
-    extern __shared__ float2 smem[];
-    const int log2T = P.log2T;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    float2 *twl = smem;
-    float2 *lds = smem + ((TWN + 63) & ~63);
-    for (int e = tid; e < TWN; e += nt) twl[e] = P.stw[e];  // first read after a barrier
-
-    const int64_t ntc = P.ncols >> log2T;
-    const int64_t tile = tile_order(blockIdx.x, gridDim.x, gridDim.x);
-    const int64_t o = tile / ntc;
-    const int64_t col0 = (tile - o * ntc) << log2T;
-
-    float2 v[EG];
-    load_tile<LOG2N, GEN, EG>(P, reinterpret_cast<const char *>(P.src + col0), uint32_t(o * P.o_in), tid, nt,
-                              log2T, v);
-    if constexpr (PRE) pre_twiddle<LOG2N, GEN, EG>(P, o, tid, nt, log2T, v);
     Ctx c;
     c.lds = lds;
     c.twl = twl;
@@ -264,83 +291,76 @@ __global__ __launch_bounds__(1024) void local_fft_kernel(LocalPass P)
     c.nt = nt;
     c.log2T = log2T;
     c.dst = reinterpret_cast<char *>(P.dst + col0);
-    c.ld8 = uint32_t(P.ld) * 8u;
+    c.ld8 = ld8;
     c.orow_out = uint32_t(o * P.o_out);
     c.k_out = uint32_t(P.k_out);
     c.out_t = P.out_t;
     c.out_ell = P.out_ell;
-    run_stage<LOG2N, 0, GEN, EG>(v, c);
+    run_stage<LOG2N, 0, EG, -1, -1, 1, GEN>(v, c);
 }
 
-// Persistent workgroups with a one-tile register prefetch (no pre-twiddle).
-template <int LOG2N, bool GEN>
-__global__ __launch_bounds__(512) void local_fft_persistent_kernel(LocalPass P)
+// Fast single-pass kernel.  MODE 0: natural input rows, digit-reversed
+// output rows (Phase I, A = P_pi Omega).  MODE 1: digit-reversed input rows,
+// natural output rows (Phase III, B = Omega P_pi).  b = 2^TB.
+template <int LOG2N, int MODE, int TB>
+__global__ __launch_bounds__(1024) void local_fft_fast_kernel(LocalPass P)
 {
-    constexpr int EG = 32;
+    constexpr int EG = LOG2N < 4 ? (1 << LOG2N) : 16;
+    constexpr int LT = fast_log2T(LOG2N);
+    constexpr int NT = (1 << (LOG2N + LT)) / EG;
+    constexpr int LR0 = stage_log2radix(LOG2N, 0);
+    constexpr int R0 = 1 << LR0;
+    constexpr int NB0 = EG / R0;
+    constexpr int LNR0 = LOG2N - LR0;
     constexpr int TWN = stage_tw_total(LOG2N);
     extern __shared__ float2 smem[];
-    const int log2T = P.log2T;
-    const int nt = blockDim.x;
+    const int tid = threadIdx.x;
     float2 *twl = smem;
     float2 *lds = smem + ((TWN + 63) & ~63);
-    for (int e = threadIdx.x; e < TWN; e += nt) twl[e] = P.stw[e];
 
-    const int64_t ntc = P.ncols >> log2T;
-    const int64_t G = P.n_outer * ntc;
-    const int64_t grid = gridDim.x;
-    int64_t i = blockIdx.x;
-    if (i >= G) return;
+    const int64_t col0 = tile_order(blockIdx.x, gridDim.x) << LT;
+    const char *src = reinterpret_cast<const char *>(P.src + col0);
+    const uint32_t ld8 = uint32_t(P.ld) * 8u;
 
-    float2 cur[EG], nxt[EG];
-    {
-        const int64_t tile = tile_order(i, G, grid);
-        const int64_t o = tile / ntc, col0 = (tile - o * ntc) << log2T;
-        load_tile<LOG2N, GEN, EG>(P, reinterpret_cast<const char *>(P.src + col0), uint32_t(o * P.o_in),
-                                  threadIdx.x, nt, log2T, cur);
-    }
-    for (; i < G; i += grid) {
-        // An opaque copy of the thread index per tile keeps thread-invariant
-        // addresses and twiddles from being hoisted out of the loop and held
-        // in registers across it.
-        int tid = threadIdx.x;
-        asm volatile("" : "+v"(tid));
-        const int64_t tile = tile_order(i, G, grid);
-        const int64_t o = tile / ntc, col0 = (tile - o * ntc) << log2T;
-        if (i + grid < G) {
-            const int64_t tn = tile_order(i + grid, G, grid);
-            const int64_t on = tn / ntc, cn = (tn - on * ntc) << log2T;
-            load_tile<LOG2N, GEN, EG>(P, reinterpret_cast<const char *>(P.src + cn), uint32_t(on * P.o_in), tid, nt,
-                                      log2T, nxt);
-        }
-        if (i != blockIdx.x) __syncthreads();  // the previous tile's last LDS reads are done
-        Ctx c;
-        c.lds = lds;
-        c.twl = twl;
-        c.tid = tid;
-        c.nt = nt;
-        c.log2T = log2T;
-        c.dst = reinterpret_cast<char *>(P.dst + col0);
-        c.ld8 = uint32_t(P.ld) * 8u;
-        c.orow_out = uint32_t(o * P.o_out);
-        c.k_out = uint32_t(P.k_out);
-        c.out_t = P.out_t;
-        c.out_ell = P.out_ell;
-        run_stage<LOG2N, 0, GEN, EG>(cur, c);
+    float2 v[EG];
 #pragma unroll
-        for (int e = 0; e < EG; ++e) cur[e] = nxt[e];
+    for (int q = 0; q < NB0; ++q) {
+        const int g = tid + q * NT;
+        const int t = g & ((1 << LT) - 1), j = g >> LT;
+        if constexpr (MODE == 0) {
+            const uint32_t base = uint32_t(j) * ld8 + uint32_t(t) * 8u;
+#pragma unroll
+            for (int r = 0; r < R0; ++r)
+                v[q * R0 + r] = *reinterpret_cast<const float2 *>(src + base + (uint32_t(r) << LNR0) * ld8);
+        } else {
+            // row pi(j + r*2^LNR0) = pi(j)*2^LR0 + pi(r)
+            const uint32_t base = (drev<TB, LNR0 / TB>(j) << LR0) * ld8 + uint32_t(t) * 8u;
+#pragma unroll
+            for (int r = 0; r < R0; ++r)
+                v[q * R0 + r] =
+                    *reinterpret_cast<const float2 *>(src + base + uint32_t(crev(r, TB, LR0 / TB)) * ld8);
+        }
     }
+    copy_twiddles(twl, P.stw, TWN, tid, NT);  // after the data loads are issued
+    Ctx c;
+    c.lds = lds;
+    c.twl = twl;
+    c.tid = tid;
+    c.nt = NT;
+    c.log2T = LT;
+    c.dst = reinterpret_cast<char *>(P.dst + col0);
+    c.ld8 = ld8;
+    c.orow_out = 0;
+    c.k_out = 1;
+    c.out_t = 0;
+    c.out_ell = 0;
+    run_stage<LOG2N, 0, EG, LT, MODE, TB, false>(v, c);
 }
 
 template <int L, bool PRE, bool GEN>
 const void *kptr()
 {
-    return reinterpret_cast<const void *>(&local_fft_kernel<L, PRE, GEN, (L < 4 ? (1 << L) : 16)>);
-}
-
-template <int L, bool GEN>
-const void *pptr()
-{
-    return reinterpret_cast<const void *>(&local_fft_persistent_kernel<L, GEN>);
+    return reinterpret_cast<const void *>(&local_fft_kernel<L, PRE, GEN>);
 }
 
 template <bool PRE, bool GEN>
@@ -363,21 +383,46 @@ const void *kernel_for_pre(int log2n)
     }
 }
 
-template <bool GEN>
-const void *persistent_for(int log2n)
+template <int L, int TB>
+const void *fast_for_tb(int mode)
 {
-    switch (log2n) {
-    case 9: return pptr<9, GEN>();
-    case 10: return pptr<10, GEN>();
-    case 11: return pptr<11, GEN>();
-    case 12: return pptr<12, GEN>();
+    if constexpr (L % TB != 0) {
+        return nullptr;
+    } else {
+        return mode == 0 ? reinterpret_cast<const void *>(&local_fft_fast_kernel<L, 0, TB>)
+                         : reinterpret_cast<const void *>(&local_fft_fast_kernel<L, 1, TB>);
+    }
+}
+
+template <int L>
+const void *fast_for_len(int mode, int tb)
+{
+    switch (tb) {
+    case 1: return fast_for_tb<L, 1>(mode);
+    case 2: return fast_for_tb<L, 2>(mode);
+    case 4: return fast_for_tb<L, 4>(mode);
     default: return nullptr;
     }
 }
 
-const void *kernel_for(int log2n, bool pre, bool gen, bool persist)
+const void *fast_kernel(int log2n, int mode, int tb)
 {
-    if (persist) return pre ? nullptr : (gen ? persistent_for<true>(log2n) : persistent_for<false>(log2n));
+    switch (log2n) {
+    case 4: return fast_for_len<4>(mode, tb);
+    case 5: return fast_for_len<5>(mode, tb);
+    case 6: return fast_for_len<6>(mode, tb);
+    case 7: return fast_for_len<7>(mode, tb);
+    case 8: return fast_for_len<8>(mode, tb);
+    case 9: return fast_for_len<9>(mode, tb);
+    case 10: return fast_for_len<10>(mode, tb);
+    case 11: return fast_for_len<11>(mode, tb);
+    case 12: return fast_for_len<12>(mode, tb);
+    default: return nullptr;
+    }
+}
+
+const void *kernel_for(int log2n, bool pre, bool gen)
+{
     if (gen) return pre ? kernel_for_pre<true, true>(log2n) : kernel_for_pre<false, true>(log2n);
     return pre ? kernel_for_pre<true, false>(log2n) : kernel_for_pre<false, false>(log2n);
 }
@@ -401,11 +446,21 @@ int32_t choose_log2T(int32_t log2n, int64_t ncols)
     return lt < lc ? lt : lc;
 }
 
-bool local_fft_has_persistent(int32_t log2n) { return kernel_for(log2n, false, false, true) != nullptr; }
+int32_t local_fft_fast_mode(const LocalPass &p)
+{
+    // single-pass Phase I (pi on output rows) or Phase III (pi on input rows)
+    if (p.pre_tw || p.n_outer != 1 || p.o_in || p.o_out || p.j_in != 1 || p.k_out != 1) return -1;
+    if (p.log2T != fast_log2T(p.log2n)) return -1;
+    int mode = -1, tb = 0;
+    if (p.out_ell && !p.in_ell) { mode = 0; tb = p.out_t; }
+    if (p.in_ell && !p.out_ell) { mode = 1; tb = p.in_t; }
+    if (mode < 0 || !fast_kernel(p.log2n, mode, tb)) return -1;
+    return mode;
+}
 
 LocalLaunch local_fft_geometry(const LocalPass &p)
 {
-    const int EG = p.persist ? 32 : (p.log2n < 4 ? (1 << p.log2n) : 16);
+    const int EG = p.log2n < 4 ? (1 << p.log2n) : 16;
     const int64_t items = int64_t(1) << (p.log2n + p.log2T);
     const int64_t twn = (stage_tw_total(p.log2n) + 63) & ~63;
     LocalLaunch g;
@@ -418,36 +473,32 @@ LocalLaunch local_fft_geometry(const LocalPass &p)
 hipError_t local_fft_prepare()
 {
     for (int l = 1; l <= kMaxOnChipLog2; ++l) {
-        for (int v = 0; v < 8; ++v) {
-            const void *k = kernel_for(l, v & 1, v & 2, v & 4);
-            if (!k) continue;
-            hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        for (int v = 0; v < 4; ++v) {
+            hipError_t e = hipFuncSetAttribute(kernel_for(l, v & 1, v & 2), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               160 * 1024);
             if (e != hipSuccess) return e;
         }
+        for (int mode = 0; mode < 2; ++mode)
+            for (int tb : {1, 2, 4}) {
+                const void *k = fast_kernel(l, mode, tb);
+                if (!k) continue;
+                hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                if (e != hipSuccess) return e;
+            }
     }
     return hipSuccess;
 }
 
-int local_fft_occupancy(const LocalPass &p)
-{
-    const void *k = kernel_for(p.log2n, p.pre_tw != 0, pass_needs_gen(p), p.persist != 0);
-    if (!k) return 0;
-    const LocalLaunch g = local_fft_geometry(p);
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, g.threads, g.lds_bytes) != hipSuccess) return 0;
-    return nb;
-}
-
 hipError_t launch_local_fft(const LocalPass &p, hipStream_t s)
 {
-    const void *k = kernel_for(p.log2n, p.pre_tw != 0, pass_needs_gen(p), p.persist != 0);
+    const int mode = p.no_fast ? -1 : local_fft_fast_mode(p);
+    const void *k = mode >= 0 ? fast_kernel(p.log2n, mode, mode == 0 ? p.out_t : p.in_t)
+                              : kernel_for(p.log2n, p.pre_tw != 0, pass_needs_gen(p));
     if (!k) return hipErrorInvalidValue;
     const LocalLaunch g = local_fft_geometry(p);
     if (g.tiles < 1 || g.tiles > 0x7fffffff) return hipErrorInvalidValue;
-    int64_t grid = g.tiles;
-    if (p.persist && p.grid > 0 && p.grid < grid) grid = p.grid;
     void *args[] = {const_cast<LocalPass *>(&p)};
-    return hipLaunchKernel(k, dim3(unsigned(grid)), dim3(unsigned(g.threads)), args, g.lds_bytes, s);
+    return hipLaunchKernel(k, dim3(unsigned(g.tiles)), dim3(unsigned(g.threads)), args, g.lds_bytes, s);
 }
 
 }  // namespace paco

@@ -32,13 +32,15 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b)
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-template <bool GEN>
+// FULL: N1, N2 >= 64, every tile is 64 x 64 (no guards).  TW: apply the
+// twiddle (else the bare permutation).
+template <bool GEN, bool FULL, bool TW>
 __global__ __launch_bounds__(kThreads) void middle_kernel(MiddlePass P)
 {
     __shared__ float2 tile[kMidTile * (kMidTile + 1)];
     __shared__ float2 rowtw[kMidTile];
-    const int lTV = P.N1 < kMidTile ? __builtin_ctzll(P.N1) : 6;
-    const int lTC = P.N2 < kMidTile ? __builtin_ctzll(P.N2) : 6;
+    const int lTV = FULL ? 6 : (P.N1 < kMidTile ? __builtin_ctzll(P.N1) : 6);
+    const int lTC = FULL ? 6 : (P.N2 < kMidTile ? __builtin_ctzll(P.N2) : 6);
     const int TV = 1 << lTV, TC = 1 << lTC;
     const int64_t nct = P.N2 >> lTC;
     const int64_t vt = blockIdx.x / nct;
@@ -57,14 +59,14 @@ __global__ __launch_bounds__(kThreads) void middle_kernel(MiddlePass P)
 #pragma unroll
     for (int q = 0; q < kPerThread; ++q) {
         const int vi = rg + q * rstep;
-        if (vi < TV) {
+        if (FULL || vi < TV) {
             const int64_t a = digrev<GEN>(v0 + vi, P.t, P.m1);
             x[q] = P.ws[a * P.N2 + c];
-            if (P.twiddle) t4[q] = P.tw_tile[vi * TC + ci];
+            if (TW) t4[q] = P.tw_tile[vi * TC + ci];
         }
     }
     float2 wc = make_float2(1.f, 0.f);
-    if (P.twiddle) {
+    if (TW) {
         const int64_t r = (v0 * c) & Nm;
         wc = cmul(P.tw_hi[r >> P.log2Lo], P.tw_lo[r & Lm]);
         if (tid < TV) {
@@ -76,9 +78,9 @@ __global__ __launch_bounds__(kThreads) void middle_kernel(MiddlePass P)
 #pragma unroll
     for (int q = 0; q < kPerThread; ++q) {
         const int vi = rg + q * rstep;
-        if (vi < TV) {
+        if (FULL || vi < TV) {
             float2 y = x[q];
-            if (P.twiddle) y = cmul(y, cmul(cmul(wc, rowtw[vi]), t4[q]));
+            if (TW) y = cmul(y, cmul(cmul(wc, rowtw[vi]), t4[q]));
             tile[ci * (kMidTile + 1) + vi] = y;
         }
     }
@@ -90,7 +92,7 @@ __global__ __launch_bounds__(kThreads) void middle_kernel(MiddlePass P)
 #pragma unroll
     for (int q = 0; q < kPerThread; ++q) {
         const int cj = cg + q * cstep;
-        if (cj < TC) {
+        if (FULL || cj < TC) {
             const int64_t u = digrev<GEN>(c0 + cj, P.t, P.m2);
             P.out[u * P.N1 + v0 + vi] = tile[cj * (kMidTile + 1) + vi];
         }
@@ -103,10 +105,15 @@ hipError_t launch_middle(const MiddlePass &p, hipStream_t s)
 {
     const int64_t TV = p.N1 < kMidTile ? p.N1 : kMidTile, TC = p.N2 < kMidTile ? p.N2 : kMidTile;
     const int64_t groups = (p.N1 / TV) * (p.N2 / TC);
-    if (digrev_fast(p.t))
-        hipLaunchKernelGGL(middle_kernel<false>, dim3(unsigned(groups)), dim3(kThreads), 0, s, p);
+    const bool full = p.N1 >= kMidTile && p.N2 >= kMidTile, tw = p.twiddle != 0;
+    void (*k)(MiddlePass);
+    if (!digrev_fast(p.t))
+        k = tw ? middle_kernel<true, false, true> : middle_kernel<true, false, false>;
+    else if (full)
+        k = tw ? middle_kernel<false, true, true> : middle_kernel<false, true, false>;
     else
-        hipLaunchKernelGGL(middle_kernel<true>, dim3(unsigned(groups)), dim3(kThreads), 0, s, p);
+        k = tw ? middle_kernel<false, false, true> : middle_kernel<false, false, false>;
+    hipLaunchKernelGGL(k, dim3(unsigned(groups)), dim3(kThreads), 0, s, p);
     return hipGetLastError();
 }
 

@@ -118,8 +118,7 @@ struct LocalPass {
     int32_t pre_tw;        // 0: none; 1: w_M^{-f(o) j} before the DFT
     int32_t log2M;         // M of the pre-twiddle (M <= L)
     int32_t tw_t, tw_ell;  // f(o) = pi_tw(o)
-    int32_t persist;       // 1: persistent 512-thread workgroups with register prefetch
-    int32_t grid;          // persistent launch: workgroups resident at once
+    int32_t no_fast;       // 1: always use the generic kernel (testing)
 };
 
 // Phase II: out[pi2(c)*N1 + v] = ws[pi1(v)*N2 + c] * w_N^{-(v*c mod N)}, the
@@ -156,9 +155,8 @@ hipError_t launch_middle(const MiddlePass &p, hipStream_t s);
 
 // Columns per workgroup for an on-chip pass of length 2^log2n over ncols.
 int32_t choose_log2T(int32_t log2n, int64_t ncols);
-// Whether the persistent kernel exists for this length.
-bool local_fft_has_persistent(int32_t log2n);
-// Workgroups of this pass one CU holds at once (0 on error).
-int local_fft_occupancy(const LocalPass &p);
+// Fast-kernel mode of a pass: 0 (Phase I rows), 1 (Phase III rows) or -1
+// when the pass needs the generic kernel.
+int32_t local_fft_fast_mode(const LocalPass &p);
 
 }  // namespace paco

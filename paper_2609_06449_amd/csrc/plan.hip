@@ -221,16 +221,11 @@ paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p
         q.ncols = ncols;
         q.log2n = log2n;
         q.log2T = paco::choose_log2T(log2n, ncols);
-        // Long transforms: persistent workgroups with register prefetch.
-        const char *pe = std::getenv("PACO_PERSIST");
-        if (!(pe && pe[0] == '0') && paco::local_fft_has_persistent(log2n) && (int64_t(1) << (14 - log2n)) <= ncols) {
-            q.persist = 1;
-            q.log2T = 14 - log2n;  // 2^14 items per tile
-        }
+        if (const char *nf = std::getenv("PACO_NO_FAST")) q.no_fast = nf[0] == '1';
         // tuning knob: columns per workgroup for long single-group transforms
         if (const char *ev = std::getenv("PACO_LOG2T_LONG")) {
             const int want = std::atoi(ev);
-            if (!q.persist && log2n >= 10 && want >= 0 && (int64_t(1) << want) <= ncols) q.log2T = want;
+            if (log2n >= 10 && want >= 0 && (int64_t(1) << want) <= ncols) q.log2T = want;
         }
         q.stw = d_stw + stw_off[log2n];
         q.tw = d_tw;
@@ -309,16 +304,9 @@ paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p
         P->phase3.push_back(A);
         P->phase3.push_back(B);
     }
-    int ncu = 0;
-    e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, P->device);
-    if (e != hipSuccess || ncu < 1) { (void)hipFree(P->dev_tables); delete P; return hip_fail(e, "hipDeviceGetAttribute"); }
-    for (auto *ph : {&P->phase1, &P->phase3})
-        for (auto &q : *ph)
-            if (q.persist) q.grid = paco::local_fft_occupancy(q) * ncu;
     for (auto *ph : {&P->phase1, &P->phase3})
         for (const auto &q : *ph)
-            if (paco::local_fft_geometry(q).lds_bytes > 160 * 1024 || paco::local_fft_geometry(q).threads > 1024 ||
-                (q.persist && q.grid < 1)) {
+            if (paco::local_fft_geometry(q).lds_bytes > 160 * 1024 || paco::local_fft_geometry(q).threads > 1024) {
                 (void)hipFree(P->dev_tables);
                 delete P;
                 return fail(PACO_ERR_UNSUPPORTED, "local FFT tile does not fit one workgroup");
@@ -343,7 +331,8 @@ paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p
         for (const auto &q : *ph) {
             const paco::LocalLaunch g = paco::local_fft_geometry(q);
             std::snprintf(buf, sizeof buf, " n=2^%d T=%d%s outer=%lld wg=%lld thr=%d lds=%zu", q.log2n, 1 << q.log2T,
-                          q.persist ? "(persistent)" : "", (long long)q.n_outer, (long long)g.tiles, g.threads, g.lds_bytes);
+                          (!q.no_fast && paco::local_fft_fast_mode(q) >= 0) ? "(fast)" : "", (long long)q.n_outer,
+                          (long long)g.tiles, g.threads, g.lds_bytes);
             desc += buf;
         }
         desc += " ]";

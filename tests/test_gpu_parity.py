@@ -244,3 +244,22 @@ def test_c3_full_size_sampled(name):
     yk = oracle.dft_at(x, ks)
     rms_y = np.sqrt(ex)            # mean |y|^2 = ||x||^2 by Parseval
     assert np.max(np.abs(y[ks] - yk)) < 1e-5 * rms_y
+
+
+@pytest.mark.parametrize("N1,N2,p,b", [(4096, 4096, 64, 16), (64, 64, 4, 4), (1024, 256, 4, 2), (256, 65536 // 256, 4, 16)])
+def test_fast_and_generic_kernels_agree(N1, N2, p, b):
+    # the fast single-pass kernels do the same arithmetic in the same order as
+    # the generic descriptor-driven kernel: outputs must match bit for bit
+    import os
+    x = _dev(inputs.normal(N1 * N2, seed=17))
+    fast = paco.Plan(N1, N2, p, b)
+    assert "(fast)" in fast.description
+    os.environ["PACO_NO_FAST"] = "1"
+    try:
+        generic = paco.Plan(N1, N2, p, b)
+    finally:
+        del os.environ["PACO_NO_FAST"]
+    assert "(fast)" not in generic.description
+    a = _host(_run(fast, x))
+    g = _host(_run(generic, x))
+    assert np.array_equal(a.view(np.uint64), g.view(np.uint64))
