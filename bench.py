@@ -124,13 +124,15 @@ def main():
     gflops = 5.0 * N * math.log2(N) / (ms_per_step * 1e-3) / 1e9
 
     # ---- per-phase durations with HIP events on the same stream ------------
+    # the same launches paco_execute makes, one phase per call
+    fl = paco.PACO_PACKED if plan.description.startswith("fused") else 0
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     for i in range(args.steps):
         e = ev[i]
         e[0].record(stream)
-        plan.execute_stage(1, xd.data_ptr(), ws.data_ptr(), sh)
+        plan.execute_stage(1, xd.data_ptr(), ws.data_ptr(), sh, fl)
         e[1].record(stream)
-        plan.execute_stage(2, ws.data_ptr(), out.data_ptr(), sh)
+        plan.execute_stage(2, ws.data_ptr(), out.data_ptr(), sh, fl)
         e[2].record(stream)
         plan.execute_stage(3, out.data_ptr(), out.data_ptr(), sh)
         e[3].record(stream)
@@ -165,7 +167,11 @@ def main():
     y = out.cpu().numpy()
 
     # the dominant kernel: the slowest of the three phases (each one launch)
-    names = ["phase1 local_fft_kernel<12>", "phase2 middle_kernel", "phase3 local_fft_kernel<12>"]
+    if fl:
+        names = ["phase1 local_fft_fast_kernel<12,2,1>", "phase2 middle_packed_kernel",
+                 "phase3 local_fft_fast_kernel<12,1,4>"]
+    else:
+        names = ["phase1 local_fft_fast_kernel<12,0,4>", "phase2 middle_kernel", "phase3 local_fft_fast_kernel<12,1,4>"]
     dom = int(np.argmax(ph_us))
     alg_bytes = 16.0 * N  # each phase reads and writes N complex64 items once
     achieved = alg_bytes / (ph_us[dom] * 1e-6) / 1e9

@@ -64,6 +64,7 @@ typedef enum {
 
 /* paco_execute_stage flags */
 #define PACO_NO_TWIDDLE 1       /* stage 2 only: apply the bare permutation pi_m */
+#define PACO_PACKED 2           /* stages 1, 2: the fused pipeline's Phase-I buffer (below) */
 
 typedef struct paco_plan_s paco_plan;
 
@@ -87,17 +88,35 @@ paco_status paco_plan_workspace_size(const paco_plan *plan, size_t *bytes);
 
 /* Runs Phase I (in -> workspace), Phase II (workspace -> out) and Phase III
  * (out -> out, in place) on `stream` (a hipStream_t; NULL = default stream).
- * in == out is allowed.  in, out and workspace are device pointers, 8-byte
- * aligned, of N1*N2 complex64 each (workspace: at least the reported size). */
+ * in == out is allowed.  in, out and workspace are device pointers, 16-byte
+ * aligned (kernels move two complex64 items per 16-byte access), of N1*N2 complex64 each (workspace: at least the reported size).
+ *
+ * Workspace layout.  With the paper's layouts (section 4.2) the workspace
+ * holds the Phase-I buffer Atilde[a, c] = A[pi_{m1}(a), c] and Phase II packs
+ * (rows a -> v = pi_{m1}(a)), exchanges, transposes and unpacks.  When the
+ * plan is "fused" (single-pass Phase I, N1, N2 >= 64, b in {2, 4, 16}) the
+ * pack and the block transpose move into Phase I's store: pi_{m1} composed
+ * with itself is the identity (appendix A.1), so the packed slab holds
+ * frequency k1 at row k1, and Phase I writes it transposed,
+ *     workspace[c*N1 + k1] = A[k1, c]   (the "packed" buffer),
+ * with contiguous runs on both sides of every HBM pass but Phase I's reads and
+ * Phase III's writes.  Phase II is then the unpack (rows c -> pi_{m2}(c)) with
+ * the top-level twiddle.  paco_plan_describe names the mode; the environment
+ * variable PACO_LAYOUT=paper at plan creation selects the paper's layouts. */
 paco_status paco_execute(const paco_plan *plan, const void *in, void *out, void *workspace,
                          size_t workspace_bytes, void *stream);
 
-/* Runs one phase alone, for stage-wise checks and per-phase timing:
- *   stage 1: src (N1 x N2, x) -> dst (N1 x N2, Phase-I layout Atilde)
- *   stage 2: src (N1 x N2, Atilde) -> dst (N2 x N1, Zhat); flags may hold
- *            PACO_NO_TWIDDLE; src and dst must not overlap
+/* Runs one phase alone, for stage-wise checks and per-phase timing, always
+ * in the paper's layouts unless flags holds PACO_PACKED:
+ *   stage 1: src (N1 x N2, x) -> dst (N1 x N2, Phase-I layout Atilde);
+ *            PACO_PACKED: dst = the packed buffer dst[c*N1 + k1] = A[k1, c]
+ *            (src and dst must differ)
+ *   stage 2: src (N1 x N2, Atilde; PACO_PACKED: the packed buffer) -> dst
+ *            (N2 x N1, Zhat); flags may also hold PACO_NO_TWIDDLE; src and
+ *            dst must not overlap
  *   stage 3: src (N2 x N1, Zhat) -> dst (N2 x N1, Y); src == dst allowed
- * Stage 1 also allows src == dst. */
+ * Stage 1 also allows src == dst.  PACO_PACKED on a plan that is not fused
+ * returns PACO_ERR_UNSUPPORTED. */
 paco_status paco_execute_stage(const paco_plan *plan, int stage, int flags, const void *src,
                                void *dst, void *stream);
 

@@ -129,12 +129,16 @@ struct Ctx {
     int out_t, out_ell;
 };
 
-// Stage S of the Stockham sequence.  v[i*R + r] is operand r of butterfly i;
-// butterfly id g = tid + i*nt covers column g mod T and index j = g / T.
-// LT >= 0: compile-time log2 T.  MODE: -1 generic output rows, 0 digit-
-// reversed output rows (Phase I), 1 natural output rows (Phase III).
-template <int LOG2N, int S, int EG, int LT, int MODE, int TB, bool GEN>
-__device__ __forceinline__ void run_stage(float2 (&v)[EG], const Ctx &c)
+// Stage S of the Stockham sequence on H column groups.  v[h*EG + i*R + r]
+// is operand r of butterfly i of group h; butterfly id g = tid + i*nt of a
+// group covers column g mod TG and index j = g / TG (TG columns per group);
+// between stages the groups take turns in LDS, which holds n x TG items.
+// LT >= 0: compile-time log2 TG.  MODE: -1 generic output rows, 0 digit-
+// reversed output rows (Phase I), 1 natural output rows (Phase III), 2 the
+// transposed natural output (row = column, n items per row; Phase I of the
+// fused pipeline).
+template <int LOG2N, int S, int EG, int LT, int MODE, int TB, bool GEN, int H>
+__device__ __forceinline__ void run_stage(float2 (&v)[H * EG], const Ctx &c)
 {
     constexpr int LR = stage_log2radix(LOG2N, S);
     constexpr int R = 1 << LR;
@@ -149,8 +153,8 @@ __device__ __forceinline__ void run_stage(float2 (&v)[EG], const Ctx &c)
     for (int i = 0; i < NB; ++i) {
         const int g = c.tid + i * nt;
         const int j = g >> log2T;
-        float2 *u = &v[i * R];
         if constexpr (LNS > 0) {
+            // the same twiddles serve every group (same j)
             constexpr int LOW = stage_lo_width(LOG2N, S);
             constexpr int HIW = stage_hi_width(LOG2N, S);
             constexpr int OFF = stage_tw_offset(LOG2N, S);
@@ -161,58 +165,96 @@ __device__ __forceinline__ void run_stage(float2 (&v)[EG], const Ctx &c)
             for (int r = 1; r < R; ++r) {
                 float2 w = tlo[(r - 1) * LOW];
                 if constexpr (HIW > 0) w = cmul(w, thi[(r - 1) * HIW]);
-                u[r] = cmul(u[r], w);
+#pragma unroll
+                for (int h = 0; h < H; ++h) v[h * EG + i * R + r] = cmul(v[h * EG + i * R + r], w);
             }
         }
-        dft_regs<LR>(u);
+#pragma unroll
+        for (int h = 0; h < H; ++h) dft_regs<LR>(&v[h * EG + i * R]);
     }
     if constexpr (!last) {
         constexpr int LR2 = stage_log2radix(LOG2N, S + 1);
         constexpr int R2 = 1 << LR2;
         constexpr int NB2 = EG / R2;
         constexpr int LNR2 = LOG2N - LR2;
-        if constexpr (S > 0) __syncthreads();  // all stage-S operands were read
 #pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            const int g = c.tid + i * nt;
-            const int t = g & Tm, j = g >> log2T;
-            const int idxD = ((j >> LNS) << (LNS + LR)) + (j & ((1 << LNS) - 1));
+        for (int h = 0; h < H; ++h) {
+            if (S > 0 || h > 0) __syncthreads();  // the previous LDS contents were consumed
 #pragma unroll
-            for (int r = 0; r < R; ++r) c.lds[lpad(((idxD + (r << LNS)) << log2T) + t)] = v[i * R + r];
+            for (int i = 0; i < NB; ++i) {
+                const int g = c.tid + i * nt;
+                const int t = g & Tm, j = g >> log2T;
+                const int idxD = ((j >> LNS) << (LNS + LR)) + (j & ((1 << LNS) - 1));
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    c.lds[lpad(((idxD + (r << LNS)) << log2T) + t)] = v[h * EG + i * R + r];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < NB2; ++i) {
+                const int g = c.tid + i * nt;
+                const int t = g & Tm, j = g >> log2T;
+#pragma unroll
+                for (int r = 0; r < R2; ++r)
+                    v[h * EG + i * R2 + r] = c.lds[lpad(((j + (r << LNR2)) << log2T) + t)];
+            }
         }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < NB2; ++i) {
-            const int g = c.tid + i * nt;
-            const int t = g & Tm, j = g >> log2T;
-#pragma unroll
-            for (int r = 0; r < R2; ++r) v[i * R2 + r] = c.lds[lpad(((j + (r << LNR2)) << log2T) + t)];
-        }
-        run_stage<LOG2N, S + 1, EG, LT, MODE, TB, GEN>(v, c);
+        run_stage<LOG2N, S + 1, EG, LT, MODE, TB, GEN, H>(v, c);
     } else {
-        // last stage: j < n/R = 2^LNS, outputs are the natural-order rows k = j + r*2^LNS
+        // last stage: j < n/R = 2^LNS, outputs are the natural-order rows k = j + r*2^LNS.
+        // With H = 2 the groups interleave: group h of tile column t holds
+        // column 2t + h, so one 16-byte store writes both groups' items.
+        if constexpr (H == 2 && (MODE == 0 || MODE == 1)) {
 #pragma unroll
-        for (int i = 0; i < NB; ++i) {
-            const int g = c.tid + i * nt;
-            const int t = g & Tm, j = g >> log2T;
-            if constexpr (MODE == 0) {
-                // row pi(k) = pi(j)*2^LR + pi(r)
-                const uint32_t base = ((drev<TB, LNS / TB>(j) << LR) * c.ld8) + uint32_t(t) * 8u;
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-                    *reinterpret_cast<float2 *>(c.dst + base + uint32_t(crev(r, TB, LR / TB)) * c.ld8) = v[i * R + r];
-            } else if constexpr (MODE == 1) {
-                const uint32_t base = uint32_t(j) * c.ld8 + uint32_t(t) * 8u;
-#pragma unroll
-                for (int r = 0; r < R; ++r)
-                    *reinterpret_cast<float2 *>(c.dst + base + (uint32_t(r) << LNS) * c.ld8) = v[i * R + r];
-            } else {
+            for (int i = 0; i < NB; ++i) {
+                const int g = c.tid + i * nt;
+                const int t = (g & Tm) << 1, j = g >> log2T;
+                uint32_t base;
+                if constexpr (MODE == 0)
+                    base = ((drev<TB, LNS / TB>(j) << LR) * c.ld8) + uint32_t(t) * 8u;
+                else
+                    base = uint32_t(j) * c.ld8 + uint32_t(t) * 8u;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const uint32_t k = j + (r << LNS);
-                    const uint32_t m = uint32_t(digrev<GEN>(k, c.out_t, c.out_ell));
-                    const uint32_t off = (c.orow_out + m * c.k_out) * c.ld8 + uint32_t(t) * 8u;
-                    *reinterpret_cast<float2 *>(c.dst + off) = v[i * R + r];
+                    const uint32_t row_off = MODE == 0 ? uint32_t(crev(r, TB, LR / TB)) * c.ld8 : (uint32_t(r) << LNS) * c.ld8;
+                    const float2 a0 = v[i * R + r], a1 = v[EG + i * R + r];
+                    *reinterpret_cast<float4 *>(c.dst + base + row_off) = make_float4(a0.x, a0.y, a1.x, a1.y);
+                }
+            }
+            return;
+        }
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                const int g = c.tid + i * nt;
+                const int t = H == 2 ? (((g & Tm) << 1) + h) : (g & Tm), j = g >> log2T;
+                const float2 *u = &v[h * EG + i * R];
+                if constexpr (MODE == 0) {
+                    // row pi(k) = pi(j)*2^LR + pi(r)
+                    const uint32_t base = ((drev<TB, LNS / TB>(j) << LR) * c.ld8) + uint32_t(t) * 8u;
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        *reinterpret_cast<float2 *>(c.dst + base + uint32_t(crev(r, TB, LR / TB)) * c.ld8) = u[r];
+                } else if constexpr (MODE == 2) {
+                    // transposed output: row (col0 + t) holds all n frequencies in order
+                    const uint32_t base = (uint32_t(t) << (LOG2N + 3)) + uint32_t(j) * 8u;
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        *reinterpret_cast<float2 *>(c.dst + base + (uint32_t(r) << (LNS + 3))) = u[r];
+                } else if constexpr (MODE == 1) {
+                    const uint32_t base = uint32_t(j) * c.ld8 + uint32_t(t) * 8u;
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        *reinterpret_cast<float2 *>(c.dst + base + (uint32_t(r) << LNS) * c.ld8) = u[r];
+                } else {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const uint32_t k = j + (r << LNS);
+                        const uint32_t m = uint32_t(digrev<GEN>(k, c.out_t, c.out_ell));
+                        const uint32_t off = (c.orow_out + m * c.k_out) * c.ld8 + uint32_t(t) * 8u;
+                        *reinterpret_cast<float2 *>(c.dst + off) = u[r];
+                    }
                 }
             }
         }
@@ -296,18 +338,27 @@ __global__ __launch_bounds__(1024) void local_fft_kernel(LocalPass P)
     c.k_out = uint32_t(P.k_out);
     c.out_t = P.out_t;
     c.out_ell = P.out_ell;
-    run_stage<LOG2N, 0, EG, -1, -1, 1, GEN>(v, c);
+    run_stage<LOG2N, 0, EG, -1, -1, 1, GEN, 1>(v, c);
 }
 
 // Fast single-pass kernel.  MODE 0: natural input rows, digit-reversed
 // output rows (Phase I, A = P_pi Omega).  MODE 1: digit-reversed input rows,
-// natural output rows (Phase III, B = Omega P_pi).  b = 2^TB.
-template <int LOG2N, int MODE, int TB>
-__global__ __launch_bounds__(1024) void local_fft_fast_kernel(LocalPass P)
+// natural output rows (Phase III, B = Omega P_pi).  MODE 2: natural input
+// rows, output written transposed in natural frequency order (Phase I of the
+// fused pipeline: Lemma 1's output layout composed with the pack step's row
+// reversal is the identity, so the packed slab holds frequency k1 at k1).
+// b = 2^TB.  H = 2 splits the T columns into two LDS groups: half the LDS
+// per workgroup, so two workgroups share a CU and overlap each other's HBM
+// traffic and arithmetic.
+constexpr int fast_threads(int l, int h) { return (1 << (l + fast_log2T(l))) / (h * (l < 4 ? (1 << l) : 16)); }
+
+template <int LOG2N, int MODE, int TB, int H>
+__global__ __launch_bounds__(fast_threads(LOG2N, H)) void local_fft_fast_kernel(LocalPass P)
 {
     constexpr int EG = LOG2N < 4 ? (1 << LOG2N) : 16;
-    constexpr int LT = fast_log2T(LOG2N);
-    constexpr int NT = (1 << (LOG2N + LT)) / EG;
+    constexpr int LT = fast_log2T(LOG2N);          // log2 of all columns of the tile
+    constexpr int LTG = LT - (H == 2 ? 1 : 0);     // log2 of the columns of one group
+    constexpr int NT = (1 << (LOG2N + LTG)) / EG;
     constexpr int LR0 = stage_log2radix(LOG2N, 0);
     constexpr int R0 = 1 << LR0;
     constexpr int NB0 = EG / R0;
@@ -322,23 +373,29 @@ __global__ __launch_bounds__(1024) void local_fft_fast_kernel(LocalPass P)
     const char *src = reinterpret_cast<const char *>(P.src + col0);
     const uint32_t ld8 = uint32_t(P.ld) * 8u;
 
-    float2 v[EG];
+    // H = 2: group h of tile column t is column 2t + h, and one 16-byte load
+    // fetches both groups' items of a row
+    float2 v[H * EG];
 #pragma unroll
     for (int q = 0; q < NB0; ++q) {
         const int g = tid + q * NT;
-        const int t = g & ((1 << LT) - 1), j = g >> LT;
-        if constexpr (MODE == 0) {
-            const uint32_t base = uint32_t(j) * ld8 + uint32_t(t) * 8u;
+        const int t = (g & ((1 << LTG) - 1)) * H, j = g >> LTG;
+        uint32_t base;
+        if constexpr (MODE == 0 || MODE == 2)
+            base = uint32_t(j) * ld8 + uint32_t(t) * 8u;
+        else  // row pi(j + r*2^LNR0) = pi(j)*2^LR0 + pi(r)
+            base = (drev<TB, LNR0 / TB>(j) << LR0) * ld8 + uint32_t(t) * 8u;
 #pragma unroll
-            for (int r = 0; r < R0; ++r)
-                v[q * R0 + r] = *reinterpret_cast<const float2 *>(src + base + (uint32_t(r) << LNR0) * ld8);
-        } else {
-            // row pi(j + r*2^LNR0) = pi(j)*2^LR0 + pi(r)
-            const uint32_t base = (drev<TB, LNR0 / TB>(j) << LR0) * ld8 + uint32_t(t) * 8u;
-#pragma unroll
-            for (int r = 0; r < R0; ++r)
-                v[q * R0 + r] =
-                    *reinterpret_cast<const float2 *>(src + base + uint32_t(crev(r, TB, LR0 / TB)) * ld8);
+        for (int r = 0; r < R0; ++r) {
+            const uint32_t row_off =
+                (MODE == 0 || MODE == 2) ? (uint32_t(r) << LNR0) * ld8 : uint32_t(crev(r, TB, LR0 / TB)) * ld8;
+            if constexpr (H == 2) {
+                const float4 a = *reinterpret_cast<const float4 *>(src + base + row_off);
+                v[q * R0 + r] = make_float2(a.x, a.y);
+                v[EG + q * R0 + r] = make_float2(a.z, a.w);
+            } else {
+                v[q * R0 + r] = *reinterpret_cast<const float2 *>(src + base + row_off);
+            }
         }
     }
     copy_twiddles(twl, P.stw, TWN, tid, NT);  // after the data loads are issued
@@ -347,14 +404,14 @@ __global__ __launch_bounds__(1024) void local_fft_fast_kernel(LocalPass P)
     c.twl = twl;
     c.tid = tid;
     c.nt = NT;
-    c.log2T = LT;
-    c.dst = reinterpret_cast<char *>(P.dst + col0);
+    c.log2T = LTG;
+    c.dst = reinterpret_cast<char *>(MODE == 2 ? P.dst + (col0 << LOG2N) : P.dst + col0);
     c.ld8 = ld8;
     c.orow_out = 0;
     c.k_out = 1;
     c.out_t = 0;
     c.out_ell = 0;
-    run_stage<LOG2N, 0, EG, LT, MODE, TB, false>(v, c);
+    run_stage<LOG2N, 0, EG, LTG, MODE, TB, false, H>(v, c);
 }
 
 template <int L, bool PRE, bool GEN>
@@ -383,42 +440,49 @@ const void *kernel_for_pre(int log2n)
     }
 }
 
-template <int L, int TB>
+template <int L, int TB, int H>
 const void *fast_for_tb(int mode)
 {
-    if constexpr (L % TB != 0) {
+    if constexpr (L % TB != 0 || (H == 2 && L < 10)) {
         return nullptr;
     } else {
-        return mode == 0 ? reinterpret_cast<const void *>(&local_fft_fast_kernel<L, 0, TB>)
-                         : reinterpret_cast<const void *>(&local_fft_fast_kernel<L, 1, TB>);
+        if (mode == 2) return TB == 1 ? reinterpret_cast<const void *>(&local_fft_fast_kernel<L, 2, 1, H>) : nullptr;
+        return mode == 0 ? reinterpret_cast<const void *>(&local_fft_fast_kernel<L, 0, TB, H>)
+                         : reinterpret_cast<const void *>(&local_fft_fast_kernel<L, 1, TB, H>);
     }
 }
 
-template <int L>
+template <int L, int H>
 const void *fast_for_len(int mode, int tb)
 {
     switch (tb) {
-    case 1: return fast_for_tb<L, 1>(mode);
-    case 2: return fast_for_tb<L, 2>(mode);
-    case 4: return fast_for_tb<L, 4>(mode);
+    case 1: return fast_for_tb<L, 1, H>(mode);
+    case 2: return fast_for_tb<L, 2, H>(mode);
+    case 4: return fast_for_tb<L, 4, H>(mode);
     default: return nullptr;
     }
 }
 
-const void *fast_kernel(int log2n, int mode, int tb)
+template <int H>
+const void *fast_kernel_h(int log2n, int mode, int tb)
 {
     switch (log2n) {
-    case 4: return fast_for_len<4>(mode, tb);
-    case 5: return fast_for_len<5>(mode, tb);
-    case 6: return fast_for_len<6>(mode, tb);
-    case 7: return fast_for_len<7>(mode, tb);
-    case 8: return fast_for_len<8>(mode, tb);
-    case 9: return fast_for_len<9>(mode, tb);
-    case 10: return fast_for_len<10>(mode, tb);
-    case 11: return fast_for_len<11>(mode, tb);
-    case 12: return fast_for_len<12>(mode, tb);
+    case 4: return fast_for_len<4, H>(mode, tb);
+    case 5: return fast_for_len<5, H>(mode, tb);
+    case 6: return fast_for_len<6, H>(mode, tb);
+    case 7: return fast_for_len<7, H>(mode, tb);
+    case 8: return fast_for_len<8, H>(mode, tb);
+    case 9: return fast_for_len<9, H>(mode, tb);
+    case 10: return fast_for_len<10, H>(mode, tb);
+    case 11: return fast_for_len<11, H>(mode, tb);
+    case 12: return fast_for_len<12, H>(mode, tb);
     default: return nullptr;
     }
+}
+
+const void *fast_kernel(int log2n, int mode, int tb, int groups)
+{
+    return groups == 2 ? fast_kernel_h<2>(log2n, mode, tb) : fast_kernel_h<1>(log2n, mode, tb);
 }
 
 const void *kernel_for(int log2n, bool pre, bool gen)
@@ -452,16 +516,23 @@ int32_t local_fft_fast_mode(const LocalPass &p)
     if (p.pre_tw || p.n_outer != 1 || p.o_in || p.o_out || p.j_in != 1 || p.k_out != 1) return -1;
     if (p.log2T != fast_log2T(p.log2n)) return -1;
     int mode = -1, tb = 0;
-    if (p.out_ell && !p.in_ell) { mode = 0; tb = p.out_t; }
-    if (p.in_ell && !p.out_ell) { mode = 1; tb = p.in_t; }
-    if (mode < 0 || !fast_kernel(p.log2n, mode, tb)) return -1;
+    if (p.out_tr) {
+        if (p.in_ell || p.out_ell) return -1;
+        mode = 2;
+        tb = 1;
+    } else {
+        if (p.out_ell && !p.in_ell) { mode = 0; tb = p.out_t; }
+        if (p.in_ell && !p.out_ell) { mode = 1; tb = p.in_t; }
+    }
+    if (mode < 0 || !fast_kernel(p.log2n, mode, tb, p.groups)) return -1;
     return mode;
 }
 
 LocalLaunch local_fft_geometry(const LocalPass &p)
 {
     const int EG = p.log2n < 4 ? (1 << p.log2n) : 16;
-    const int64_t items = int64_t(1) << (p.log2n + p.log2T);
+    const bool grouped = p.groups == 2 && !p.no_fast && local_fft_fast_mode(p) >= 0;
+    const int64_t items = int64_t(1) << (p.log2n + p.log2T - (grouped ? 1 : 0));  // one LDS group
     const int64_t twn = (stage_tw_total(p.log2n) + 63) & ~63;
     LocalLaunch g;
     g.threads = int(items / EG);
@@ -478,9 +549,10 @@ hipError_t local_fft_prepare()
                                                160 * 1024);
             if (e != hipSuccess) return e;
         }
-        for (int mode = 0; mode < 2; ++mode)
-            for (int tb : {1, 2, 4}) {
-                const void *k = fast_kernel(l, mode, tb);
+        for (int mode = 0; mode < 3; ++mode)
+            for (int tb : {1, 2, 4})
+                for (int grp : {1, 2}) {
+                const void *k = fast_kernel(l, mode, tb, grp);
                 if (!k) continue;
                 hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
                 if (e != hipSuccess) return e;
@@ -492,7 +564,7 @@ hipError_t local_fft_prepare()
 hipError_t launch_local_fft(const LocalPass &p, hipStream_t s)
 {
     const int mode = p.no_fast ? -1 : local_fft_fast_mode(p);
-    const void *k = mode >= 0 ? fast_kernel(p.log2n, mode, mode == 0 ? p.out_t : p.in_t)
+    const void *k = mode >= 0 ? fast_kernel(p.log2n, mode, mode == 2 ? 1 : (mode == 0 ? p.out_t : p.in_t), p.groups)
                               : kernel_for(p.log2n, p.pre_tw != 0, pass_needs_gen(p));
     if (!k) return hipErrorInvalidValue;
     const LocalLaunch g = local_fft_geometry(p);

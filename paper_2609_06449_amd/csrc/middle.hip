@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kThreads) void middle_kernel(MiddlePass P)
         if (FULL || vi < TV) {
             const int64_t a = digrev<GEN>(v0 + vi, P.t, P.m1);
             x[q] = P.ws[a * P.N2 + c];
-            if (TW) t4[q] = P.tw_tile[vi * TC + ci];
+            if (TW) t4[q] = P.tw_tile[vi * kMidTile + ci];
         }
     }
     float2 wc = make_float2(1.f, 0.f);
@@ -99,10 +99,67 @@ __global__ __launch_bounds__(kThreads) void middle_kernel(MiddlePass P)
     }
 }
 
+// Fused-pipeline variant: ws is the packed slab stored transposed,
+// ws[c*N1 + v] = A[v, c] with v the logical first-stage frequency (the pack
+// step's row reversal already undone by Phase I's store).  What remains of
+// the redistribution is the unpack (row c -> u = pi_{m2}(c)) with the
+// twiddle w_N^{-v c}: a streaming row permutation.  A workgroup owns 64 rows
+// c x 64 columns v; wave w takes rows c0 + w + 4q, lane = column, so every
+// load and store is a 512-byte run and the row index, its digit reversal
+// and the per-row twiddle factor are wave-uniform (scalar) values.
+template <bool GEN, bool TW>
+__global__ __launch_bounds__(kThreads) void middle_packed_kernel(MiddlePass P)
+{
+    const int64_t nvt = P.N1 >> 6;
+    const int64_t ct = blockIdx.x / nvt;
+    const int64_t vt = blockIdx.x - ct * nvt;
+    const int64_t v0 = vt << 6, c0 = ct << 6;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t Nm = (int64_t(1) << P.log2N) - 1;
+    const int64_t Lm = (int64_t(1) << P.log2Lo) - 1;
+
+    float2 rw = make_float2(1.f, 0.f);  // w_N^{-vi c0}
+    if (TW) {
+        const int64_t r = (int64_t(lane) * c0) & Nm;
+        rw = cmul(P.tw_hi[r >> P.log2Lo], P.tw_lo[r & Lm]);
+    }
+    float2 x[kPerThread], t4[kPerThread];
+#pragma unroll
+    for (int q = 0; q < kPerThread; ++q) {
+        const int ci = w + 4 * q;
+        x[q] = P.ws[(c0 + ci) * P.N1 + v0 + lane];
+        if (TW) t4[q] = P.tw_tile[ci * kMidTile + lane];
+    }
+#pragma unroll
+    for (int q = 0; q < kPerThread; ++q) {
+        const int64_t c = c0 + w + 4 * q;
+        const int64_t u = digrev<GEN>(c, P.t, P.m2);
+        float2 y = x[q];
+        if (TW) {
+            const int64_t r = (v0 * c) & Nm;  // w_N^{-v0 c}: one value per row
+            const float2 wc = cmul(P.tw_hi[r >> P.log2Lo], P.tw_lo[r & Lm]);
+            y = cmul(y, cmul(wc, cmul(rw, t4[q])));
+        }
+        P.out[u * P.N1 + v0 + lane] = y;
+    }
+}
+
 }  // namespace
 
 hipError_t launch_middle(const MiddlePass &p, hipStream_t s)
 {
+    if (p.packed) {
+        if (p.N1 < kMidTile || p.N2 < kMidTile) return hipErrorInvalidValue;
+        const int64_t groups = (p.N1 / kMidTile) * (p.N2 / kMidTile);
+        void (*k)(MiddlePass);
+        if (digrev_fast(p.t))
+            k = p.twiddle ? middle_packed_kernel<false, true> : middle_packed_kernel<false, false>;
+        else
+            k = p.twiddle ? middle_packed_kernel<true, true> : middle_packed_kernel<true, false>;
+        hipLaunchKernelGGL(k, dim3(unsigned(groups)), dim3(kThreads), 0, s, p);
+        return hipGetLastError();
+    }
     const int64_t TV = p.N1 < kMidTile ? p.N1 : kMidTile, TC = p.N2 < kMidTile ? p.N2 : kMidTile;
     const int64_t groups = (p.N1 / TV) * (p.N2 / TC);
     const bool full = p.N1 >= kMidTile && p.N2 >= kMidTile, tw = p.twiddle != 0;

@@ -119,6 +119,8 @@ struct LocalPass {
     int32_t log2M;         // M of the pre-twiddle (M <= L)
     int32_t tw_t, tw_ell;  // f(o) = pi_tw(o)
     int32_t no_fast;       // 1: always use the generic kernel (testing)
+    int32_t out_tr;        // 1: write the output transposed (row = column, n items; fast kernel only)
+    int32_t groups;        // fast kernel: 1, or 2 column groups taking turns in LDS
 };
 
 // Phase II: out[pi2(c)*N1 + v] = ws[pi1(v)*N2 + c] * w_N^{-(v*c mod N)}, the
@@ -126,7 +128,8 @@ struct LocalPass {
 // v = v0 + vi and c = c0 + ci inside a TV x TC tile,
 //   w_N^{-v c} = w_N^{-v0 c} * w_N^{-vi c0} * w_N^{-vi ci}
 // the first factor per thread (tw_hi/tw_lo two-level table), the second per
-// tile row, the third from a fixed TV x TC table (tw_tile).
+// tile row, the third from a fixed 64 x 64 table (tw_tile, symmetric,
+// [i*64 + j] = w_N^{-(i*j mod N)}).
 struct MiddlePass {
     const float2 *ws;
     float2 *out;
@@ -134,9 +137,10 @@ struct MiddlePass {
     int32_t t, m1, m2;        // b = 2^t, N1 = b^m1, N2 = b^m2
     const float2 *tw_hi;      // w_N^{-h*Lo}, h < N/Lo
     const float2 *tw_lo;      // w_N^{-l}, l < Lo
-    const float2 *tw_tile;    // [vi][ci] = w_N^{-(vi*ci mod N)}, TV x TC
+    const float2 *tw_tile;    // [i*64 + j] = w_N^{-(i*j mod N)}, i, j < 64
     int32_t log2N, log2Lo;
     int32_t twiddle;          // 0: bare permutation
+    int32_t packed;           // 1: ws is the transposed natural buffer ws[c*N1 + v] = A[v, c]
 };
 
 constexpr int kMidTile = 64;
@@ -155,8 +159,8 @@ hipError_t launch_middle(const MiddlePass &p, hipStream_t s);
 
 // Columns per workgroup for an on-chip pass of length 2^log2n over ncols.
 int32_t choose_log2T(int32_t log2n, int64_t ncols);
-// Fast-kernel mode of a pass: 0 (Phase I rows), 1 (Phase III rows) or -1
-// when the pass needs the generic kernel.
+// Fast-kernel mode of a pass: 0 (Phase I rows), 1 (Phase III rows), 2
+// (transposed natural output) or -1 when the pass needs the generic kernel.
 int32_t local_fft_fast_mode(const LocalPass &p);
 
 }  // namespace paco

@@ -61,6 +61,8 @@ struct paco_plan_s {
     void *dev_tables = nullptr;
     std::vector<LocalPass> phase1, phase3;  // src/dst filled per execution
     MiddlePass mid{};
+    bool fused = false;                     // packed Phase-I buffer (see paco_execute)
+    LocalPass phase1_packed{};
     std::string desc;
 };
 
@@ -160,13 +162,13 @@ paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p
     // ---- host tables (FP64-generated, rounded once to FP32) ----------------
     const int64_t N = int64_t(1) << P->lN;
     const int64_t L = int64_t(1) << P->lL, Lo = int64_t(1) << P->lLo, Hi = N >> P->lLo;
-    const int64_t TV = N1 < paco::kMidTile ? N1 : paco::kMidTile, TC = N2 < paco::kMidTile ? N2 : paco::kMidTile;
-    std::vector<float2> tw(L), thi(Hi), tlo(Lo), ttile(TV * TC);
+    constexpr int64_t TT = paco::kMidTile;
+    std::vector<float2> tw(L), thi(Hi), tlo(Lo), ttile(TT * TT);
     for (int64_t r = 0; r < L; ++r) tw[r] = root_neg(r, L);
     for (int64_t h = 0; h < Hi; ++h) thi[h] = root_neg(h * Lo, N);
     for (int64_t l = 0; l < Lo; ++l) tlo[l] = root_neg(l, N);
-    for (int64_t vi = 0; vi < TV; ++vi)
-        for (int64_t ci = 0; ci < TC; ++ci) ttile[vi * TC + ci] = root_neg((vi * ci) % N, N);
+    for (int64_t i = 0; i < TT; ++i)
+        for (int64_t j = 0; j < TT; ++j) ttile[i * TT + j] = root_neg((i * j) % N, N);
     // stage twiddle factor tables of every on-chip length 2^1 .. 2^12
     std::vector<float2> stw;
     int64_t stw_off[paco::kMaxOnChipLog2 + 1] = {0};
@@ -222,6 +224,7 @@ paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p
         q.log2n = log2n;
         q.log2T = paco::choose_log2T(log2n, ncols);
         if (const char *nf = std::getenv("PACO_NO_FAST")) q.no_fast = nf[0] == '1';
+        q.groups = 1;
         // tuning knob: columns per workgroup for long single-group transforms
         if (const char *ev = std::getenv("PACO_LOG2T_LONG")) {
             const int want = std::atoi(ev);
@@ -311,6 +314,33 @@ paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p
                 delete P;
                 return fail(PACO_ERR_UNSUPPORTED, "local FFT tile does not fit one workgroup");
             }
+    // Two LDS column groups (two workgroups per CU) for n = 2^12 in Phase I,
+    // where they measured faster; one group in Phase III.  Tuning knobs:
+    // PACO_GROUPS1 / PACO_GROUPS3 = 1 or 2.
+    {
+        auto pick = [](LocalPass &q, const char *env, int dflt) {
+            int g = dflt;
+            if (const char *e = std::getenv(env)) g = e[0] == '2' ? 2 : 1;
+            if (q.log2n < 10 || q.log2T < 1) g = 1;
+            q.groups = g;
+        };
+        for (auto &q : P->phase1) pick(q, "PACO_GROUPS1", q.log2n >= 12 ? 2 : 1);
+        for (auto &q : P->phase3) pick(q, "PACO_GROUPS3", 1);
+    }
+    // ---- fused pipeline: Phase I writes the packed slab transposed --------
+    {
+        const char *lay = std::getenv("PACO_LAYOUT");
+        const bool want = !(lay && std::strcmp(lay, "paper") == 0);
+        LocalPass q = P->phase1[0];
+        q.out_tr = 1;
+        q.out_t = 0;
+        q.out_ell = 0;
+        if (want && b1 == 0 && N1 >= paco::kMidTile && N2 >= paco::kMidTile && !q.no_fast &&
+            paco::local_fft_fast_mode(q) == 2) {
+            P->fused = true;
+            P->phase1_packed = q;
+        }
+    }
     // ---- Phase II ---------------------------------------------------------
     P->mid.N1 = N1;
     P->mid.N2 = N2;
@@ -337,6 +367,7 @@ paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p
         }
         desc += " ]";
     }
+    if (P->fused) desc = "fused[phase1 -> packed transposed slab, phase2 row unpack+twiddle] " + desc;
     P->desc = desc;
     *plan = P;
     return PACO_OK;
@@ -374,7 +405,7 @@ paco_status paco_plan_destroy(paco_plan *plan)
 
 namespace {
 
-bool bad_ptr(const void *p) { return !p || (reinterpret_cast<uintptr_t>(p) & 7); }
+bool bad_ptr(const void *p) { return !p || (reinterpret_cast<uintptr_t>(p) & 15); }
 
 paco_status run_local(const std::vector<LocalPass> &passes, const void *src, void *dst, hipStream_t s)
 {
@@ -388,12 +419,13 @@ paco_status run_local(const std::vector<LocalPass> &passes, const void *src, voi
     return PACO_OK;
 }
 
-paco_status run_middle(const paco_plan *plan, const void *src, void *dst, int twiddle, hipStream_t s)
+paco_status run_middle(const paco_plan *plan, const void *src, void *dst, int twiddle, bool packed, hipStream_t s)
 {
     MiddlePass m = plan->mid;
     m.ws = static_cast<const float2 *>(src);
     m.out = static_cast<float2 *>(dst);
     m.twiddle = twiddle;
+    m.packed = packed ? 1 : 0;
     hipError_t e = paco::launch_middle(m, s);
     if (e != hipSuccess) return hip_fail(e, "phase II launch");
     return PACO_OK;
@@ -408,7 +440,7 @@ paco_status paco_execute(const paco_plan *plan, const void *in, void *out, void 
 {
     if (!plan) return fail(PACO_ERR_INVALID_ARG, "plan is NULL");
     if (bad_ptr(in) || bad_ptr(out) || bad_ptr(workspace))
-        return fail(PACO_ERR_INVALID_ARG, "in/out/workspace must be non-NULL and 8-byte aligned");
+        return fail(PACO_ERR_INVALID_ARG, "in/out/workspace must be non-NULL and 16-byte aligned");
     const size_t need = size_t(plan->N1) * size_t(plan->N2) * 8;
     if (workspace_bytes < need) return fail(PACO_ERR_WORKSPACE, "workspace smaller than N1*N2*8 bytes");
     const size_t wb = reinterpret_cast<uintptr_t>(workspace), ib = reinterpret_cast<uintptr_t>(in),
@@ -416,9 +448,10 @@ paco_status paco_execute(const paco_plan *plan, const void *in, void *out, void 
     if ((wb < ib + need && ib < wb + need) || (wb < ob + need && ob < wb + need))
         return fail(PACO_ERR_INVALID_ARG, "workspace overlaps in or out");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    paco_status st = run_local(plan->phase1, in, workspace, s);
+    paco_status st = plan->fused ? run_local({plan->phase1_packed}, in, workspace, s)
+                                 : run_local(plan->phase1, in, workspace, s);
     if (st != PACO_OK) return st;
-    st = run_middle(plan, workspace, out, 1, s);
+    st = run_middle(plan, workspace, out, 1, plan->fused, s);
     if (st != PACO_OK) return st;
     return run_local(plan->phase3, out, out, s);
 }
@@ -427,16 +460,22 @@ paco_status paco_execute_stage(const paco_plan *plan, int stage, int flags, cons
                                void *stream)
 {
     if (!plan) return fail(PACO_ERR_INVALID_ARG, "plan is NULL");
-    if (bad_ptr(src) || bad_ptr(dst)) return fail(PACO_ERR_INVALID_ARG, "src/dst must be non-NULL and 8-byte aligned");
-    if (flags & ~PACO_NO_TWIDDLE) return fail(PACO_ERR_INVALID_ARG, "unknown flags");
+    if (bad_ptr(src) || bad_ptr(dst)) return fail(PACO_ERR_INVALID_ARG, "src/dst must be non-NULL and 16-byte aligned");
+    if (flags & ~(PACO_NO_TWIDDLE | PACO_PACKED)) return fail(PACO_ERR_INVALID_ARG, "unknown flags");
+    const bool packed = (flags & PACO_PACKED) != 0;
+    if (packed && !plan->fused) return fail(PACO_ERR_UNSUPPORTED, "this plan has no packed Phase-I buffer");
+    if (packed && stage == 3) return fail(PACO_ERR_INVALID_ARG, "PACO_PACKED applies to stages 1 and 2");
     hipStream_t s = static_cast<hipStream_t>(stream);
     switch (stage) {
-    case 1: return run_local(plan->phase1, src, dst, s);
+    case 1: {
+        if (packed && src == dst) return fail(PACO_ERR_INVALID_ARG, "packed stage 1 is out of place");
+        return packed ? run_local({plan->phase1_packed}, src, dst, s) : run_local(plan->phase1, src, dst, s);
+    }
     case 2: {
         const size_t need = size_t(plan->N1) * size_t(plan->N2) * 8;
         const uintptr_t a = reinterpret_cast<uintptr_t>(src), b = reinterpret_cast<uintptr_t>(dst);
         if (a < b + need && b < a + need) return fail(PACO_ERR_INVALID_ARG, "stage 2 src and dst overlap");
-        return run_middle(plan, src, dst, (flags & PACO_NO_TWIDDLE) ? 0 : 1, s);
+        return run_middle(plan, src, dst, (flags & PACO_NO_TWIDDLE) ? 0 : 1, packed, s);
     }
     case 3: return run_local(plan->phase3, src, dst, s);
     default: return fail(PACO_ERR_INVALID_ARG, "stage must be 1, 2 or 3");

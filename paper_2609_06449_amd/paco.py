@@ -24,6 +24,7 @@ PACO_ERR_HIP = 7
 PACO_C64 = 0
 
 PACO_NO_TWIDDLE = 1
+PACO_PACKED = 2
 
 # every symbol include/paco.h declares
 EXPORTED = (

@@ -252,14 +252,72 @@ def test_fast_and_generic_kernels_agree(N1, N2, p, b):
     # the generic descriptor-driven kernel: outputs must match bit for bit
     import os
     x = _dev(inputs.normal(N1 * N2, seed=17))
-    fast = paco.Plan(N1, N2, p, b)
-    assert "(fast)" in fast.description
-    os.environ["PACO_NO_FAST"] = "1"
+    os.environ["PACO_LAYOUT"] = "paper"
     try:
+        fast = paco.Plan(N1, N2, p, b)
+        os.environ["PACO_NO_FAST"] = "1"
         generic = paco.Plan(N1, N2, p, b)
     finally:
-        del os.environ["PACO_NO_FAST"]
+        os.environ.pop("PACO_NO_FAST", None)
+        del os.environ["PACO_LAYOUT"]
+    assert "(fast)" in fast.description
     assert "(fast)" not in generic.description
     a = _host(_run(fast, x))
     g = _host(_run(generic, x))
     assert np.array_equal(a.view(np.uint64), g.view(np.uint64))
+
+
+def _paper_plan(N1, N2, p, b):
+    import os
+    os.environ["PACO_LAYOUT"] = "paper"
+    try:
+        return paco.Plan(N1, N2, p, b)
+    finally:
+        del os.environ["PACO_LAYOUT"]
+
+
+@pytest.mark.parametrize("N1,N2,p,b", [(64, 64, 4, 4), (4096, 256, 16, 16), (256, 4096, 4, 16), (1024, 2048, 8, 2)])
+def test_fused_and_paper_layouts_both_match_oracle(N1, N2, p, b):
+    x = inputs.normal(N1 * N2, seed=18)
+    ref = oracle.dft(x)
+    fused = paco.Plan(N1, N2, p, b)
+    paper = _paper_plan(N1, N2, p, b)
+    assert fused.description.startswith("fused") and not paper.description.startswith("fused")
+    for plan in (fused, paper):
+        assert oracle.rel_l2(_host(_run(plan, _dev(x))), ref) <= TOL
+
+
+@pytest.mark.parametrize("N1,N2,p,b", [(64, 64, 4, 4), (4096, 512, 8, 2), (256, 4096, 4, 16)])
+def test_packed_stage_buffers(N1, N2, p, b):
+    # stage 1 (packed): buf[c*N1 + k1] = A[k1, c], the natural column DFTs
+    x = inputs.normal(N1 * N2, seed=19)
+    plan = paco.Plan(N1, N2, p, b)
+    s1 = _host(_stage(plan, 1, _dev(x), flags=paco.PACO_PACKED)).reshape(N2, N1)
+    t = b.bit_length() - 1
+    m1 = round(np.log2(N1)) // t
+    pi1 = np.array([oracle.digit_reverse(a, b, m1) for a in range(N1)])
+    At = oracle.phase1(x, N1, N2, b)          # Atilde[a, c] = A[pi1(a), c]
+    A = np.empty_like(At)
+    A[pi1, :] = At                            # A[k1, c]
+    assert oracle.rel_l2(s1, A.T) <= TOL
+    # stage 2 (packed, no twiddle) on a seeded buffer W[c, v] taken as the
+    # packed slab: a pure permutation, bit exact against the oracle's
+    # permutation applied to the equivalent paper-layout buffer
+    W = inputs.normal(N1 * N2, seed=20).reshape(N2, N1)
+    got = _host(_stage(plan, 2, _dev(W), flags=paco.PACO_PACKED | paco.PACO_NO_TWIDDLE))
+    Atilde = W.T[pi1, :]                      # Atilde[a, c] = A[pi1(a), c] = W[c, pi1(a)]
+    want = oracle.phase2(Atilde, N1, N2, b, twiddle=False).astype(np.complex64).ravel()
+    assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+    # and with the twiddle, against the oracle's fused middle stage
+    got = _host(_stage(plan, 2, _dev(W), flags=paco.PACO_PACKED)).astype(np.complex128)
+    want = oracle.phase2(Atilde, N1, N2, b, twiddle=True).ravel()
+    assert oracle.rel_l2(got, want) < 3e-7
+
+
+def test_packed_flag_rejected_on_paper_plan():
+    plan = _paper_plan(64, 64, 4, 4)
+    buf = torch.empty(4096, dtype=torch.complex64, device="cuda")
+    ws = torch.empty(4096, dtype=torch.complex64, device="cuda")
+    lib = paco.lib()
+    s = torch.cuda.current_stream().cuda_stream
+    assert lib.paco_execute_stage(plan.handle, 1, paco.PACO_PACKED, buf.data_ptr(), ws.data_ptr(), s) == paco.PACO_ERR_UNSUPPORTED
