@@ -167,11 +167,12 @@ def main():
     y = out.cpu().numpy()
 
     # the dominant kernel: the slowest of the three phases (each one launch)
-    if fl:
-        names = ["phase1 local_fft_fast_kernel<12,2,1>", "phase2 middle_packed_kernel",
-                 "phase3 local_fft_fast_kernel<12,1,4>"]
+    if fl:  # the kernels of the default (fused) plan for this workload
+        names = ["phase1 local_fft_fast_kernel<12,2,1,2,16>", "phase2 middle_packed2_kernel<false,true>",
+                 "phase3 local_fft_fast_kernel<12,1,4,2,32>"]
     else:
-        names = ["phase1 local_fft_fast_kernel<12,0,4>", "phase2 middle_kernel", "phase3 local_fft_fast_kernel<12,1,4>"]
+        names = ["phase1 local_fft_fast_kernel<12,0,4,2,16>", "phase2 middle_kernel<false,true,true>",
+                 "phase3 local_fft_fast_kernel<12,1,4,2,32>"]
     dom = int(np.argmax(ph_us))
     alg_bytes = 16.0 * N  # each phase reads and writes N complex64 items once
     achieved = alg_bytes / (ph_us[dom] * 1e-6) / 1e9

@@ -350,14 +350,19 @@ __global__ __launch_bounds__(1024) void local_fft_kernel(LocalPass P)
 // b = 2^TB.  H = 2 splits the T columns into two LDS groups: half the LDS
 // per workgroup, so two workgroups share a CU and overlap each other's HBM
 // traffic and arithmetic.
-constexpr int fast_threads(int l, int h) { return (1 << (l + fast_log2T(l))) / (h * (l < 4 ? (1 << l) : 16)); }
-
-template <int LOG2N, int MODE, int TB, int H>
-__global__ __launch_bounds__(fast_threads(LOG2N, H)) void local_fft_fast_kernel(LocalPass P)
+// EG = 32 (with H = 2) doubles the tile width: 512 threads hold 64 items
+// each (two waves per SIMD, 256 VGPRs of budget).
+constexpr int fast_tile_log2T(int l, int h, int eg) { return fast_log2T(l) + (h == 2 && eg == 32 ? 1 : 0); }
+constexpr int fast_threads(int l, int h, int eg)
 {
-    constexpr int EG = LOG2N < 4 ? (1 << LOG2N) : 16;
-    constexpr int LT = fast_log2T(LOG2N);          // log2 of all columns of the tile
-    constexpr int LTG = LT - (H == 2 ? 1 : 0);     // log2 of the columns of one group
+    return (1 << (l + fast_tile_log2T(l, h, eg))) / (h * eg);
+}
+
+template <int LOG2N, int MODE, int TB, int H, int EG>
+__global__ __launch_bounds__(fast_threads(LOG2N, H, EG)) void local_fft_fast_kernel(LocalPass P)
+{
+    constexpr int LT = fast_tile_log2T(LOG2N, H, EG);  // log2 of all columns of the tile
+    constexpr int LTG = LT - (H == 2 ? 1 : 0);         // log2 of the columns of one group
     constexpr int NT = (1 << (LOG2N + LTG)) / EG;
     constexpr int LR0 = stage_log2radix(LOG2N, 0);
     constexpr int R0 = 1 << LR0;
@@ -440,49 +445,53 @@ const void *kernel_for_pre(int log2n)
     }
 }
 
-template <int L, int TB, int H>
+template <int L, int TB, int H, int EG>
 const void *fast_for_tb(int mode)
 {
-    if constexpr (L % TB != 0 || (H == 2 && L < 10)) {
+    if constexpr (L % TB != 0 || (H == 2 && L < 10) || (L < 4 && EG != (1 << L)) || (L >= 4 && EG < 16) ||
+                  (EG == 32 && H != 2)) {
         return nullptr;
     } else {
-        if (mode == 2) return TB == 1 ? reinterpret_cast<const void *>(&local_fft_fast_kernel<L, 2, 1, H>) : nullptr;
-        return mode == 0 ? reinterpret_cast<const void *>(&local_fft_fast_kernel<L, 0, TB, H>)
-                         : reinterpret_cast<const void *>(&local_fft_fast_kernel<L, 1, TB, H>);
+        if (mode == 2) return TB == 1 ? reinterpret_cast<const void *>(&local_fft_fast_kernel<L, 2, 1, H, EG>) : nullptr;
+        return mode == 0 ? reinterpret_cast<const void *>(&local_fft_fast_kernel<L, 0, TB, H, EG>)
+                         : reinterpret_cast<const void *>(&local_fft_fast_kernel<L, 1, TB, H, EG>);
     }
 }
 
-template <int L, int H>
+template <int L, int H, int EG>
 const void *fast_for_len(int mode, int tb)
 {
     switch (tb) {
-    case 1: return fast_for_tb<L, 1, H>(mode);
-    case 2: return fast_for_tb<L, 2, H>(mode);
-    case 4: return fast_for_tb<L, 4, H>(mode);
+    case 1: return fast_for_tb<L, 1, H, EG>(mode);
+    case 2: return fast_for_tb<L, 2, H, EG>(mode);
+    case 4: return fast_for_tb<L, 4, H, EG>(mode);
     default: return nullptr;
     }
 }
 
-template <int H>
+template <int H, int EGW>
 const void *fast_kernel_h(int log2n, int mode, int tb)
 {
+    // EGW: 0 = the natural per-thread width min(16, n), 32 = wide
     switch (log2n) {
-    case 4: return fast_for_len<4, H>(mode, tb);
-    case 5: return fast_for_len<5, H>(mode, tb);
-    case 6: return fast_for_len<6, H>(mode, tb);
-    case 7: return fast_for_len<7, H>(mode, tb);
-    case 8: return fast_for_len<8, H>(mode, tb);
-    case 9: return fast_for_len<9, H>(mode, tb);
-    case 10: return fast_for_len<10, H>(mode, tb);
-    case 11: return fast_for_len<11, H>(mode, tb);
-    case 12: return fast_for_len<12, H>(mode, tb);
+    case 4: return fast_for_len<4, H, EGW ? EGW : 16>(mode, tb);
+    case 5: return fast_for_len<5, H, EGW ? EGW : 16>(mode, tb);
+    case 6: return fast_for_len<6, H, EGW ? EGW : 16>(mode, tb);
+    case 7: return fast_for_len<7, H, EGW ? EGW : 16>(mode, tb);
+    case 8: return fast_for_len<8, H, EGW ? EGW : 16>(mode, tb);
+    case 9: return fast_for_len<9, H, EGW ? EGW : 16>(mode, tb);
+    case 10: return fast_for_len<10, H, EGW ? EGW : 16>(mode, tb);
+    case 11: return fast_for_len<11, H, EGW ? EGW : 16>(mode, tb);
+    case 12: return fast_for_len<12, H, EGW ? EGW : 16>(mode, tb);
     default: return nullptr;
     }
 }
 
+// groups: 1, 2 (two 16-item groups) or 3 (two 32-item groups: tile twice as wide)
 const void *fast_kernel(int log2n, int mode, int tb, int groups)
 {
-    return groups == 2 ? fast_kernel_h<2>(log2n, mode, tb) : fast_kernel_h<1>(log2n, mode, tb);
+    if (groups == 3) return fast_kernel_h<2, 32>(log2n, mode, tb);
+    return groups == 2 ? fast_kernel_h<2, 0>(log2n, mode, tb) : fast_kernel_h<1, 0>(log2n, mode, tb);
 }
 
 const void *kernel_for(int log2n, bool pre, bool gen)
@@ -514,7 +523,7 @@ int32_t local_fft_fast_mode(const LocalPass &p)
 {
     // single-pass Phase I (pi on output rows) or Phase III (pi on input rows)
     if (p.pre_tw || p.n_outer != 1 || p.o_in || p.o_out || p.j_in != 1 || p.k_out != 1) return -1;
-    if (p.log2T != fast_log2T(p.log2n)) return -1;
+    if (p.log2T != fast_tile_log2T(p.log2n, p.groups >= 2 ? 2 : 1, p.groups == 3 ? 32 : 16)) return -1;
     int mode = -1, tb = 0;
     if (p.out_tr) {
         if (p.in_ell || p.out_ell) return -1;
@@ -530,8 +539,9 @@ int32_t local_fft_fast_mode(const LocalPass &p)
 
 LocalLaunch local_fft_geometry(const LocalPass &p)
 {
-    const int EG = p.log2n < 4 ? (1 << p.log2n) : 16;
-    const bool grouped = p.groups == 2 && !p.no_fast && local_fft_fast_mode(p) >= 0;
+    const bool fast = !p.no_fast && local_fft_fast_mode(p) >= 0;
+    const bool grouped = fast && p.groups >= 2;
+    const int EG = (fast && p.groups == 3) ? 32 : (p.log2n < 4 ? (1 << p.log2n) : 16);
     const int64_t items = int64_t(1) << (p.log2n + p.log2T - (grouped ? 1 : 0));  // one LDS group
     const int64_t twn = (stage_tw_total(p.log2n) + 63) & ~63;
     LocalLaunch g;
@@ -551,7 +561,7 @@ hipError_t local_fft_prepare()
         }
         for (int mode = 0; mode < 3; ++mode)
             for (int tb : {1, 2, 4})
-                for (int grp : {1, 2}) {
+                for (int grp : {1, 2, 3}) {
                 const void *k = fast_kernel(l, mode, tb, grp);
                 if (!k) continue;
                 hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);

@@ -62,7 +62,7 @@ __global__ __launch_bounds__(kThreads) void middle_kernel(MiddlePass P)
         if (FULL || vi < TV) {
             const int64_t a = digrev<GEN>(v0 + vi, P.t, P.m1);
             x[q] = P.ws[a * P.N2 + c];
-            if (TW) t4[q] = P.tw_tile[vi * kMidTile + ci];
+            if (TW) t4[q] = P.tw_tile[vi * kTwTile + ci];
         }
     }
     float2 wc = make_float2(1.f, 0.f);
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(kThreads) void middle_packed_kernel(MiddlePass P)
     for (int q = 0; q < kPerThread; ++q) {
         const int ci = w + 4 * q;
         x[q] = P.ws[(c0 + ci) * P.N1 + v0 + lane];
-        if (TW) t4[q] = P.tw_tile[ci * kMidTile + lane];
+        if (TW) t4[q] = P.tw_tile[ci * kTwTile + lane];
     }
 #pragma unroll
     for (int q = 0; q < kPerThread; ++q) {
@@ -145,10 +145,63 @@ __global__ __launch_bounds__(kThreads) void middle_packed_kernel(MiddlePass P)
     }
 }
 
+// The same with two adjacent columns per lane: a workgroup owns 64 rows x
+// 128 columns and every load and store is a 1 KB run of 16-byte accesses.
+template <bool GEN, bool TW>
+__global__ __launch_bounds__(kThreads) void middle_packed2_kernel(MiddlePass P)
+{
+    const int64_t nvt = P.N1 >> 7;
+    const int64_t ct = blockIdx.x / nvt;
+    const int64_t vt = blockIdx.x - ct * nvt;
+    const int64_t v0 = vt << 7, c0 = ct << 6;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t Nm = (int64_t(1) << P.log2N) - 1;
+    const int64_t Lm = (int64_t(1) << P.log2Lo) - 1;
+    const int vi = 2 * lane;
+
+    float2 rw0 = make_float2(1.f, 0.f), rw1 = rw0;  // w_N^{-vi c0}, w_N^{-(vi+1) c0}
+    if (TW) {
+        const int64_t r0 = (int64_t(vi) * c0) & Nm, r1 = (int64_t(vi + 1) * c0) & Nm;
+        rw0 = cmul(P.tw_hi[r0 >> P.log2Lo], P.tw_lo[r0 & Lm]);
+        rw1 = cmul(P.tw_hi[r1 >> P.log2Lo], P.tw_lo[r1 & Lm]);
+    }
+    float4 x[kPerThread], t4[kPerThread];
+#pragma unroll
+    for (int q = 0; q < kPerThread; ++q) {
+        const int ci = w + 4 * q;
+        x[q] = *reinterpret_cast<const float4 *>(P.ws + (c0 + ci) * P.N1 + v0 + vi);
+        if (TW) t4[q] = *reinterpret_cast<const float4 *>(P.tw_tile + ci * kTwTile + vi);
+    }
+#pragma unroll
+    for (int q = 0; q < kPerThread; ++q) {
+        const int64_t c = c0 + w + 4 * q;
+        const int64_t u = digrev<GEN>(c, P.t, P.m2);
+        float2 y0 = make_float2(x[q].x, x[q].y), y1 = make_float2(x[q].z, x[q].w);
+        if (TW) {
+            const int64_t r = (v0 * c) & Nm;  // w_N^{-v0 c}: one value per row
+            const float2 wc = cmul(P.tw_hi[r >> P.log2Lo], P.tw_lo[r & Lm]);
+            y0 = cmul(y0, cmul(wc, cmul(rw0, make_float2(t4[q].x, t4[q].y))));
+            y1 = cmul(y1, cmul(wc, cmul(rw1, make_float2(t4[q].z, t4[q].w))));
+        }
+        *reinterpret_cast<float4 *>(P.out + u * P.N1 + v0 + vi) = make_float4(y0.x, y0.y, y1.x, y1.y);
+    }
+}
+
 }  // namespace
 
 hipError_t launch_middle(const MiddlePass &p, hipStream_t s)
 {
+    if (p.packed && p.N1 >= 2 * kMidTile && p.N2 >= kMidTile) {
+        const int64_t groups = (p.N1 / (2 * kMidTile)) * (p.N2 / kMidTile);
+        void (*k)(MiddlePass);
+        if (digrev_fast(p.t))
+            k = p.twiddle ? middle_packed2_kernel<false, true> : middle_packed2_kernel<false, false>;
+        else
+            k = p.twiddle ? middle_packed2_kernel<true, true> : middle_packed2_kernel<true, false>;
+        hipLaunchKernelGGL(k, dim3(unsigned(groups)), dim3(kThreads), 0, s, p);
+        return hipGetLastError();
+    }
     if (p.packed) {
         if (p.N1 < kMidTile || p.N2 < kMidTile) return hipErrorInvalidValue;
         const int64_t groups = (p.N1 / kMidTile) * (p.N2 / kMidTile);

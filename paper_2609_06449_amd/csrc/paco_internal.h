@@ -128,8 +128,8 @@ struct LocalPass {
 // v = v0 + vi and c = c0 + ci inside a TV x TC tile,
 //   w_N^{-v c} = w_N^{-v0 c} * w_N^{-vi c0} * w_N^{-vi ci}
 // the first factor per thread (tw_hi/tw_lo two-level table), the second per
-// tile row, the third from a fixed 64 x 64 table (tw_tile, symmetric,
-// [i*64 + j] = w_N^{-(i*j mod N)}).
+// tile row, the third from a fixed 128 x 128 table (tw_tile, symmetric,
+// [i*128 + j] = w_N^{-(i*j mod N)}).
 struct MiddlePass {
     const float2 *ws;
     float2 *out;
@@ -137,13 +137,14 @@ struct MiddlePass {
     int32_t t, m1, m2;        // b = 2^t, N1 = b^m1, N2 = b^m2
     const float2 *tw_hi;      // w_N^{-h*Lo}, h < N/Lo
     const float2 *tw_lo;      // w_N^{-l}, l < Lo
-    const float2 *tw_tile;    // [i*64 + j] = w_N^{-(i*j mod N)}, i, j < 64
+    const float2 *tw_tile;    // [i*128 + j] = w_N^{-(i*j mod N)}, i, j < 128
     int32_t log2N, log2Lo;
     int32_t twiddle;          // 0: bare permutation
     int32_t packed;           // 1: ws is the transposed natural buffer ws[c*N1 + v] = A[v, c]
 };
 
 constexpr int kMidTile = 64;
+constexpr int kTwTile = 128;  // tile-twiddle table side: [i*128 + j] = w_N^{-(i*j mod N)}
 
 // Workgroup geometry a local pass is launched with.
 struct LocalLaunch {

@@ -162,7 +162,7 @@ paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p
     // ---- host tables (FP64-generated, rounded once to FP32) ----------------
     const int64_t N = int64_t(1) << P->lN;
     const int64_t L = int64_t(1) << P->lL, Lo = int64_t(1) << P->lLo, Hi = N >> P->lLo;
-    constexpr int64_t TT = paco::kMidTile;
+    constexpr int64_t TT = paco::kTwTile;
     std::vector<float2> tw(L), thi(Hi), tlo(Lo), ttile(TT * TT);
     for (int64_t r = 0; r < L; ++r) tw[r] = root_neg(r, L);
     for (int64_t h = 0; h < Hi; ++h) thi[h] = root_neg(h * Lo, N);
@@ -307,25 +307,27 @@ paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p
         P->phase3.push_back(A);
         P->phase3.push_back(B);
     }
-    for (auto *ph : {&P->phase1, &P->phase3})
-        for (const auto &q : *ph)
-            if (paco::local_fft_geometry(q).lds_bytes > 160 * 1024 || paco::local_fft_geometry(q).threads > 1024) {
-                (void)hipFree(P->dev_tables);
-                delete P;
-                return fail(PACO_ERR_UNSUPPORTED, "local FFT tile does not fit one workgroup");
-            }
-    // Two LDS column groups (two workgroups per CU) for n = 2^12 in Phase I,
-    // where they measured faster; one group in Phase III.  Tuning knobs:
-    // PACO_GROUPS1 / PACO_GROUPS3 = 1 or 2.
+    // Column groups for n >= 2^10 (tuning knobs PACO_GROUPS1 / PACO_GROUPS3):
+    // 1 = one LDS group of T columns; 2 = two groups of T/2 (half the LDS, two
+    // workgroups per CU); 3 = two groups of T, a tile twice as wide (512
+    // threads with 64 items each).
     {
         auto pick = [](LocalPass &q, const char *env, int dflt) {
             int g = dflt;
-            if (const char *e = std::getenv(env)) g = e[0] == '2' ? 2 : 1;
-            if (q.log2n < 10 || q.log2T < 1) g = 1;
+            if (const char *e = std::getenv(env)) g = e[0] - '0';
+            if (g < 1 || g > 3 || q.log2n < 10 || q.log2T < 1 || q.no_fast) g = 1;
+            if (g == 3) {
+                if ((int64_t(1) << (q.log2T + 1)) > q.ncols) g = 2;
+                else q.log2T += 1;  // twice as many columns per tile
+            }
             q.groups = g;
+            if (g > 1 && paco::local_fft_fast_mode(q) < 0) {  // not a fast pass: plain tile
+                if (g == 3) q.log2T -= 1;
+                q.groups = 1;
+            }
         };
         for (auto &q : P->phase1) pick(q, "PACO_GROUPS1", q.log2n >= 12 ? 2 : 1);
-        for (auto &q : P->phase3) pick(q, "PACO_GROUPS3", 1);
+        for (auto &q : P->phase3) pick(q, "PACO_GROUPS3", q.log2n >= 12 ? 3 : 1);
     }
     // ---- fused pipeline: Phase I writes the packed slab transposed --------
     {
@@ -341,6 +343,13 @@ paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p
             P->phase1_packed = q;
         }
     }
+    for (auto *ph : {&P->phase1, &P->phase3})
+        for (const auto &q : *ph)
+            if (paco::local_fft_geometry(q).lds_bytes > 160 * 1024 || paco::local_fft_geometry(q).threads > 1024) {
+                (void)hipFree(P->dev_tables);
+                delete P;
+                return fail(PACO_ERR_UNSUPPORTED, "local FFT tile does not fit one workgroup");
+            }
     // ---- Phase II ---------------------------------------------------------
     P->mid.N1 = N1;
     P->mid.N2 = N2;
