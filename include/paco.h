@@ -24,8 +24,9 @@
  *
  * Ownership: the caller allocates and owns in, out, workspace (device
  * memory) and the stream.  A plan owns only its small device tables
- * (digit-reversal maps and twiddle tables generated in FP64 on the host and
- * rounded once to FP32), allocated by paco_plan_create and released by
+ * (twiddle-factor tables generated in FP64 on the host and rounded once to
+ * FP32; digit reversals are computed in the kernels from the indices),
+ * allocated by paco_plan_create and released by
  * paco_plan_destroy.  A plan is immutable after creation and may be shared
  * by threads; executions that share a workspace must not overlap.
  *
