@@ -34,12 +34,22 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
+TRAFFIC_PATH = os.path.join(ROOT, "profiles", "traffic_c2.json")
+COPY_BYTES = 1 << 28  # the --calibrate-copy device-to-device copy
+
+
+def short_kernel_name(name: str) -> str:
+    """'void paco::(anonymous namespace)::k<12, 1>(paco::P)' -> 'k<12,1>'."""
+    name = name.split("(paco::")[0].replace("(anonymous namespace)::", "")
+    name = name.replace("void ", "").replace("paco::", "").replace(" ", "")
+    return name
+
+
 def load_traffic(kernel: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", "traffic_c2.json")
     try:
-        with open(path) as f:
+        with open(TRAFFIC_PATH) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -49,6 +59,39 @@ def load_traffic(kernel: str):
     if not k:
         return None
     return k.get("hbm_bytes_per_launch")
+
+
+def traffic_from(fetch_csv: str, write_csv: str):
+    """Turns two `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs of
+    `bench.py --calibrate-copy` (csv output) into HBM bytes per launch.  Each
+    counter (KiB per dispatch) is scaled by what it reads for the 256 MiB
+    device-to-device copy: the largest-grid copyBuffer dispatch."""
+    import csv
+
+    def per_kernel(path, counter):
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        gmax = max(int(r["Grid_Size"]) for r in copies)
+        cal = [float(r["Counter_Value"]) * 1024 for r in copies if int(r["Grid_Size"]) == gmax]
+        scale = COPY_BYTES / (sum(cal) / len(cal))
+        acc = {}
+        for r in rows:
+            if "paco::" in r["Kernel_Name"]:
+                acc.setdefault(short_kernel_name(r["Kernel_Name"]), []).append(float(r["Counter_Value"]) * 1024)
+        return scale, {k: sum(v) / len(v) for k, v in acc.items()}
+
+    fs, fetch = per_kernel(fetch_csv, "FETCH_SIZE")
+    ws, write = per_kernel(write_csv, "WRITE_SIZE")
+    kernels = {}
+    for k in sorted(set(fetch) & set(write)):
+        kernels[k] = dict(fetch_bytes=round(fetch[k] * fs), write_bytes=round(write[k] * ws),
+                          hbm_bytes_per_launch=round(fetch[k] * fs + write[k] * ws))
+    rec = dict(kernel_hash=kernel_hash(), workload=WORKLOAD, fetch_scale=round(fs, 4), write_scale=round(ws, 4),
+               copy_bytes=COPY_BYTES, kernels=kernels)
+    with open(TRAFFIC_PATH, "w") as f:
+        json.dump(rec, f, indent=1)
+        f.write("\n")
+    print(json.dumps(rec, indent=1))
 
 
 def cpu_baseline(x, N: int, budget_s: float):
@@ -83,7 +126,12 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run plain 256 MiB device copies (traffic-counter calibration)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the HBM-traffic summary from two rocprofv3 --pmc csv files and exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        traffic_from(*args.traffic_from)
+        return
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -177,7 +225,7 @@ def main():
     alg_bytes = 16.0 * N  # each phase reads and writes N complex64 items once
     achieved = alg_bytes / (ph_us[dom] * 1e-6) / 1e9
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=load_traffic(names[dom]),
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=load_traffic(names[dom].split()[1]),
                     kernel=names[dom], alg_bytes_per_launch=int(alg_bytes))
 
     rec = dict(metric=METRIC, value=round(gflops, 1), unit="GFLOP/s", n_gpus=1, steps=args.steps,
