@@ -23,7 +23,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "FFT GFLOP/s (5N·log2N/t) + % HBM roofline, N=2^24 c64; MFMA-split vs FP32"
 WORKLOAD = dict(name="c2", N1=4096, N2=4096, p=64, b=16, gen="normal", seed=2)
-KERNEL_SOURCES = ["paper_2609_06449_amd/csrc/local_fft.hip", "paper_2609_06449_amd/csrc/middle.hip"]
+KERNEL_SOURCES = ["paper_2609_06449_amd/csrc/" + f for f in ("local_fft.hip", "middle.hip", "stages.h", "middle_dev.h",
+                                                                  "paco_internal.h")]
 
 
 def kernel_hash() -> str:
@@ -117,12 +118,101 @@ def cpu_baseline(x, N: int, budget_s: float):
                             f"(median {t:.3f} s each, {sum(times):.1f} s total); FP64 recursive radix-2, one thread")
 
 
+def bench_batched(steps: int, warmup: int):
+    """The batched form: 4096 transforms, N_i = 2^k_i with k_i ~ U{8..20}
+    (seed 6), N(0,1) entries, packed back to back; one persistent launch per
+    step, replayed from a captured graph, against a loop of single-transform
+    calls with the same per-size plans (eager, and captured in a graph)."""
+    import numpy as np
+    import torch
+
+    from paper_2609_06449_amd import inputs, paco
+
+    sizes = inputs.batch_sizes(4096, seed=6)
+    t0 = time.perf_counter()
+    plan = paco.BatchPlan(sizes.tolist())
+    tune_s = time.perf_counter() - t0
+    x = torch.from_numpy(inputs.batch_inputs(sizes, seed=6)).to("cuda")
+    out = torch.empty_like(x)
+    ws = torch.empty_like(x)
+    flops = float(np.sum(5.0 * sizes * np.log2(sizes)))
+    E = int(sizes.sum())
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(2):
+            plan.execute(x.data_ptr(), out.data_ptr(), ws.data_ptr(), s.cuda_stream)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            plan.execute(x.data_ptr(), out.data_ptr(), ws.data_ptr(), s.cuda_stream)
+    torch.cuda.synchronize()
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    errors = plan.errors()
+
+    # loop of single calls, same per-size plans
+    singles = {}
+    for i, n in enumerate(sizes.tolist()):
+        if n not in singles:
+            singles[n] = paco.Plan(*plan.transform_plan(i))
+    offs = plan.offsets
+    calls = [(singles[n], x.data_ptr() + 8 * offs[i], out.data_ptr() + 8 * offs[i], ws.data_ptr() + 8 * offs[i])
+             for i, n in enumerate(sizes.tolist())]
+
+    def loop(stream_handle):
+        for pl, a, b, w in calls:
+            pl.execute(a, b, w, stream_handle)
+
+    sh = torch.cuda.current_stream().cuda_stream
+    loop(sh)
+    torch.cuda.synchronize()
+    reps = max(1, min(steps, 5))
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        loop(sh)
+    torch.cuda.synchronize()
+    loop_ms = (time.perf_counter() - t0) * 1e3 / reps
+    g2 = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g2, stream=s):
+            loop(s.cuda_stream)
+    torch.cuda.synchronize()
+    g2.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g2.replay()
+    torch.cuda.synchronize()
+    loop_graph_ms = (time.perf_counter() - t0) * 1e3 / reps
+    rec = dict(workload="4096 complex64 transforms, N_i = 2^k, k ~ U{8..20} (seed 6), N(0,1) entries, "
+                        f"{E} items in total, one persistent launch replayed from a graph",
+               gflops=round(flops / (ms * 1e-3) / 1e9, 1), ms_per_step=round(ms, 4),
+               hbm_frac_3pass=round(48.0 * E / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+               loop_single_calls_ms=round(loop_ms, 3), loop_single_calls_graph_ms=round(loop_graph_ms, 3),
+               speedup_vs_loop=round(loop_ms / ms, 2), speedup_vs_loop_graph=round(loop_graph_ms / ms, 2),
+               plan_create_s=round(tune_s, 2), wait_timeouts=errors, plan=plan.description)
+    del g, g2, x, out, ws
+    for pl in singles.values():
+        pl.close()
+    plan.close()
+    torch.cuda.empty_cache()
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--skip-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run plain 256 MiB device copies (traffic-counter calibration)")
@@ -240,6 +330,11 @@ def main():
                cold_ms_per_step=round(cold_ms, 5),
                cold_hbm_frac_3pass=round(48.0 * N / (cold_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                plan=plan.description)
+
+    if not args.skip_batched:
+        del xd, out, ws
+        torch.cuda.empty_cache()
+        rec["batched"] = bench_batched(max(10, args.steps // 10), 3)
 
     if not args.skip_cpu_baseline:
         import oracle

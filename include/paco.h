@@ -127,6 +127,57 @@ paco_status paco_plan_describe(const paco_plan *plan, int32_t *launches, char *b
 
 paco_status paco_plan_destroy(paco_plan *plan);
 
+/* ---- batched form ---------------------------------------------------------
+ * Many independent transforms, transform i of N[i] = 2^k items (2 <= k <= 20),
+ * each computed as y_i = Omega_{N_i} x_i through the same three phases
+ * (section 3) with its own factorisation N_i = N1 * N2, base b and tile
+ * widths, all inside ONE kernel launch (a persistent grid that takes tiles
+ * from a work queue).  Layout: the transforms are packed back to back, x_i at
+ * items [off_i, off_i + N[i]) of `in`, off_i = N[0] + ... + N[i-1]; y_i is
+ * written in natural order at the same items of `out`.
+ */
+typedef struct paco_batch_plan_s paco_batch_plan;
+
+/* Plans `count` transforms of sizes N[0..count-1] (copied; the caller keeps
+ * N).  The per-size choices (N1 = 2^l1 with N2 = N/N1, b in {2, 4, 16}
+ * dividing both exponents, tile widths) come from, in order: the tuning
+ * cache file tune_cache_path (text, one line per size, written by an earlier
+ * call), else timing every candidate on the current device (allocates about
+ * 400 MB of device memory for a moment; the environment variable
+ * PACO_BATCH_TUNE=0 skips the timing and takes the defaults), after which
+ * the cache file, if named, is (re)written.  NULL: tune now, no file.
+ * Errors: NOT_POWER_OF_B (a size not a power of two), UNSUPPORTED (a size
+ * outside [2^2, 2^20]), INVALID_ARG (count < 1, NULL N, unwritable cache). */
+paco_status paco_batch_plan_create(paco_batch_plan **bp, int32_t count, const int64_t *N, paco_dtype dt,
+                                   const char *tune_cache_path);
+
+/* Bytes of device workspace paco_execute_batched needs: 8 * sum N[i]. */
+paco_status paco_batch_workspace_size(const paco_batch_plan *bp, size_t *bytes);
+
+/* Runs every transform of the plan with one kernel launch on `stream`.
+ * in, out and workspace are 16-byte aligned device buffers of sum N[i]
+ * complex64 items (workspace: at least the reported size); in == out is
+ * allowed, any other overlap is rejected.  The call enqueues exactly one
+ * kernel and no memset or allocation, so it may be captured into a HIP
+ * graph and replayed.  Executions of one batch plan must not overlap in
+ * time (they share the plan's work-queue counters): issue them on one
+ * stream.  A completion wait that exceeds its poll limit is counted (see
+ * paco_batch_errors) instead of hanging. */
+paco_status paco_execute_batched(const paco_batch_plan *bp, const void *in, void *out, void *workspace,
+                                 size_t workspace_bytes, void *stream);
+
+/* Per-transform plan of transform `index` (N1, N2, the reported slab count p
+ * and b; any pointer may be NULL; index < 0 fills only buf) and a short
+ * description of the whole batch plan in buf. */
+paco_status paco_batch_plan_describe(const paco_batch_plan *bp, int32_t index, int64_t *N1, int64_t *N2, int64_t *p,
+                                     int32_t *b, char *buf, size_t buflen);
+
+/* Number of completion waits that gave up since the plan was created
+ * (0 in every correct run).  Synchronous: copies one counter to the host. */
+paco_status paco_batch_errors(const paco_batch_plan *bp, uint32_t *count);
+
+paco_status paco_batch_plan_destroy(paco_batch_plan *bp);
+
 const char *paco_status_string(paco_status st);
 const char *paco_last_error(void);
 

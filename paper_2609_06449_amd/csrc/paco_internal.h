@@ -4,8 +4,19 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <string>
+#include <vector>
 
 namespace paco {
+
+// Complex product with an explicit fused multiply-add in each component:
+// with a plain a*b - c*d the compiler may fuse either product, and its choice
+// depends on the surrounding code, so two kernels doing the same arithmetic
+// could round differently.  Every kernel multiplies through this function.
+__device__ __forceinline__ float2 cmul(float2 a, float2 b)
+{
+    return make_float2(__builtin_fmaf(a.x, b.x, -(a.y * b.y)), __builtin_fmaf(a.x, b.y, a.y * b.x));
+}
 
 // Largest transform length one local pass keeps on chip (LDS + registers).
 constexpr int kMaxOnChipLog2 = 12;
@@ -152,6 +163,21 @@ struct LocalLaunch {
     size_t lds_bytes;  // dynamic LDS per workgroup
     int64_t tiles;     // column tiles in the pass
 };
+
+// Thread-local detail string returned by paco_last_error (plan.hip).
+void set_last_error(const std::string &msg);
+
+// ---- host tables (tables.hip) -------------------------------------------
+// w_M^{-r} = exp(-2 pi i r / M) from the exact integer r, in FP64, rounded
+// once to FP32.
+float2 root_neg(int64_t r, int64_t M);
+// Stage twiddle factor tables of every on-chip length 2^1 .. 2^12,
+// concatenated; off[l] is the first entry of length 2^l.
+bool stage_tables(std::vector<float2> &stw, int64_t off[kMaxOnChipLog2 + 1]);
+// Phase-II tables of N = 2^lN: w_N^{-h*Lo} (hi), w_N^{-l} (lo) with
+// Lo = 2^middle_log2lo(lN), and the 128 x 128 tile table.
+constexpr int middle_log2lo(int lN) { return (lN + 1) / 2; }
+void middle_tables(int lN, std::vector<float2> &hi, std::vector<float2> &lo, std::vector<float2> &tile);
 
 LocalLaunch local_fft_geometry(const LocalPass &p);
 hipError_t local_fft_prepare();  // raises the dynamic-LDS limit of every kernel once

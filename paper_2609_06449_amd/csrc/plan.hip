@@ -39,18 +39,12 @@ int ilog2_exact(int64_t n)
     return l;
 }
 
-// w_M^{-r} = exp(-2 pi i r / M), evaluated in FP64 from the exact integer r
-// and rounded once to FP32.
-float2 root_neg(int64_t r, int64_t M)
-{
-    const double a = 2.0 * M_PI * (double(r) / double(M));
-    return make_float2(float(std::cos(a)), float(-std::sin(a)));
-}
-
 constexpr int kMaxLocalLog2 = 16;  // N1, N2 <= 2^16 (at most two on-chip passes)
 constexpr int kMaxTotalLog2 = 28;  // N1*N2 <= 2^28: every buffer < 4 GiB (32-bit byte offsets)
 
 }  // namespace
+
+void paco::set_last_error(const std::string &msg) { g_last_error = msg; }
 
 struct paco_plan_s {
     int64_t N1 = 0, N2 = 0, p = 0;
@@ -148,7 +142,7 @@ paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p
     P->m2 = P->l2 / P->t;
     P->lN = P->l1 + P->l2;
     P->lL = P->l1 > P->l2 ? P->l1 : P->l2;
-    P->lLo = (P->lN + 1) / 2;
+    P->lLo = paco::middle_log2lo(P->lN);
 
     int a1, b1, a3, b3;
     split_local(P->l1, P->t, a1, b1);
@@ -160,35 +154,15 @@ paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p
     }
 
     // ---- host tables (FP64-generated, rounded once to FP32) ----------------
-    const int64_t N = int64_t(1) << P->lN;
-    const int64_t L = int64_t(1) << P->lL, Lo = int64_t(1) << P->lLo, Hi = N >> P->lLo;
-    constexpr int64_t TT = paco::kTwTile;
-    std::vector<float2> tw(L), thi(Hi), tlo(Lo), ttile(TT * TT);
-    for (int64_t r = 0; r < L; ++r) tw[r] = root_neg(r, L);
-    for (int64_t h = 0; h < Hi; ++h) thi[h] = root_neg(h * Lo, N);
-    for (int64_t l = 0; l < Lo; ++l) tlo[l] = root_neg(l, N);
-    for (int64_t i = 0; i < TT; ++i)
-        for (int64_t j = 0; j < TT; ++j) ttile[i * TT + j] = root_neg((i * j) % N, N);
-    // stage twiddle factor tables of every on-chip length 2^1 .. 2^12
-    std::vector<float2> stw;
-    int64_t stw_off[paco::kMaxOnChipLog2 + 1] = {0};
-    for (int l = 1; l <= paco::kMaxOnChipLog2; ++l) {
-        stw_off[l] = int64_t(stw.size());
-        for (int S = 1; S < paco::stage_count(l); ++S) {
-            const int R = 1 << paco::stage_log2radix(l, S);
-            const int64_t Ns = int64_t(1) << paco::stage_log2ns(l, S), M = Ns * R;
-            const int LOW = paco::stage_lo_width(l, S), HIW = paco::stage_hi_width(l, S);
-            for (int r = 1; r < R; ++r)
-                for (int kl = 0; kl < LOW; ++kl) stw.push_back(root_neg((int64_t(kl) * r) % M, M));
-            for (int r = 1; r < R; ++r)
-                for (int kh = 0; kh < HIW; ++kh) stw.push_back(root_neg((int64_t(16) * kh * r) % M, M));
-        }
-        if (int64_t(stw.size()) - stw_off[l] != paco::stage_tw_total(l)) {
-            delete P;
-            return fail(PACO_ERR_INVALID_ARG, "internal: stage twiddle layout mismatch");
-        }
+    const int64_t L = int64_t(1) << P->lL;
+    std::vector<float2> tw(L), thi, tlo, ttile, stw;
+    for (int64_t r = 0; r < L; ++r) tw[r] = paco::root_neg(r, L);
+    paco::middle_tables(P->lN, thi, tlo, ttile);
+    int64_t stw_off[paco::kMaxOnChipLog2 + 1];
+    if (!paco::stage_tables(stw, stw_off)) {
+        delete P;
+        return fail(PACO_ERR_INVALID_ARG, "internal: stage twiddle layout mismatch");
     }
-    stw.push_back(make_float2(0.f, 0.f));  // never empty
 
     // one device allocation, 256-byte aligned pieces
     struct Piece { const void *src; size_t bytes; size_t off; };

@@ -1,0 +1,374 @@
+// Device code shared by the LocalFFT kernels (local_fft.hip) and the batched
+// persistent kernel (batch.hip): radix-16 Stockham stages with LDS
+// exchanges, the HBM-boundary row maps of Lemma 1, and one column tile of a
+// single-pass local transform.  Included once per translation unit.
+#pragma once
+
+#include "paco_internal.h"
+
+namespace paco {
+namespace {
+
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+
+// d * w_16^{-m} for a compile-time m (after unrolling), w_16 = exp(2 pi i/16).
+// Constants are cos/sin(2 pi m/16) rounded to float.
+__device__ __forceinline__ float2 mul_w16(float2 d, int m)
+{
+    constexpr float c1 = 0.923879532511286756f;  // cos(pi/8)
+    constexpr float s1 = 0.382683432365089772f;  // sin(pi/8)
+    constexpr float h = 0.707106781186547524f;   // cos(pi/4)
+    switch (m & 15) {
+    case 0: return d;
+    case 1: return cmul(d, make_float2(c1, -s1));
+    case 2: return make_float2(h * (d.x + d.y), h * (d.y - d.x));
+    case 3: return cmul(d, make_float2(s1, -c1));
+    case 4: return make_float2(d.y, -d.x);
+    case 5: return cmul(d, make_float2(-s1, -c1));
+    case 6: return make_float2(h * (d.y - d.x), -h * (d.x + d.y));
+    case 7: return cmul(d, make_float2(-c1, -s1));
+    case 8: return make_float2(-d.x, -d.y);
+    case 9: return cmul(d, make_float2(-c1, s1));
+    case 10: return make_float2(-h * (d.x + d.y), h * (d.x - d.y));
+    case 11: return cmul(d, make_float2(-s1, c1));
+    case 12: return make_float2(-d.y, d.x);
+    case 13: return cmul(d, make_float2(s1, c1));
+    case 14: return make_float2(h * (d.x - d.y), h * (d.x + d.y));
+    default: return cmul(d, make_float2(c1, s1));
+    }
+}
+
+constexpr int bitrev_c(int x, int bits)
+{
+    int r = 0;
+    for (int i = 0; i < bits; ++i) r |= ((x >> i) & 1) << (bits - 1 - i);
+    return r;
+}
+
+// In-register length-R DFT (R = 2^LR <= 16), natural order in and out:
+// radix-2 decimation-in-frequency network, then a compile-time reorder.
+template <int LR>
+__device__ __forceinline__ void dft_regs(float2 *v)
+{
+    constexpr int R = 1 << LR;
+#pragma unroll
+    for (int len = R; len >= 2; len >>= 1) {
+        const int half = len >> 1;
+#pragma unroll
+        for (int base = 0; base < R; base += len) {
+#pragma unroll
+            for (int k = 0; k < half; ++k) {
+                float2 a = v[base + k], b = v[base + k + half];
+                v[base + k] = cadd(a, b);
+                v[base + k + half] = mul_w16(csub(a, b), k * (16 / len));
+            }
+        }
+    }
+    float2 t[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) t[k] = v[bitrev_c(k, LR)];
+#pragma unroll
+    for (int k = 0; k < R; ++k) v[k] = t[k];
+}
+
+// HBM stores of a tile's results.  COH: a device-coherent store (written
+// through this XCD's L2), for results another workgroup of the same launch
+// reads after a completion counter says they are there; the 16-byte form
+// becomes two such 8-byte stores.
+template <bool COH>
+__device__ __forceinline__ void st2(char *p, float2 v)
+{
+    if constexpr (COH) {
+        uint64_t bits;
+        __builtin_memcpy(&bits, &v, 8);
+        __hip_atomic_store(reinterpret_cast<uint64_t *>(p), bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        *reinterpret_cast<float2 *>(p) = v;
+    }
+}
+template <bool COH>
+__device__ __forceinline__ void st4(char *p, float4 v)
+{
+    if constexpr (COH) {
+        st2<true>(p, make_float2(v.x, v.y));
+        st2<true>(p + 8, make_float2(v.z, v.w));
+    } else {
+        *reinterpret_cast<float4 *>(p) = v;
+    }
+}
+
+// LDS index with 4 pad items per 64: the radix-16 first-stage writes (row
+// stride 16*T items) land on distinct banks.
+__device__ __forceinline__ int lpad(int e) { return e + ((e >> 6) << 2); }
+
+// Digit reversal with compile-time digit width TB and digit count ND.
+template <int TB, int ND>
+__device__ __forceinline__ uint32_t drev(uint32_t x)
+{
+    uint32_t r = 0;
+#pragma unroll
+    for (int g = 0; g < ND; ++g) r |= ((x >> (TB * g)) & ((1u << TB) - 1)) << (TB * (ND - 1 - g));
+    return r;
+}
+constexpr int crev(int x, int tb, int nd)
+{
+    int r = 0;
+    for (int g = 0; g < nd; ++g) r |= ((x >> (tb * g)) & ((1 << tb) - 1)) << (tb * (nd - 1 - g));
+    return r;
+}
+
+// Tile width of the fast kernels: 4096 items per workgroup for short
+// transforms, 4 columns (32-byte row runs) for long ones.
+constexpr int fast_log2T(int l) { return l >= 10 ? 2 : 12 - l; }
+
+struct Ctx {
+    float2 *lds;
+    const float2 *twl;
+    int tid, nt, log2T;
+    char *dst;                 // tile base (column col0 of row 0)
+    uint32_t ld8;              // row length in bytes
+    uint32_t orow_out, k_out;  // generic: output row = orow_out + pi_out(k) * k_out
+    int out_t, out_ell;
+    bool act;                  // runtime tile width: this thread owns butterflies (tid < nt)
+};
+
+// Stage S of the Stockham sequence on H column groups.  v[h*EG + i*R + r]
+// is operand r of butterfly i of group h; butterfly id g = tid + i*nt of a
+// group covers column g mod TG and index j = g / TG (TG columns per group);
+// between stages the groups take turns in LDS, which holds n x TG items.
+// LT >= 0: compile-time log2 TG.  MODE: -1 generic output rows, 0 digit-
+// reversed output rows (Phase I), 1 natural output rows (Phase III), 2 the
+// transposed natural output (row = column, n items per row; Phase I of the
+// fused pipeline).
+template <int LOG2N, int S, int EG, int LT, int MODE, int TB, bool GEN, int H, bool COH = false>
+__device__ __forceinline__ void run_stage(float2 (&v)[H * EG], const Ctx &c)
+{
+    constexpr int LR = stage_log2radix(LOG2N, S);
+    constexpr int R = 1 << LR;
+    constexpr int LNS = stage_log2ns(LOG2N, S);
+    constexpr int NB = EG / R;
+    constexpr bool last = (S + 1 == stage_count(LOG2N));
+    const int log2T = LT >= 0 ? LT : c.log2T;
+    const int nt = LT >= 0 ? ((1 << (LOG2N + (LT >= 0 ? LT : 0))) / EG) : c.nt;
+    const int Tm = (1 << log2T) - 1;
+    // with a compile-time tile width every thread of the workgroup owns
+    // butterflies; with a runtime one the threads from nt on only take part
+    // in the barriers
+    const bool act = LT >= 0 || c.act;
+
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+        const int g = c.tid + i * nt;
+        const int j = g >> log2T;
+        if constexpr (LNS > 0) {
+            // the same twiddles serve every group (same j)
+            constexpr int LOW = stage_lo_width(LOG2N, S);
+            constexpr int HIW = stage_hi_width(LOG2N, S);
+            constexpr int OFF = stage_tw_offset(LOG2N, S);
+            const int k = j & ((1 << LNS) - 1);
+            const float2 *tlo = c.twl + OFF + (k & (LOW - 1));
+            const float2 *thi = c.twl + OFF + (R - 1) * LOW + (k >> 4);
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                float2 w = tlo[(r - 1) * LOW];
+                if constexpr (HIW > 0) w = cmul(w, thi[(r - 1) * HIW]);
+#pragma unroll
+                for (int h = 0; h < H; ++h) v[h * EG + i * R + r] = cmul(v[h * EG + i * R + r], w);
+            }
+        }
+#pragma unroll
+        for (int h = 0; h < H; ++h) dft_regs<LR>(&v[h * EG + i * R]);
+    }
+    if constexpr (!last) {
+        constexpr int LR2 = stage_log2radix(LOG2N, S + 1);
+        constexpr int R2 = 1 << LR2;
+        constexpr int NB2 = EG / R2;
+        constexpr int LNR2 = LOG2N - LR2;
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            if (S > 0 || h > 0) __syncthreads();  // the previous LDS contents were consumed
+            if (act) {
+#pragma unroll
+                for (int i = 0; i < NB; ++i) {
+                    const int g = c.tid + i * nt;
+                    const int t = g & Tm, j = g >> log2T;
+                    const int idxD = ((j >> LNS) << (LNS + LR)) + (j & ((1 << LNS) - 1));
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        c.lds[lpad(((idxD + (r << LNS)) << log2T) + t)] = v[h * EG + i * R + r];
+                }
+            }
+            __syncthreads();
+            if (act) {
+#pragma unroll
+                for (int i = 0; i < NB2; ++i) {
+                    const int g = c.tid + i * nt;
+                    const int t = g & Tm, j = g >> log2T;
+#pragma unroll
+                    for (int r = 0; r < R2; ++r)
+                        v[h * EG + i * R2 + r] = c.lds[lpad(((j + (r << LNR2)) << log2T) + t)];
+                }
+            }
+        }
+        run_stage<LOG2N, S + 1, EG, LT, MODE, TB, GEN, H, COH>(v, c);
+    } else {
+        // last stage: j < n/R = 2^LNS, outputs are the natural-order rows k = j + r*2^LNS.
+        if (!act) return;
+        // With H = 2 the groups interleave: group h of tile column t holds
+        // column 2t + h, so one 16-byte store writes both groups' items.
+        if constexpr (H == 2 && (MODE == 0 || MODE == 1)) {
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                const int g = c.tid + i * nt;
+                const int t = (g & Tm) << 1, j = g >> log2T;
+                uint32_t base;
+                if constexpr (MODE == 0)
+                    base = ((drev<TB, LNS / TB>(j) << LR) * c.ld8) + uint32_t(t) * 8u;
+                else
+                    base = uint32_t(j) * c.ld8 + uint32_t(t) * 8u;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const uint32_t row_off = MODE == 0 ? uint32_t(crev(r, TB, LR / TB)) * c.ld8 : (uint32_t(r) << LNS) * c.ld8;
+                    const float2 a0 = v[i * R + r], a1 = v[EG + i * R + r];
+                    st4<COH>(c.dst + base + row_off, make_float4(a0.x, a0.y, a1.x, a1.y));
+                }
+            }
+            return;
+        }
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                const int g = c.tid + i * nt;
+                const int t = H == 2 ? (((g & Tm) << 1) + h) : (g & Tm), j = g >> log2T;
+                const float2 *u = &v[h * EG + i * R];
+                if constexpr (MODE == 0) {
+                    // row pi(k) = pi(j)*2^LR + pi(r)
+                    const uint32_t base = ((drev<TB, LNS / TB>(j) << LR) * c.ld8) + uint32_t(t) * 8u;
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        st2<COH>(c.dst + base + uint32_t(crev(r, TB, LR / TB)) * c.ld8, u[r]);
+                } else if constexpr (MODE == 2) {
+                    // transposed output: row (col0 + t) holds all n frequencies in order
+                    const uint32_t base = (uint32_t(t) << (LOG2N + 3)) + uint32_t(j) * 8u;
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        st2<COH>(c.dst + base + (uint32_t(r) << (LNS + 3)), u[r]);
+                } else if constexpr (MODE == 1) {
+                    const uint32_t base = uint32_t(j) * c.ld8 + uint32_t(t) * 8u;
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        st2<COH>(c.dst + base + (uint32_t(r) << LNS) * c.ld8, u[r]);
+                } else {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const uint32_t k = j + (r << LNS);
+                        const uint32_t m = uint32_t(digrev<GEN>(k, c.out_t, c.out_ell));
+                        const uint32_t off = (c.orow_out + m * c.k_out) * c.ld8 + uint32_t(t) * 8u;
+                        st2<COH>(c.dst + off, u[r]);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Tile order: the hardware deals consecutive workgroup ids to the 8 XCDs in
+// turn.  Renumber so that the workgroups one XCD receives back to back own
+// neighbouring column tiles, which share 128-byte lines in that XCD's L2.
+__device__ __forceinline__ int64_t tile_order(int64_t i, int64_t G)
+{
+    if (G & 7) return i;
+    return (i & 7) * (G >> 3) + (i >> 3);
+}
+
+__device__ __forceinline__ void copy_twiddles(float2 *twl, const float2 *stw, int n, int tid, int nt)
+{
+    for (int e = tid; e < n; e += nt) twl[e] = stw[e];  // first read after a barrier
+}
+
+
+constexpr int fast_tile_log2T(int l, int h, int eg) { return fast_log2T(l) + (h == 2 && eg == 32 ? 1 : 0); }
+constexpr int fast_threads(int l, int h, int eg)
+{
+    return (1 << (l + fast_tile_log2T(l, h, eg))) / (h * eg);
+}
+
+// One column tile of a single-pass local transform, the body of the fast
+// kernels.  MODE 0: natural input rows, digit-reversed
+// output rows (Phase I, A = P_pi Omega).  MODE 1: digit-reversed input rows,
+// natural output rows (Phase III, B = Omega P_pi).  MODE 2: natural input
+// rows, output written transposed in natural frequency order (Phase I of the
+// fused pipeline: Lemma 1's output layout composed with the pack step's row
+// reversal is the identity, so the packed slab holds frequency k1 at k1).
+// b = 2^TB.  H = 2 splits the T columns into two LDS groups: half the LDS
+// per workgroup, so two workgroups share a CU and overlap each other's HBM
+// traffic and arithmetic.
+// EG = 32 (with H = 2) doubles the tile width: 512 threads hold 64 items
+// each (two waves per SIMD, 256 VGPRs of budget).
+// COH: device-coherent result stores (see st2).
+// LT = log2 of the tile's columns; the caller launches exactly
+// 2^(LOG2N + LT - (H == 2)) / EG threads per tile.  srcm/dstm: the matrix
+// (row length ld items); col0: the tile's first column.
+template <int LOG2N, int MODE, int TB, int H, int EG, int LT, bool COH = false>
+__device__ __forceinline__ void fast_tile(const float2 *srcm, float2 *dstm, uint32_t ld, int64_t col0,
+                                          const float2 *stw, float2 *smem, int tid)
+{
+    constexpr int LTG = LT - (H == 2 ? 1 : 0);         // log2 of the columns of one group
+    constexpr int NT = (1 << (LOG2N + LTG)) / EG;
+    constexpr int LR0 = stage_log2radix(LOG2N, 0);
+    constexpr int R0 = 1 << LR0;
+    constexpr int NB0 = EG / R0;
+    constexpr int LNR0 = LOG2N - LR0;
+    constexpr int TWN = stage_tw_total(LOG2N);
+    float2 *twl = smem;
+    float2 *lds = smem + ((TWN + 63) & ~63);
+    const char *src = reinterpret_cast<const char *>(srcm + col0);
+    const uint32_t ld8 = ld * 8u;
+
+    // H = 2: group h of tile column t is column 2t + h, and one 16-byte load
+    // fetches both groups' items of a row
+    float2 v[H * EG];
+#pragma unroll
+    for (int q = 0; q < NB0; ++q) {
+        const int g = tid + q * NT;
+        const int t = (g & ((1 << LTG) - 1)) * H, j = g >> LTG;
+        uint32_t base;
+        if constexpr (MODE == 0 || MODE == 2)
+            base = uint32_t(j) * ld8 + uint32_t(t) * 8u;
+        else  // row pi(j + r*2^LNR0) = pi(j)*2^LR0 + pi(r)
+            base = (drev<TB, LNR0 / TB>(j) << LR0) * ld8 + uint32_t(t) * 8u;
+#pragma unroll
+        for (int r = 0; r < R0; ++r) {
+            const uint32_t row_off =
+                (MODE == 0 || MODE == 2) ? (uint32_t(r) << LNR0) * ld8 : uint32_t(crev(r, TB, LR0 / TB)) * ld8;
+            if constexpr (H == 2) {
+                const float4 a = *reinterpret_cast<const float4 *>(src + base + row_off);
+                v[q * R0 + r] = make_float2(a.x, a.y);
+                v[EG + q * R0 + r] = make_float2(a.z, a.w);
+            } else {
+                v[q * R0 + r] = *reinterpret_cast<const float2 *>(src + base + row_off);
+            }
+        }
+    }
+    copy_twiddles(twl, stw, TWN, tid, NT);  // after the data loads are issued
+    Ctx c;
+    c.lds = lds;
+    c.twl = twl;
+    c.tid = tid;
+    c.nt = NT;
+    c.log2T = LTG;
+    c.dst = reinterpret_cast<char *>(MODE == 2 ? dstm + (col0 << LOG2N) : dstm + col0);
+    c.ld8 = ld8;
+    c.orow_out = 0;
+    c.k_out = 1;
+    c.out_t = 0;
+    c.out_ell = 0;
+    c.act = true;
+    run_stage<LOG2N, 0, EG, LTG, MODE, TB, false, H, COH>(v, c);
+}
+
+}  // namespace
+}  // namespace paco

@@ -30,7 +30,8 @@ PACO_PACKED = 2
 EXPORTED = (
     "paco_plan_validate", "paco_plan_create", "paco_plan_workspace_size", "paco_execute",
     "paco_execute_stage", "paco_plan_describe", "paco_plan_destroy", "paco_status_string",
-    "paco_last_error",
+    "paco_last_error", "paco_batch_plan_create", "paco_batch_workspace_size", "paco_execute_batched",
+    "paco_batch_plan_describe", "paco_batch_errors", "paco_batch_plan_destroy",
 )
 
 
@@ -64,6 +65,13 @@ def _load() -> ctypes.CDLL:
         "paco_plan_destroy": (st, [P]),
         "paco_status_string": (ctypes.c_char_p, [st]),
         "paco_last_error": (ctypes.c_char_p, []),
+        "paco_batch_plan_create": (st, [ctypes.POINTER(P), i32, ctypes.POINTER(i64), st, ctypes.c_char_p]),
+        "paco_batch_workspace_size": (st, [P, ctypes.POINTER(sz)]),
+        "paco_execute_batched": (st, [P, P, P, P, sz, P]),
+        "paco_batch_plan_describe": (st, [P, i32, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                          ctypes.POINTER(i32), ctypes.c_char_p, sz]),
+        "paco_batch_errors": (st, [P, ctypes.POINTER(ctypes.c_uint32)]),
+        "paco_batch_plan_destroy": (st, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -146,6 +154,92 @@ class Plan:
     def close(self):
         if self.handle:
             paco_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- batched form ----------------------------------------------------------
+
+
+def paco_batch_plan_create(sizes, dt: int = PACO_C64, tune_cache_path=None) -> int:
+    arr = (ctypes.c_int64 * len(sizes))(*[int(n) for n in sizes])
+    h = ctypes.c_void_p()
+    path = tune_cache_path.encode() if tune_cache_path is not None else None
+    _check(_lib.paco_batch_plan_create(ctypes.byref(h), len(sizes), arr, dt, path), "paco_batch_plan_create")
+    return h.value
+
+
+def paco_batch_plan_create_status(sizes, dt: int = PACO_C64, tune_cache_path=None) -> int:
+    """Status code only (no exception); destroys the plan when one was made."""
+    arr = (ctypes.c_int64 * max(len(sizes), 1))(*[int(n) for n in sizes])
+    h = ctypes.c_void_p()
+    path = tune_cache_path.encode() if tune_cache_path is not None else None
+    st = int(_lib.paco_batch_plan_create(ctypes.byref(h), len(sizes), arr, dt, path))
+    if h.value:
+        _lib.paco_batch_plan_destroy(h)
+    return st
+
+
+def paco_batch_workspace_size(bp: int) -> int:
+    n = ctypes.c_size_t()
+    _check(_lib.paco_batch_workspace_size(bp, ctypes.byref(n)), "paco_batch_workspace_size")
+    return n.value
+
+
+def paco_execute_batched(bp: int, src: int, dst: int, workspace: int, workspace_bytes: int, stream: int = 0):
+    _check(_lib.paco_execute_batched(bp, src, dst, workspace, workspace_bytes, stream), "paco_execute_batched")
+
+
+def paco_batch_plan_describe(bp: int, index: int = -1):
+    n1, n2, p, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+    buf = ctypes.create_string_buffer(4096)
+    _check(_lib.paco_batch_plan_describe(bp, index, ctypes.byref(n1), ctypes.byref(n2), ctypes.byref(p),
+                                         ctypes.byref(b), buf, 4096), "paco_batch_plan_describe")
+    return (n1.value, n2.value, p.value, b.value), buf.value.decode()
+
+
+def paco_batch_errors(bp: int) -> int:
+    n = ctypes.c_uint32()
+    _check(_lib.paco_batch_errors(bp, ctypes.byref(n)), "paco_batch_errors")
+    return n.value
+
+
+def paco_batch_plan_destroy(bp: int):
+    _check(_lib.paco_batch_plan_destroy(bp), "paco_batch_plan_destroy")
+
+
+class BatchPlan:
+    """Owns one paco_batch_plan handle: transform i has sizes[i] items, packed
+    back to back (offsets = running sums)."""
+
+    def __init__(self, sizes, dt: int = PACO_C64, tune_cache_path=None):
+        self.sizes = [int(n) for n in sizes]
+        self.offsets = [0]
+        for n in self.sizes:
+            self.offsets.append(self.offsets[-1] + n)
+        self.total = self.offsets[-1]
+        self.handle = paco_batch_plan_create(self.sizes, dt, tune_cache_path)
+        self.workspace_bytes = paco_batch_workspace_size(self.handle)
+        _, self.description = paco_batch_plan_describe(self.handle, -1)
+
+    def transform_plan(self, i: int):
+        """(N1, N2, p, b) chosen for transform i."""
+        return paco_batch_plan_describe(self.handle, i)[0]
+
+    def execute(self, src: int, dst: int, workspace: int, stream: int = 0):
+        paco_execute_batched(self.handle, src, dst, workspace, self.workspace_bytes, stream)
+
+    def errors(self) -> int:
+        return paco_batch_errors(self.handle)
+
+    def close(self):
+        if self.handle:
+            paco_batch_plan_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

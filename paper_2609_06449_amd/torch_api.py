@@ -51,3 +51,18 @@ def stage(x: torch.Tensor, N1: int, N2: int, p: int, b: int, stage: int, flags: 
         out = torch.empty(N, dtype=torch.complex64, device=x.device)
     plan.execute_stage(stage, x.data_ptr(), out.data_ptr(), _stream(), flags)
     return out
+
+
+def fft_batched(x: torch.Tensor, plan: paco.BatchPlan, out: torch.Tensor | None = None,
+                workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """Every transform of a batch plan in one launch: x holds the inputs back
+    to back (transform i at plan.offsets[i]); returns the outputs in the same
+    places, each y_i in natural order."""
+    _check_tensor(x, plan.total, "x")
+    if out is None:
+        out = torch.empty(plan.total, dtype=torch.complex64, device=x.device)
+    _check_tensor(out, plan.total, "out")
+    if workspace is None:
+        workspace = torch.empty(plan.total, dtype=torch.complex64, device=x.device)
+    plan.execute(x.data_ptr(), out.data_ptr(), workspace.data_ptr(), _stream())
+    return out

@@ -87,3 +87,20 @@ def test_status_strings():
     for st in range(8):
         assert paco.paco_status_string(st)
     assert paco.paco_status_string(0) == "ok"
+
+
+@pytest.mark.parametrize("sizes,status", [
+    ([], paco.PACO_ERR_INVALID_ARG),                      # no transforms
+    ([256, 48], paco.PACO_ERR_NOT_POWER_OF_B),            # not a power of two
+    ([256, 0], paco.PACO_ERR_NOT_POWER_OF_B),
+    ([256, -4], paco.PACO_ERR_NOT_POWER_OF_B),
+    ([2], paco.PACO_ERR_UNSUPPORTED),                     # N1 = N2 >= 2 needs N >= 4
+    ([1 << 21], paco.PACO_ERR_UNSUPPORTED),               # local lengths above 2^10
+])
+def test_batch_plan_rejects_before_any_hip_call(sizes, status):
+    assert paco.paco_batch_plan_create_status(sizes) == status
+    assert paco.paco_last_error()
+
+
+def test_batch_plan_rejects_unknown_dtype():
+    assert paco.paco_batch_plan_create_status([256], dt=7) == paco.PACO_ERR_INVALID_ARG
