@@ -59,8 +59,20 @@ typedef enum {
     PACO_ERR_HIP = 7            /* a HIP runtime call failed (detail in last_error) */
 } paco_status;
 
+/* Arithmetic of a plan; I/O is always complex64 (interleaved FP32 re, im).
+ * The split forms run every radix-16 butterfly of the local FFTs as a real
+ * contraction [Wr, -Wi; Wi, Wr][xr; xi] (K = 32) on the MFMA units, with each
+ * FP32 operand split into 16-bit parts and the partial products summed in
+ * FP32; twiddle multiplications stay FP32 (tables generated in FP64).  Not in
+ * the paper: its DFT is exact in exact arithmetic; these trade accuracy for
+ * matrix-core arithmetic, and their error against FP64 is a measured figure
+ * (no bound is claimed). */
 typedef enum {
-    PACO_C64 = 0                /* complex64 I/O, FP32 arithmetic on the vector ALUs */
+    PACO_C64 = 0,               /* FP32 arithmetic on the vector ALUs                  */
+    PACO_C64_MFMA_FP16X3 = 1,   /* FP16 hi + 2^11-scaled lo, per-butterfly power-of-two
+                                   scale, products hi*hi + hi*lo + lo*hi (~22 bits)      */
+    PACO_C64_MFMA_BF16X3 = 2,   /* BF16 hi + lo, products hi*hi + hi*lo + lo*hi (~16 bits) */
+    PACO_C64_MFMA_BF16X6 = 3    /* BF16 hi + mid + lo, six products (~24 bits)           */
 } paco_dtype;
 
 /* paco_execute_stage flags */
@@ -146,8 +158,10 @@ typedef struct paco_batch_plan_s paco_batch_plan;
  * 400 MB of device memory for a moment; the environment variable
  * PACO_BATCH_TUNE=0 skips the timing and takes the defaults), after which
  * the cache file, if named, is (re)written.  NULL: tune now, no file.
+ * dt must be PACO_C64 (the split MFMA forms are single-transform only).
  * Errors: NOT_POWER_OF_B (a size not a power of two), UNSUPPORTED (a size
- * outside [2^2, 2^20]), INVALID_ARG (count < 1, NULL N, unwritable cache). */
+ * outside [2^2, 2^20], or another dt), INVALID_ARG (count < 1, NULL N, an
+ * unknown dt, unwritable cache). */
 paco_status paco_batch_plan_create(paco_batch_plan **bp, int32_t count, const int64_t *N, paco_dtype dt,
                                    const char *tune_cache_path);
 

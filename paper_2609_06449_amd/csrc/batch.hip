@@ -868,6 +868,8 @@ paco_status paco_batch_plan_create(paco_batch_plan **bp, int32_t count, const in
 {
     if (!bp) return bfail(PACO_ERR_INVALID_ARG, "plan out-pointer is NULL");
     *bp = nullptr;
+    if (dt == PACO_C64_MFMA_FP16X3 || dt == PACO_C64_MFMA_BF16X3 || dt == PACO_C64_MFMA_BF16X6)
+        return bfail(PACO_ERR_UNSUPPORTED, "the batched form runs the FP32 arithmetic only");
     if (dt != PACO_C64) return bfail(PACO_ERR_INVALID_ARG, "unknown dtype");
     if (count < 1 || !N) return bfail(PACO_ERR_INVALID_ARG, "need count >= 1 and a size array");
     paco_batch_plan_s *P = new (std::nothrow) paco_batch_plan_s();

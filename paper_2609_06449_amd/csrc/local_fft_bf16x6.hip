@@ -1,0 +1,17 @@
+// LocalFFT kernels whose radix-16 butterflies run on MFMA in the BF16x6
+// split form (stages.h); everything else as in the FP32 kernels.
+#include "local_fft_kernels.h"
+
+namespace paco {
+
+const void *fast_kernel_bf16x6(int log2n, int mode, int tb, int groups)
+{
+    return fast_kernel_t<kPrecBF16x6>(log2n, mode, tb, groups);
+}
+
+const void *generic_kernel_bf16x6(int log2n, bool pre, bool gen)
+{
+    return generic_kernel_t<kPrecBF16x6>(log2n, pre, gen);
+}
+
+}  // namespace paco

@@ -132,6 +132,7 @@ struct LocalPass {
     int32_t no_fast;       // 1: always use the generic kernel (testing)
     int32_t out_tr;        // 1: write the output transposed (row = column, n items; fast kernel only)
     int32_t groups;        // fast kernel: 1, or 2 column groups taking turns in LDS
+    int32_t prec;          // radix-16 butterflies: 0 FP32 VALU, 1 FP16x3, 2 BF16x3, 3 BF16x6 (MFMA)
 };
 
 // Phase II: out[pi2(c)*N1 + v] = ws[pi1(v)*N2 + c] * w_N^{-(v*c mod N)}, the
@@ -178,6 +179,15 @@ bool stage_tables(std::vector<float2> &stw, int64_t off[kMaxOnChipLog2 + 1]);
 // Lo = 2^middle_log2lo(lN), and the 128 x 128 tile table.
 constexpr int middle_log2lo(int lN) { return (lN + 1) / 2; }
 void middle_tables(int lN, std::vector<float2> &hi, std::vector<float2> &lo, std::vector<float2> &tile);
+
+// Kernel tables of the split MFMA forms (local_fft_fp16x3.hip,
+// local_fft_bf16x3.hip, local_fft_bf16x6.hip); nullptr where no kernel exists.
+const void *fast_kernel_fp16x3(int log2n, int mode, int tb, int groups);
+const void *fast_kernel_bf16x3(int log2n, int mode, int tb, int groups);
+const void *fast_kernel_bf16x6(int log2n, int mode, int tb, int groups);
+const void *generic_kernel_fp16x3(int log2n, bool pre, bool gen);
+const void *generic_kernel_bf16x3(int log2n, bool pre, bool gen);
+const void *generic_kernel_bf16x6(int log2n, bool pre, bool gen);
 
 LocalLaunch local_fft_geometry(const LocalPass &p);
 hipError_t local_fft_prepare();  // raises the dynamic-LDS limit of every kernel once

@@ -81,7 +81,8 @@ const char *paco_last_error(void) { return g_last_error.c_str(); }
 
 paco_status paco_plan_validate(int64_t N1, int64_t N2, int64_t p, int32_t b, paco_dtype dt)
 {
-    if (dt != PACO_C64) return fail(PACO_ERR_INVALID_ARG, "unknown dtype");
+    if (dt != PACO_C64 && dt != PACO_C64_MFMA_FP16X3 && dt != PACO_C64_MFMA_BF16X3 && dt != PACO_C64_MFMA_BF16X6)
+        return fail(PACO_ERR_INVALID_ARG, "unknown dtype");
     const int t = ilog2_exact(b);
     if (b < 2 || t < 1) return fail(PACO_ERR_NOT_POWER_OF_B, "b must be 2^t with t >= 1");
     const int l1 = ilog2_exact(N1), l2 = ilog2_exact(N2);
@@ -204,6 +205,7 @@ paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p
             const int want = std::atoi(ev);
             if (log2n >= 10 && want >= 0 && (int64_t(1) << want) <= ncols) q.log2T = want;
         }
+        q.prec = int32_t(dt);  // paco_dtype values are the butterfly arithmetic codes
         q.stw = d_stw + stw_off[log2n];
         q.tw = d_tw;
         q.log2L = P->lL;
@@ -290,6 +292,7 @@ paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p
             int g = dflt;
             if (const char *e = std::getenv(env)) g = e[0] - '0';
             if (g < 1 || g > 3 || q.log2n < 10 || q.log2T < 1 || q.no_fast) g = 1;
+            if (g == 3 && q.prec != 0) g = 2;  // the split MFMA forms have no wide tile
             if (g == 3) {
                 if ((int64_t(1) << (q.log2T + 1)) > q.ncols) g = 2;
                 else q.log2T += 1;  // twice as many columns per tile
@@ -351,6 +354,8 @@ paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p
         desc += " ]";
     }
     if (P->fused) desc = "fused[phase1 -> packed transposed slab, phase2 row unpack+twiddle] " + desc;
+    static const char *kPrecName[] = {"fp32", "fp16x3", "bf16x3", "bf16x6"};
+    desc += std::string(" prec=") + kPrecName[int(dt)];
     P->desc = desc;
     *plan = P;
     return PACO_OK;

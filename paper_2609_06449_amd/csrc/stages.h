@@ -134,6 +134,174 @@ struct Ctx {
     bool act;                  // runtime tile width: this thread owns butterflies (tid < nt)
 };
 
+// ---- split-precision MFMA form of the radix-16 butterflies -----------------
+// A radix-16 butterfly y = W x, W[m][k] = w_16^{-mk}, is one real contraction
+//     [yr; yi] = [[Wr, -Wi], [Wi, Wr]] [xr; xi]          (K = 32),
+// so the butterflies of 16 columns are one v_mfma_f32_16x16x32 per output
+// half (rows yr, rows yi).  MFMA takes 16-bit operands: each FP32 value is
+// split into 16-bit parts and the partial products are summed in FP32:
+//   FP16x3: x = s * (hi + 2^-11 lo), s a power of two per butterfly (the
+//           butterfly's largest |component| scaled into [1/2, 1)); products
+//           hi*hi + 2^-11 (hi*lo + lo*hi)                   (~22 bits)
+//   BF16x3: x = hi + lo; products hi*hi + hi*lo + lo*hi     (~16 bits)
+//   BF16x6: x = hi + mid + lo; the six products down to 2^-16 (~24 bits).
+// Operand layouts of v_mfma_f32_16x16x32_{f16,bf16} (lane l, i < 8):
+// A[l & 15][8 (l >> 4) + i], B[8 (l >> 4) + i][l & 15]; result D[4 (l >> 4)
+// + i][l & 15], i < 4.  Twiddles stay FP32 (FP64-generated tables).
+enum : int { kPrecFP32 = 0, kPrecFP16x3 = 1, kPrecBF16x3 = 2, kPrecBF16x6 = 3 };
+
+typedef __bf16 mf_bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 mf_f16x8 __attribute__((ext_vector_type(8)));
+typedef float mf_f32x4 __attribute__((ext_vector_type(4)));
+
+// cos(2 pi r / 16) for any integer r: FP64 values rounded once to FP32.
+__device__ __forceinline__ float cos16(int r)
+{
+    const int a = r & 7;
+    const float v = a == 0   ? 1.0f
+                    : a == 1 ? 0.923879532511286756f
+                    : a == 2 ? 0.707106781186547524f
+                    : a == 3 ? 0.382683432365089772f
+                    : a == 4 ? 0.0f
+                    : a == 5 ? -0.382683432365089772f
+                    : a == 6 ? -0.707106781186547524f
+                             : -0.923879532511286756f;
+    return (r & 8) ? -v : v;
+}
+
+// 16-bit parts of 8 values (see above); lo parts of FP16 carry 2^11.
+template <int PREC>
+struct MfSplit {
+    using T = mf_bf16x8;
+    T h, m, l;
+};
+template <>
+struct MfSplit<kPrecFP16x3> {
+    using T = mf_f16x8;
+    T h, m, l;
+};
+
+template <int PREC>
+__device__ __forceinline__ MfSplit<PREC> mf_split(const float (&x)[8])
+{
+    MfSplit<PREC> s;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        if constexpr (PREC == kPrecFP16x3) {
+            const _Float16 h = (_Float16)x[i];
+            s.h[i] = h;
+            s.l[i] = (_Float16)((x[i] - (float)h) * 2048.0f);
+        } else {
+            const __bf16 h = (__bf16)x[i];
+            const float r = x[i] - (float)h;
+            s.h[i] = h;
+            if constexpr (PREC == kPrecBF16x6) {
+                const __bf16 m = (__bf16)r;
+                s.m[i] = m;
+                s.l[i] = (__bf16)(r - (float)m);
+            } else {
+                s.l[i] = (__bf16)r;
+            }
+        }
+    }
+    return s;
+}
+
+__device__ __forceinline__ mf_f32x4 mf_mma(mf_bf16x8 a, mf_bf16x8 b, mf_f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ mf_f32x4 mf_mma(mf_f16x8 a, mf_f16x8 b, mf_f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+// A * B from the split products.  Every partial product goes into its own
+// zero accumulator and the partial sums are added in FP32 on the vector ALU,
+// smallest first: chaining them through the MFMA accumulator rounds in a way
+// that does not average out and piles up at the lowest output frequencies
+// (measured at N = 2^24: about 4x larger errors near k = 0 for BF16x6).
+template <int PREC>
+__device__ __forceinline__ mf_f32x4 mf_product(const MfSplit<PREC> &a, const MfSplit<PREC> &b)
+{
+    const mf_f32x4 z = {0.f, 0.f, 0.f, 0.f};
+    mf_f32x4 d;
+    if constexpr (PREC == kPrecFP16x3) {
+        const mf_f32x4 c1 = mf_mma(a.l, b.h, z), c2 = mf_mma(a.h, b.l, z), m = mf_mma(a.h, b.h, z);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) d[i] = __builtin_fmaf(c1[i] + c2[i], 1.0f / 2048.0f, m[i]);
+    } else if constexpr (PREC == kPrecBF16x6) {
+        const mf_f32x4 p1 = mf_mma(a.l, b.h, z), p2 = mf_mma(a.h, b.l, z), p3 = mf_mma(a.m, b.m, z),
+                       p4 = mf_mma(a.m, b.h, z), p5 = mf_mma(a.h, b.m, z), p6 = mf_mma(a.h, b.h, z);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) d[i] = p6[i] + ((p4[i] + p5[i]) + ((p1[i] + p2[i]) + p3[i]));
+    } else {
+        const mf_f32x4 p1 = mf_mma(a.l, b.h, z), p2 = mf_mma(a.h, b.l, z), p3 = mf_mma(a.h, b.h, z);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) d[i] = p3[i] + (p1[i] + p2[i]);
+    }
+    return d;
+}
+
+// The 64 butterflies held by one wave (lane l: the 16 inputs u[0..15] of its
+// own butterfly, natural order) become their DFTs, in place.  scr is the
+// wave's private 1024-item LDS scratch: row b (butterfly of lane b) holds
+// item r at b*16 + (r ^ (b & 15)), which spreads the lanes of every access
+// over the banks.
+template <int PREC>
+__device__ __forceinline__ void mfma_dft16(float2 *u, float2 *scr, int lane)
+{
+    const int n = lane & 15, kb = lane >> 4;
+    // A operands: row m = n of [Wr, -Wi] (yr) and [Wi, Wr] (yi), columns k = 8 kb + i
+    float ar[8], ai[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int k = 8 * kb + i;
+        if (kb < 2) {
+            ar[i] = cos16(n * k);           //  Wr =  cos
+            ai[i] = -cos16(n * k + 12);     //  Wi = -sin
+        } else {
+            ar[i] = cos16(n * (k - 16) + 12);  // -Wi =  sin
+            ai[i] = cos16(n * (k - 16));       //  Wr
+        }
+    }
+    const MfSplit<PREC> Ar = mf_split<PREC>(ar), Ai = mf_split<PREC>(ai);
+    int e = 0;
+    if constexpr (PREC == kPrecFP16x3) {
+        float amax = 0.f;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) amax = fmaxf(amax, fmaxf(fabsf(u[r].x), fabsf(u[r].y)));
+        if (amax > 0.f) (void)frexpf(amax, &e);  // amax * 2^-e in [1/2, 1)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) u[r] = make_float2(ldexpf(u[r].x, -e), ldexpf(u[r].y, -e));
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) scr[lane * 16 + (r ^ n)] = u[r];
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int G = 0; G < 4; ++G) {
+        const int b = 16 * G + n;
+        float x[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const float2 q = scr[b * 16 + ((8 * (kb & 1) + i) ^ n)];
+            x[i] = kb < 2 ? q.x : q.y;
+        }
+        const MfSplit<PREC> B = mf_split<PREC>(x);
+        const mf_f32x4 yr = mf_product<PREC>(Ar, B), yi = mf_product<PREC>(Ai, B);
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int i = 0; i < 4; ++i) scr[b * 16 + ((4 * kb + i) ^ n)] = make_float2(yr[i], yi[i]);
+    }
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int m = 0; m < 16; ++m) u[m] = scr[lane * 16 + (m ^ n)];
+    if constexpr (PREC == kPrecFP16x3) {
+#pragma unroll
+        for (int m = 0; m < 16; ++m) u[m] = make_float2(ldexpf(u[m].x, e), ldexpf(u[m].y, e));
+    }
+}
+
 // Stage S of the Stockham sequence on H column groups.  v[h*EG + i*R + r]
 // is operand r of butterfly i of group h; butterfly id g = tid + i*nt of a
 // group covers column g mod TG and index j = g / TG (TG columns per group);
@@ -142,7 +310,7 @@ struct Ctx {
 // reversed output rows (Phase I), 1 natural output rows (Phase III), 2 the
 // transposed natural output (row = column, n items per row; Phase I of the
 // fused pipeline).
-template <int LOG2N, int S, int EG, int LT, int MODE, int TB, bool GEN, int H, bool COH = false>
+template <int LOG2N, int S, int EG, int LT, int MODE, int TB, bool GEN, int H, bool COH = false, int PREC = kPrecFP32>
 __device__ __forceinline__ void run_stage(float2 (&v)[H * EG], const Ctx &c)
 {
     constexpr int LR = stage_log2radix(LOG2N, S);
@@ -157,6 +325,8 @@ __device__ __forceinline__ void run_stage(float2 (&v)[H * EG], const Ctx &c)
     // butterflies; with a runtime one the threads from nt on only take part
     // in the barriers
     const bool act = LT >= 0 || c.act;
+    // radix-16 stages of the split-precision forms run on MFMA
+    constexpr bool MF = PREC != kPrecFP32 && LR == 4;
 
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
@@ -178,8 +348,21 @@ __device__ __forceinline__ void run_stage(float2 (&v)[H * EG], const Ctx &c)
                 for (int h = 0; h < H; ++h) v[h * EG + i * R + r] = cmul(v[h * EG + i * R + r], w);
             }
         }
+        if constexpr (!MF) {
 #pragma unroll
-        for (int h = 0; h < H; ++h) dft_regs<LR>(&v[h * EG + i * R]);
+            for (int h = 0; h < H; ++h) dft_regs<LR>(&v[h * EG + i * R]);
+        }
+    }
+    if constexpr (MF) {
+        // the exchange buffer serves as the waves' scratch (1024 items each;
+        // the tile has at least 16 items per thread): first every wave has
+        // read its inputs out of it
+        if constexpr (S > 0) __syncthreads();
+        float2 *scr = c.lds + ((c.tid >> 6) << 10);
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+#pragma unroll
+            for (int h = 0; h < H; ++h) mfma_dft16<PREC>(&v[h * EG + i * R], scr, c.tid & 63);
     }
     if constexpr (!last) {
         constexpr int LR2 = stage_log2radix(LOG2N, S + 1);
@@ -188,7 +371,7 @@ __device__ __forceinline__ void run_stage(float2 (&v)[H * EG], const Ctx &c)
         constexpr int LNR2 = LOG2N - LR2;
 #pragma unroll
         for (int h = 0; h < H; ++h) {
-            if (S > 0 || h > 0) __syncthreads();  // the previous LDS contents were consumed
+            if (S > 0 || h > 0 || MF) __syncthreads();  // the previous LDS contents were consumed
             if (act) {
 #pragma unroll
                 for (int i = 0; i < NB; ++i) {
@@ -212,7 +395,7 @@ __device__ __forceinline__ void run_stage(float2 (&v)[H * EG], const Ctx &c)
                 }
             }
         }
-        run_stage<LOG2N, S + 1, EG, LT, MODE, TB, GEN, H, COH>(v, c);
+        run_stage<LOG2N, S + 1, EG, LT, MODE, TB, GEN, H, COH, PREC>(v, c);
     } else {
         // last stage: j < n/R = 2^LNS, outputs are the natural-order rows k = j + r*2^LNS.
         if (!act) return;
@@ -308,11 +491,12 @@ constexpr int fast_threads(int l, int h, int eg)
 // traffic and arithmetic.
 // EG = 32 (with H = 2) doubles the tile width: 512 threads hold 64 items
 // each (two waves per SIMD, 256 VGPRs of budget).
-// COH: device-coherent result stores (see st2).
+// COH: device-coherent result stores (see st2).  PREC: arithmetic of the
+// radix-16 butterflies (FP32 VALU, or one of the split MFMA forms).
 // LT = log2 of the tile's columns; the caller launches exactly
 // 2^(LOG2N + LT - (H == 2)) / EG threads per tile.  srcm/dstm: the matrix
 // (row length ld items); col0: the tile's first column.
-template <int LOG2N, int MODE, int TB, int H, int EG, int LT, bool COH = false>
+template <int LOG2N, int MODE, int TB, int H, int EG, int LT, bool COH = false, int PREC = kPrecFP32>
 __device__ __forceinline__ void fast_tile(const float2 *srcm, float2 *dstm, uint32_t ld, int64_t col0,
                                           const float2 *stw, float2 *smem, int tid)
 {
@@ -367,7 +551,7 @@ __device__ __forceinline__ void fast_tile(const float2 *srcm, float2 *dstm, uint
     c.out_t = 0;
     c.out_ell = 0;
     c.act = true;
-    run_stage<LOG2N, 0, EG, LTG, MODE, TB, false, H, COH>(v, c);
+    run_stage<LOG2N, 0, EG, LTG, MODE, TB, false, H, COH, PREC>(v, c);
 }
 
 }  // namespace

@@ -22,6 +22,9 @@ PACO_ERR_ALLOC = 6
 PACO_ERR_HIP = 7
 
 PACO_C64 = 0
+PACO_C64_MFMA_FP16X3 = 1
+PACO_C64_MFMA_BF16X3 = 2
+PACO_C64_MFMA_BF16X6 = 3
 
 PACO_NO_TWIDDLE = 1
 PACO_PACKED = 2
