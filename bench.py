@@ -206,6 +206,69 @@ def bench_batched(steps: int, warmup: int):
     return rec
 
 
+PRECISION_WORKLOADS = [  # N = 2^24 and 2^26, |x| = 10^U[-4,4], arg x ~ U[0, 2 pi), seed 5
+    dict(name="2^24", N1=4096, N2=4096, p=64, b=16),
+    dict(name="2^26", N1=4096, N2=1 << 14, p=64, b=4),
+]
+FORMS = [(0, "fp32"), (1, "fp16x3"), (2, "bf16x3"), (3, "bf16x6")]
+
+
+def bench_precision(steps: int, warmup: int):
+    """Every arithmetic form on the precision workloads: milliseconds per
+    transform (back-to-back launches on one stream, inputs resident).
+    Returns the timing record and the outputs (their error against the FP64
+    oracle is taken in the CPU-baseline leg)."""
+    import numpy as np
+    import torch
+
+    from paper_2609_06449_amd import inputs, paco
+
+    rec, outs = {}, {}
+    sh = torch.cuda.current_stream().cuda_stream
+    for w in PRECISION_WORKLOADS:
+        N = w["N1"] * w["N2"]
+        x = inputs.loguniform(N, seed=5)
+        xd = torch.from_numpy(x).to("cuda")
+        out = torch.empty_like(xd)
+        ws = torch.empty_like(xd)
+        for dt, name in FORMS:
+            plan = paco.Plan(w["N1"], w["N2"], w["p"], w["b"], dt)
+            for _ in range(warmup):
+                plan.execute(xd.data_ptr(), out.data_ptr(), ws.data_ptr(), sh)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                plan.execute(xd.data_ptr(), out.data_ptr(), ws.data_ptr(), sh)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / steps
+            rec.setdefault(name, {})[w["name"]] = dict(
+                ms=round(ms, 4), gflops=round(5.0 * N * math.log2(N) / (ms * 1e-3) / 1e9, 1),
+                hbm_frac_passes=round(16.0 * N * plan.launches / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                launches=plan.launches)
+            outs[(name, w["name"])] = out.cpu().numpy()
+            plan.close()
+        outs[("x", w["name"])] = x
+        del xd, out, ws
+        torch.cuda.empty_cache()
+    return rec, outs
+
+
+def precision_errors(outs):
+    """rel-L2 and max|err|/max|y| of every form against the FP64 oracle."""
+    import numpy as np
+    import oracle
+
+    errs = {}
+    for w in PRECISION_WORKLOADS:
+        ref = oracle.dft(outs[("x", w["name"])].astype(np.complex128))
+        for _, name in FORMS:
+            y = outs[(name, w["name"])]
+            errs.setdefault(name, {})[w["name"]] = dict(
+                rel_l2=float(f"{oracle.rel_l2(y, ref):.4e}"),
+                max_err_over_max_y=float(f"{np.max(np.abs(y - ref)) / np.max(np.abs(ref)):.4e}"))
+    return errs
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -213,6 +276,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--skip-batched", action="store_true")
+    ap.add_argument("--skip-precision", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run plain 256 MiB device copies (traffic-counter calibration)")
@@ -336,12 +400,26 @@ def main():
         torch.cuda.empty_cache()
         rec["batched"] = bench_batched(max(10, args.steps // 10), 3)
 
+    prec_outs = None
+    if not args.skip_precision:
+        if "xd" in locals():
+            del xd, out, ws
+        torch.cuda.empty_cache()
+        rec["precision"], prec_outs = bench_precision(max(10, args.steps // 4), 3)
+        rec["precision"]["workload"] = ("log-uniform |x| = 10^U[-4,4], uniform phase (seed 5); N = 2^24 as 4096 x 4096 "
+                                       "(b = 16) and N = 2^26 as 4096 x 16384 (b = 4); split forms run every "
+                                       "radix-16 butterfly on MFMA")
+
     if not args.skip_cpu_baseline:
         import oracle
 
         ref, cb = cpu_baseline(x, N, args.cpu_budget)
         rec["cpu_baseline"] = cb
         rec["rel_l2_vs_oracle"] = float(oracle.rel_l2(y, ref))
+        if prec_outs is not None:
+            for name, by_w in precision_errors(prec_outs).items():
+                for wname, e in by_w.items():
+                    rec["precision"][name][wname].update(e)
     else:
         rec["cpu_baseline"] = None
     print(json.dumps(rec), flush=True)
