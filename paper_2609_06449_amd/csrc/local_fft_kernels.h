@@ -86,6 +86,17 @@ __global__ __launch_bounds__(fast_threads(LOG2N, H, EG)) void local_fft_fast_ker
     fast_tile<LOG2N, MODE, TB, H, EG, LT, false, PREC>(P.src, P.dst, uint32_t(P.ld), col0, P.stw, smem, threadIdx.x);
 }
 
+// Single-pass tile of a 16^s-point transform with every butterfly on MFMA in
+// the operand layout (the split forms' fast kernel for those lengths).
+template <int LOG2N, int MODE, int TB, int PREC>
+__global__ __launch_bounds__(fast_threads(LOG2N, 1, 16)) void local_fft_mf_kernel(LocalPass P)
+{
+    constexpr int LT = fast_tile_log2T(LOG2N, 1, 16);
+    extern __shared__ float2 smem[];
+    const int64_t col0 = tile_order(blockIdx.x, gridDim.x) << LT;
+    mf_tile<LOG2N, MODE, TB, PREC>(P.src, P.dst, uint32_t(P.ld), col0, P.stw, smem, threadIdx.x);
+}
+
 template <int L, bool PRE, bool GEN, int PREC>
 const void *kptr()
 {
@@ -120,6 +131,10 @@ const void *fast_for_tb(int mode)
     if constexpr (L % TB != 0 || (H == 2 && L < 10) || (L < 4 && EG != (1 << L)) || (L >= 4 && EG < 16) ||
                   (EG == 32 && H != 2) || (EG == 32 && PREC != kPrecFP32)) {
         return nullptr;
+    } else if constexpr (PREC != kPrecFP32 && L % 4 == 0 && H == 1 && EG == 16) {
+        if (mode == 2) return TB == 1 ? reinterpret_cast<const void *>(&local_fft_mf_kernel<L, 2, 1, PREC>) : nullptr;
+        return mode == 0 ? reinterpret_cast<const void *>(&local_fft_mf_kernel<L, 0, TB, PREC>)
+                         : reinterpret_cast<const void *>(&local_fft_mf_kernel<L, 1, TB, PREC>);
     } else {
         if (mode == 2) return TB == 1 ? reinterpret_cast<const void *>(&local_fft_fast_kernel<L, 2, 1, H, EG, PREC>) : nullptr;
         return mode == 0 ? reinterpret_cast<const void *>(&local_fft_fast_kernel<L, 0, TB, H, EG, PREC>)

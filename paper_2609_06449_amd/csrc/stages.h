@@ -216,30 +216,29 @@ __device__ __forceinline__ mf_f32x4 mf_mma(mf_f16x8 a, mf_f16x8 b, mf_f32x4 c)
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
 }
 
-// A * B from the split products.  Every partial product goes into its own
-// zero accumulator and the partial sums are added in FP32 on the vector ALU,
-// smallest first: chaining them through the MFMA accumulator rounds in a way
-// that does not average out and piles up at the lowest output frequencies
-// (measured at N = 2^24: about 4x larger errors near k = 0 for BF16x6).
+// A * B from the split products.  The products that involve a low part are
+// about 2^-8 (BF16) or 2^-11 (FP16) of the result: they are chained through
+// one MFMA accumulator, where the hardware's summation rounding is negligible
+// at their size.  hi*hi goes into its own accumulator and the two are added
+// in FP32 on the vector ALU: chaining hi*hi as well rounded in a way that did
+// not average out and piled up at the lowest output frequencies (measured at
+// N = 2^24: about 4x larger errors near k = 0 for BF16x6).
 template <int PREC>
 __device__ __forceinline__ mf_f32x4 mf_product(const MfSplit<PREC> &a, const MfSplit<PREC> &b)
 {
     const mf_f32x4 z = {0.f, 0.f, 0.f, 0.f};
-    mf_f32x4 d;
-    if constexpr (PREC == kPrecFP16x3) {
-        const mf_f32x4 c1 = mf_mma(a.l, b.h, z), c2 = mf_mma(a.h, b.l, z), m = mf_mma(a.h, b.h, z);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) d[i] = __builtin_fmaf(c1[i] + c2[i], 1.0f / 2048.0f, m[i]);
-    } else if constexpr (PREC == kPrecBF16x6) {
-        const mf_f32x4 p1 = mf_mma(a.l, b.h, z), p2 = mf_mma(a.h, b.l, z), p3 = mf_mma(a.m, b.m, z),
-                       p4 = mf_mma(a.m, b.h, z), p5 = mf_mma(a.h, b.m, z), p6 = mf_mma(a.h, b.h, z);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) d[i] = p6[i] + ((p4[i] + p5[i]) + ((p1[i] + p2[i]) + p3[i]));
-    } else {
-        const mf_f32x4 p1 = mf_mma(a.l, b.h, z), p2 = mf_mma(a.h, b.l, z), p3 = mf_mma(a.h, b.h, z);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) d[i] = p3[i] + (p1[i] + p2[i]);
+    mf_f32x4 small = mf_mma(a.l, b.h, z);
+    small = mf_mma(a.h, b.l, small);
+    if constexpr (PREC == kPrecBF16x6) {
+        small = mf_mma(a.m, b.m, small);
+        small = mf_mma(a.m, b.h, small);
+        small = mf_mma(a.h, b.m, small);
     }
+    const mf_f32x4 main = mf_mma(a.h, b.h, z);
+    mf_f32x4 d;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        d[i] = PREC == kPrecFP16x3 ? __builtin_fmaf(small[i], 1.0f / 2048.0f, main[i]) : main[i] + small[i];
     return d;
 }
 
@@ -552,6 +551,157 @@ __device__ __forceinline__ void fast_tile(const float2 *srcm, float2 *dstm, uint
     c.out_ell = 0;
     c.act = true;
     run_stage<LOG2N, 0, EG, LTG, MODE, TB, false, H, COH, PREC>(v, c);
+}
+
+// One column tile of a single-pass transform of n = 16^s points (s <= 3)
+// whose butterflies all run on MFMA, in the operand layout throughout: a
+// wave owns 64 butterflies as four groups of 16, and lane l (column n = l & 15,
+// K slice kb = l >> 4) holds, for each group, only its 8 real MFMA operands
+// (components 8 (kb & 1) .. +8 of the real part for kb < 2, of the imaginary
+// part otherwise) and afterwards the 4 outputs m = 4 kb .. +4 of its column.
+// Stage-0 operands are read straight from HBM rows, later ones from the
+// exchange buffer; outputs go straight to their Stockham positions with the
+// next stage's twiddle applied (or to HBM rows after the last stage), so a
+// stage costs the same LDS traffic as an FP32 stage.  The tile is n x 2^LT
+// columns with one 16-item butterfly per thread and stage (H = 1, EG = 16).
+template <int LOG2N, int MODE, int TB, int PREC>
+__device__ __forceinline__ void mf_tile(const float2 *srcm, float2 *dstm, uint32_t ld, int64_t col0,
+                                        const float2 *stw, float2 *smem, int tid)
+{
+    static_assert(LOG2N % 4 == 0 && LOG2N >= 4 && LOG2N <= 12, "radix-16 stages only");
+    constexpr int NS = LOG2N / 4;
+    constexpr int LT = fast_log2T(LOG2N);
+    constexpr int Tm = (1 << LT) - 1;
+    constexpr int NT = (1 << (LOG2N + LT)) / 16;
+    constexpr int LNR = LOG2N - 4;  // input k of a butterfly: row j + k 2^LNR
+    constexpr int TWN = stage_tw_total(LOG2N);
+    float2 *twl = smem;
+    float2 *lds = smem + ((TWN + 63) & ~63);
+    const int lane = tid & 63, n = lane & 15, kb = lane >> 4, wbase = (tid >> 6) << 6;
+    const int comp = kb >> 1, half = kb & 1;  // real (0) or imaginary (1) part; first or second 8 inputs
+    const char *src = reinterpret_cast<const char *>(srcm + col0);
+    char *dst = reinterpret_cast<char *>(MODE == 2 ? dstm + (col0 << LOG2N) : dstm + col0);
+    const uint32_t ld8 = ld * 8u;
+
+    // A operands: row m = n of [Wr, -Wi] (yr) and [Wi, Wr] (yi), columns 8 kb + i
+    float ar[8], ai[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int k = 8 * kb + i;
+        if (kb < 2) {
+            ar[i] = cos16(n * k);
+            ai[i] = -cos16(n * k + 12);
+        } else {
+            ar[i] = cos16(n * (k - 16) + 12);
+            ai[i] = cos16(n * (k - 16));
+        }
+    }
+    const MfSplit<PREC> Ar = mf_split<PREC>(ar), Ai = mf_split<PREC>(ai);
+
+    // stage 0 operands straight from HBM rows (one component per lane)
+    float xin[4][8];
+#pragma unroll
+    for (int G = 0; G < 4; ++G) {
+        const int g = wbase + 16 * G + n;
+        const int t = g & Tm, j = g >> LT;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const uint32_t jj = uint32_t(j + ((8 * half + i) << LNR));
+            const uint32_t row = MODE == 1 ? uint32_t(digrev<false>(jj, TB, LOG2N / TB)) : jj;
+            xin[G][i] = *reinterpret_cast<const float *>(src + row * ld8 + uint32_t(t) * 8u + uint32_t(comp) * 4u);
+        }
+    }
+    copy_twiddles(twl, stw, TWN, tid, NT);  // after the data loads are issued
+
+    float2 o[4][4];  // outputs of this lane: group G, m = 4 kb + i
+#pragma unroll
+    for (int S = 0; S < NS; ++S) {
+        const int LNS = 4 * S;
+        // Butterfly g of a stage is (column t, index j); any assignment works
+        // as long as one stage uses one.  The last stage of the transposed
+        // store (MODE 2) takes j fastest, so each store instruction writes 16
+        // consecutive outputs of a column (128-byte runs); elsewhere t is
+        // fastest (neighbouring columns of a row are adjacent in HBM and LDS).
+        const bool jfast = MODE == 2 && S == NS - 1 && S > 0;
+#pragma unroll
+        for (int G = 0; G < 4; ++G) {
+            if (S > 0) {
+                // operands of stage S out of the exchange buffer (already twiddled)
+                const int g = wbase + 16 * G + n;
+                const int t = jfast ? g >> LNR : g & Tm, j = jfast ? g & ((1 << LNR) - 1) : g >> LT;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int row = j + ((8 * half + i) << LNR);
+                    xin[G][i] = reinterpret_cast<const float *>(lds + lpad((row << LT) + t))[comp];
+                }
+            }
+            int e = 0;
+            if constexpr (PREC == kPrecFP16x3) {
+                // per-butterfly power-of-two scale: the column's 32 reals sit in
+                // lanes n, n + 16, n + 32, n + 48
+                float amax = 0.f;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) amax = fmaxf(amax, fabsf(xin[G][i]));
+                amax = fmaxf(amax, __shfl_xor(amax, 16));
+                amax = fmaxf(amax, __shfl_xor(amax, 32));
+                if (amax > 0.f) (void)frexpf(amax, &e);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) xin[G][i] = ldexpf(xin[G][i], -e);
+            }
+            const MfSplit<PREC> B = mf_split<PREC>(xin[G]);
+            const mf_f32x4 yr = mf_product<PREC>(Ar, B);
+            const mf_f32x4 yi = mf_product<PREC>(Ai, B);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                o[G][i] = make_float2(yr[i], yi[i]);
+                if constexpr (PREC == kPrecFP16x3) o[G][i] = make_float2(ldexpf(o[G][i].x, e), ldexpf(o[G][i].y, e));
+            }
+        }
+        if (S + 1 < NS) {
+            // outputs to the exchange buffer, scaled by the next stage's twiddle
+            const int LNS2 = LNS + 4;
+            const int OFF = stage_tw_offset(LOG2N, S + 1);
+            const int LOW = stage_lo_width(LOG2N, S + 1), HIW = stage_hi_width(LOG2N, S + 1);
+            __syncthreads();  // stage S's operands are read (and the twiddle table is in LDS)
+#pragma unroll
+            for (int G = 0; G < 4; ++G) {
+                const int g = wbase + 16 * G + n;
+                const int t = g & Tm, j = g >> LT;
+                const int idxD = ((j >> LNS) << (LNS + 4)) + (j & ((1 << LNS) - 1));
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int pos = idxD + ((4 * kb + i) << LNS);
+                    const int r2 = pos >> LNR, k2 = (pos & ((1 << LNR) - 1)) & ((1 << LNS2) - 1);
+                    float2 w = make_float2(1.f, 0.f);
+                    if (r2 > 0) {
+                        w = twl[OFF + (r2 - 1) * LOW + (k2 & (LOW - 1))];
+                        if (HIW > 0) w = cmul(w, twl[OFF + 15 * LOW + (r2 - 1) * HIW + (k2 >> 4)]);
+                    }
+                    lds[lpad((pos << LT) + t)] = r2 > 0 ? cmul(o[G][i], w) : o[G][i];
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // last stage: output k = j + m 2^(LOG2N - 4) of every butterfly to its HBM row
+    constexpr bool jfast_last = MODE == 2 && NS > 1;
+#pragma unroll
+    for (int G = 0; G < 4; ++G) {
+        const int g = wbase + 16 * G + n;
+        const int t = jfast_last ? g >> LNR : g & Tm, j = jfast_last ? g & ((1 << LNR) - 1) : g >> LT;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t k = uint32_t(j + ((4 * kb + i) << (LOG2N - 4)));
+            uint32_t off;
+            if constexpr (MODE == 2)
+                off = (uint32_t(t) << (LOG2N + 3)) + k * 8u;
+            else if constexpr (MODE == 0)
+                off = uint32_t(digrev<false>(k, TB, LOG2N / TB)) * ld8 + uint32_t(t) * 8u;
+            else
+                off = k * ld8 + uint32_t(t) * 8u;
+            st2<false>(dst + off, o[G][i]);
+        }
+    }
 }
 
 }  // namespace
