@@ -253,6 +253,49 @@ def bench_precision(steps: int, warmup: int):
     return rec, outs
 
 
+LARGE_WORKLOADS = [  # the full-HBM-scale shapes: N = 2^28 (2 GiB per buffer), N(0,1) inputs
+    dict(name="2^28 square", N1=1 << 14, N2=1 << 14, p=256, b=4, seed=3),
+    dict(name="2^28 non-square", N1=1 << 13, N2=1 << 15, p=128, b=2, seed=4),
+]
+
+
+def bench_large(steps: int, warmup: int):
+    """The N = 2^28 shapes (two on-chip passes per local phase: 5 HBM passes):
+    milliseconds per transform and the fraction of the 5-pass roofline.  Inputs
+    are drawn on the device from a seeded generator (timing only; their
+    values are checked against the oracle in the tests)."""
+    import torch
+
+    from paper_2609_06449_amd import paco
+
+    rec = {}
+    sh = torch.cuda.current_stream().cuda_stream
+    for w in LARGE_WORKLOADS:
+        N = w["N1"] * w["N2"]
+        gen = torch.Generator(device="cuda").manual_seed(w["seed"])
+        xd = torch.randn(N, dtype=torch.complex64, device="cuda", generator=gen)
+        out = torch.empty_like(xd)
+        ws = torch.empty_like(xd)
+        plan = paco.Plan(w["N1"], w["N2"], w["p"], w["b"])
+        for _ in range(warmup):
+            plan.execute(xd.data_ptr(), out.data_ptr(), ws.data_ptr(), sh)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.execute(xd.data_ptr(), out.data_ptr(), ws.data_ptr(), sh)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        rec[w["name"]] = dict(N1=w["N1"], N2=w["N2"], p=w["p"], b=w["b"], ms=round(ms, 4),
+                              gflops=round(5.0 * N * math.log2(N) / (ms * 1e-3) / 1e9, 1),
+                              hbm_frac_passes=round(16.0 * N * plan.launches / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                              hbm_frac_3pass=round(48.0 * N / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                              launches=plan.launches)
+        plan.close()
+        del xd, out, ws
+        torch.cuda.empty_cache()
+    return rec
+
+
 def precision_errors(outs):
     """rel-L2 and max|err|/max|y| of every form against the FP64 oracle."""
     import numpy as np
@@ -277,6 +320,7 @@ def main():
     ap.add_argument("--skip-cpu-baseline", action="store_true")
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-precision", action="store_true")
+    ap.add_argument("--skip-large", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run plain 256 MiB device copies (traffic-counter calibration)")
@@ -399,6 +443,12 @@ def main():
         del xd, out, ws
         torch.cuda.empty_cache()
         rec["batched"] = bench_batched(max(10, args.steps // 10), 3)
+
+    if not args.skip_large:
+        if "xd" in locals():
+            del xd, out, ws
+        torch.cuda.empty_cache()
+        rec["large"] = bench_large(max(5, args.steps // 20), 2)
 
     prec_outs = None
     if not args.skip_precision:
