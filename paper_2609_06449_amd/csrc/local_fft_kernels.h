@@ -135,6 +135,7 @@ const void *fast_for_tb(int mode)
         if (mode == 2) return TB == 1 ? reinterpret_cast<const void *>(&local_fft_mf_kernel<L, 2, 1, PREC>) : nullptr;
         return mode == 0 ? reinterpret_cast<const void *>(&local_fft_mf_kernel<L, 0, TB, PREC>)
                          : reinterpret_cast<const void *>(&local_fft_mf_kernel<L, 1, TB, PREC>);
+
     } else {
         if (mode == 2) return TB == 1 ? reinterpret_cast<const void *>(&local_fft_fast_kernel<L, 2, 1, H, EG, PREC>) : nullptr;
         return mode == 0 ? reinterpret_cast<const void *>(&local_fft_fast_kernel<L, 0, TB, H, EG, PREC>)

@@ -294,7 +294,7 @@ paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p
             if (g < 1 || g > 3 || q.log2n < 10 || q.log2T < 1 || q.no_fast) g = 1;
             // split MFMA forms: no wide tile; 16^s-point passes use the one-group
             // kernel that keeps the MFMA operand layout throughout
-            if (q.prec != 0) g = q.log2n % 4 == 0 ? 1 : (g == 3 ? 2 : g);
+            if (q.prec != 0 && !q.no_fast) g = q.log2n % 4 == 0 ? 1 : (g == 3 ? 2 : g);
             if (g == 3) {
                 if ((int64_t(1) << (q.log2T + 1)) > q.ncols) g = 2;
                 else q.log2T += 1;  // twice as many columns per tile

@@ -563,14 +563,13 @@ __device__ __forceinline__ void fast_tile(const float2 *srcm, float2 *dstm, uint
 // exchange buffer; outputs go straight to their Stockham positions with the
 // next stage's twiddle applied (or to HBM rows after the last stage), so a
 // stage costs the same LDS traffic as an FP32 stage.  The tile is n x 2^LT
-// columns with one 16-item butterfly per thread and stage (H = 1, EG = 16).
-template <int LOG2N, int MODE, int TB, int PREC>
+// columns with one 16-item butterfly per thread and stage (EG = 16).
+template <int LOG2N, int MODE, int TB, int PREC, int LT = fast_log2T(LOG2N)>
 __device__ __forceinline__ void mf_tile(const float2 *srcm, float2 *dstm, uint32_t ld, int64_t col0,
                                         const float2 *stw, float2 *smem, int tid)
 {
     static_assert(LOG2N % 4 == 0 && LOG2N >= 4 && LOG2N <= 12, "radix-16 stages only");
     constexpr int NS = LOG2N / 4;
-    constexpr int LT = fast_log2T(LOG2N);
     constexpr int Tm = (1 << LT) - 1;
     constexpr int NT = (1 << (LOG2N + LT)) / 16;
     constexpr int LNR = LOG2N - 4;  // input k of a butterfly: row j + k 2^LNR
