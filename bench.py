@@ -401,6 +401,46 @@ def main():
     del flush
     cold_ms = float(np.median(cold))
 
+    y = out.cpu().numpy()  # the three-pass output (out is reused below)
+
+    # ---- two-pass form (Phase III reads the packed buffer, twiddle on load)
+    two, y2 = None, None
+    if plan.has_two_pass:
+        def step2():
+            plan.execute_two_pass(xd.data_ptr(), out.data_ptr(), ws.data_ptr(), sh)
+
+        for _ in range(args.warmup):
+            step2()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step2()
+        torch.cuda.synchronize()
+        ms2 = (time.perf_counter() - t0) * 1e3 / args.steps
+        y2 = out.cpu().numpy()
+        ev2 = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+        for i in range(args.steps):
+            e = ev2[i]
+            e[0].record(stream)
+            plan.execute_stage(1, xd.data_ptr(), ws.data_ptr(), sh, paco.PACO_PACKED)
+            e[1].record(stream)
+            plan.execute_stage(3, ws.data_ptr(), out.data_ptr(), sh, paco.PACO_PACKED)
+            e[2].record(stream)
+        torch.cuda.synchronize()
+        ph2 = np.array([[ev2[i][k].elapsed_time(ev2[i][k + 1]) for k in range(2)] for i in range(args.steps)])
+        ph2_us = ph2.mean(axis=0) * 1e3
+        p3_gbs = 16.0 * N / (ph2_us[1] * 1e-6) / 1e9
+        two = dict(ms_per_step=round(ms2, 5), value=round(5.0 * N * math.log2(N) / (ms2 * 1e-3) / 1e9, 1),
+                   unit="GFLOP/s", speedup_vs_3pass=round(ms_per_step / ms2, 3),
+                   hbm_frac_2pass=round(32.0 * N / (ms2 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                   phase_us=[round(float(v), 2) for v in ph2_us],
+                   phase3_roofline=dict(bound="hbm", achieved=round(p3_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                                        frac=round(p3_gbs / HBM_PEAK_GBS, 4),
+                                        kernel="phase3 local_fft_fast_kernel<12,3,1,2,32>",
+                                        alg_bytes_per_launch=int(16.0 * N)),
+                   note="ablation: two HBM passes (32 B per item) instead of the paper's three; "
+                        "not the headline metric")
+
     if args.calibrate_copy:
         src = torch.empty(1 << 25, dtype=torch.complex64, device=dev)
         dst = torch.empty_like(src)
@@ -409,8 +449,6 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-
-    y = out.cpu().numpy()
 
     # the dominant kernel: the slowest of the three phases (each one launch)
     if fl:  # the kernels of the default (fused) plan for this workload
@@ -438,6 +476,8 @@ def main():
                cold_ms_per_step=round(cold_ms, 5),
                cold_hbm_frac_3pass=round(48.0 * N / (cold_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                plan=plan.description)
+    if two is not None:
+        rec["two_pass"] = two
 
     if not args.skip_batched:
         del xd, out, ws
@@ -466,6 +506,8 @@ def main():
         ref, cb = cpu_baseline(x, N, args.cpu_budget)
         rec["cpu_baseline"] = cb
         rec["rel_l2_vs_oracle"] = float(oracle.rel_l2(y, ref))
+        if y2 is not None:
+            rec["two_pass"]["rel_l2_vs_oracle"] = float(oracle.rel_l2(y2, ref))
         if prec_outs is not None:
             for name, by_w in precision_errors(prec_outs).items():
                 for wname, e in by_w.items():

@@ -77,7 +77,7 @@ typedef enum {
 
 /* paco_execute_stage flags */
 #define PACO_NO_TWIDDLE 1       /* stage 2 only: apply the bare permutation pi_m */
-#define PACO_PACKED 2           /* stages 1, 2: the fused pipeline's Phase-I buffer (below) */
+#define PACO_PACKED 2           /* the fused pipeline's Phase-I buffer (below) */
 
 typedef struct paco_plan_s paco_plan;
 
@@ -119,6 +119,27 @@ paco_status paco_plan_workspace_size(const paco_plan *plan, size_t *bytes);
 paco_status paco_execute(const paco_plan *plan, const void *in, void *out, void *workspace,
                          size_t workspace_bytes, void *stream);
 
+/* The same transform in two HBM passes instead of three (an ablation of the
+ * paper's pass structure, not the paper's schedule).  Phase I writes the
+ * packed buffer workspace[c*N1 + k1] = A[k1, c] as in paco_execute; Phase III
+ * then reads that buffer itself.  Phase III's input-layout read of row
+ * pi_{m2}(j) of Zhat[u, v] = Z[v, pi_{m2}(u)] (the theorem on the fused global
+ * permutation, section 4.2) finds Z[v, j], pi_{m2} being an involution, so
+ * its tile for columns v takes packed rows j in natural order and forms
+ * Z[v, j] = A[v, j] w_N^{-vj} on load.
+ * Twiddle and digit reversal thus happen in registers, and Phase II's HBM
+ * round trip (16 of the 48 bytes per item of the three passes) is gone.
+ * out = y in natural order, as paco_execute.  Arguments, alignment,
+ * workspace and overlap rules as paco_execute (in == out allowed: Phase III
+ * writes out only after Phase I has read all of in).  Needs a fused
+ * PACO_C64 plan whose Phase III is one on-chip pass (N1 <= 2^12);
+ * paco_plan_has_two_pass tells; otherwise PACO_ERR_UNSUPPORTED. */
+paco_status paco_execute_two_pass(const paco_plan *plan, const void *in, void *out, void *workspace,
+                                  size_t workspace_bytes, void *stream);
+
+/* *yes = 1 when paco_execute_two_pass runs for this plan, else 0. */
+paco_status paco_plan_has_two_pass(const paco_plan *plan, int32_t *yes);
+
 /* Runs one phase alone, for stage-wise checks and per-phase timing, always
  * in the paper's layouts unless flags holds PACO_PACKED:
  *   stage 1: src (N1 x N2, x) -> dst (N1 x N2, Phase-I layout Atilde);
@@ -127,9 +148,12 @@ paco_status paco_execute(const paco_plan *plan, const void *in, void *out, void 
  *   stage 2: src (N1 x N2, Atilde; PACO_PACKED: the packed buffer) -> dst
  *            (N2 x N1, Zhat); flags may also hold PACO_NO_TWIDDLE; src and
  *            dst must not overlap
- *   stage 3: src (N2 x N1, Zhat) -> dst (N2 x N1, Y); src == dst allowed
+ *   stage 3: src (N2 x N1, Zhat) -> dst (N2 x N1, Y); src == dst allowed;
+ *            PACO_PACKED: src = the packed buffer, Phase III of
+ *            paco_execute_two_pass (twiddle on load), src == dst allowed
  * Stage 1 also allows src == dst.  PACO_PACKED on a plan that is not fused
- * returns PACO_ERR_UNSUPPORTED. */
+ * (stage 3: that has no two-pass form) returns PACO_ERR_UNSUPPORTED;
+ * PACO_NO_TWIDDLE on stage 1 or 3 returns PACO_ERR_INVALID_ARG. */
 paco_status paco_execute_stage(const paco_plan *plan, int stage, int flags, const void *src,
                                void *dst, void *stream);
 

@@ -81,7 +81,11 @@ int32_t local_fft_fast_mode(const LocalPass &p)
     if (p.pre_tw || p.n_outer != 1 || p.o_in || p.o_out || p.j_in != 1 || p.k_out != 1) return -1;
     if (p.log2T != fast_tile_log2T(p.log2n, p.groups >= 2 ? 2 : 1, p.groups == 3 ? 32 : 16)) return -1;
     int mode = -1, tb = 0;
-    if (p.out_tr) {
+    if (p.top_tw) {
+        if (p.in_ell || p.out_ell || p.out_tr) return -1;
+        mode = 3;
+        tb = 1;
+    } else if (p.out_tr) {
         if (p.in_ell || p.out_ell) return -1;
         mode = 2;
         tb = 1;
@@ -116,7 +120,7 @@ hipError_t local_fft_prepare()
                                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
             if (e != hipSuccess) return e;
         }
-        for (int mode = 0; mode < 3; ++mode)
+        for (int mode = 0; mode < 4; ++mode)
             for (int tb : {1, 2, 4})
                 for (int grp : {1, 2, 3}) {
                 const void *k = fast_kernel(prec, l, mode, tb, grp);
@@ -131,7 +135,7 @@ hipError_t local_fft_prepare()
 hipError_t launch_local_fft(const LocalPass &p, hipStream_t s)
 {
     const int mode = p.no_fast ? -1 : local_fft_fast_mode(p);
-    const void *k = mode >= 0 ? fast_kernel(p.prec, p.log2n, mode, mode == 2 ? 1 : (mode == 0 ? p.out_t : p.in_t), p.groups)
+    const void *k = mode >= 0 ? fast_kernel(p.prec, p.log2n, mode, mode >= 2 ? 1 : (mode == 0 ? p.out_t : p.in_t), p.groups)
                               : kernel_for(p.prec, p.log2n, p.pre_tw != 0, pass_needs_gen(p));
     if (!k) return hipErrorInvalidValue;
     const LocalLaunch g = local_fft_geometry(p);

@@ -83,7 +83,18 @@ __global__ __launch_bounds__(fast_threads(LOG2N, H, EG)) void local_fft_fast_ker
     constexpr int LT = fast_tile_log2T(LOG2N, H, EG);
     extern __shared__ float2 smem[];
     const int64_t col0 = tile_order(blockIdx.x, gridDim.x) << LT;
-    fast_tile<LOG2N, MODE, TB, H, EG, LT, false, PREC>(P.src, P.dst, uint32_t(P.ld), col0, P.stw, smem, threadIdx.x);
+    TopTw top;
+    if constexpr (MODE == 3) {
+        top.hi = P.top_hi;
+        top.lo = P.top_lo;
+        top.cw = P.top_cw;
+        top.cmask = uint32_t(16 * P.ncols - 1);
+        top.nmask = uint32_t((uint64_t(1) << P.top_log2N) - 1);
+        top.lomask = (1u << P.top_log2Lo) - 1;
+        top.lshift = P.top_log2Lo;
+    }
+    fast_tile<LOG2N, MODE, TB, H, EG, LT, false, PREC>(P.src, P.dst, uint32_t(P.ld), col0, P.stw, smem, threadIdx.x,
+                                                       &top);
 }
 
 // Single-pass tile of a 16^s-point transform with every butterfly on MFMA in
@@ -132,11 +143,15 @@ const void *fast_for_tb(int mode)
                   (EG == 32 && H != 2) || (EG == 32 && PREC != kPrecFP32)) {
         return nullptr;
     } else if constexpr (PREC != kPrecFP32 && L % 4 == 0 && H == 1 && EG == 16) {
+        if (mode == 3) return nullptr;
         if (mode == 2) return TB == 1 ? reinterpret_cast<const void *>(&local_fft_mf_kernel<L, 2, 1, PREC>) : nullptr;
         return mode == 0 ? reinterpret_cast<const void *>(&local_fft_mf_kernel<L, 0, TB, PREC>)
                          : reinterpret_cast<const void *>(&local_fft_mf_kernel<L, 1, TB, PREC>);
 
     } else {
+        if (mode == 3)  // the two-pass form's Phase III: FP32 only
+            return (TB == 1 && PREC == kPrecFP32) ? reinterpret_cast<const void *>(&local_fft_fast_kernel<L, 3, 1, H, EG, PREC>)
+                                                  : nullptr;
         if (mode == 2) return TB == 1 ? reinterpret_cast<const void *>(&local_fft_fast_kernel<L, 2, 1, H, EG, PREC>) : nullptr;
         return mode == 0 ? reinterpret_cast<const void *>(&local_fft_fast_kernel<L, 0, TB, H, EG, PREC>)
                          : reinterpret_cast<const void *>(&local_fft_fast_kernel<L, 1, TB, H, EG, PREC>);

@@ -133,6 +133,13 @@ struct LocalPass {
     int32_t out_tr;        // 1: write the output transposed (row = column, n items; fast kernel only)
     int32_t groups;        // fast kernel: 1, or 2 column groups taking turns in LDS
     int32_t prec;          // radix-16 butterflies: 0 FP32 VALU, 1 FP16x3, 2 BF16x3, 3 BF16x6 (MFMA)
+    // top-level twiddle on load (the two-pass form of Phase III): input item
+    // (row j, column v) is scaled by w_N^{-(v j mod N)}, N = 2^top_log2N,
+    // from the two-level tables top_hi / top_lo (split at 2^top_log2Lo) and
+    // top_cw[k] = w_{16 ncols}^{-k}, k < 16 ncols (see TopTw)
+    int32_t top_tw;
+    int32_t top_log2N, top_log2Lo;
+    const float2 *top_hi, *top_lo, *top_cw;
 };
 
 // Phase II: out[pi2(c)*N1 + v] = ws[pi1(v)*N2 + c] * w_N^{-(v*c mod N)}, the

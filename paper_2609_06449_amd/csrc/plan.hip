@@ -57,6 +57,8 @@ struct paco_plan_s {
     MiddlePass mid{};
     bool fused = false;                     // packed Phase-I buffer (see paco_execute)
     LocalPass phase1_packed{};
+    bool two_pass = false;                  // Phase III can read the packed buffer itself
+    LocalPass phase3_two{};
     std::string desc;
 };
 
@@ -156,8 +158,15 @@ paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p
 
     // ---- host tables (FP64-generated, rounded once to FP32) ----------------
     const int64_t L = int64_t(1) << P->lL;
-    std::vector<float2> tw(L), thi, tlo, ttile, stw;
+    std::vector<float2> tw(L), thi, tlo, ttile, stw, tcw;
     for (int64_t r = 0; r < L; ++r) tw[r] = paco::root_neg(r, L);
+    // the two-pass form's column factor w_{16 N1}^{-k} (single-pass Phase III
+    // over at most 2^12 columns: a table of at most 512 KiB)
+    const bool two_pass_tables = dt == PACO_C64 && P->l2 <= paco::kMaxOnChipLog2 && P->l1 <= 12;
+    if (two_pass_tables) {
+        tcw.resize(size_t(16 * N1));
+        for (int64_t k = 0; k < 16 * N1; ++k) tcw[k] = paco::root_neg(k, 16 * N1);
+    }
     paco::middle_tables(P->lN, thi, tlo, ttile);
     int64_t stw_off[paco::kMaxOnChipLog2 + 1];
     if (!paco::stage_tables(stw, stw_off)) {
@@ -169,7 +178,7 @@ paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p
     struct Piece { const void *src; size_t bytes; size_t off; };
     std::vector<Piece> pieces = {{tw.data(), tw.size() * 8, 0},       {thi.data(), thi.size() * 8, 0},
                                  {tlo.data(), tlo.size() * 8, 0},     {ttile.data(), ttile.size() * 8, 0},
-                                 {stw.data(), stw.size() * 8, 0}};
+                                 {stw.data(), stw.size() * 8, 0},     {tcw.data(), tcw.size() * 8, 0}};
     size_t total = 0;
     for (auto &pc : pieces) {
         pc.off = total;
@@ -182,7 +191,8 @@ paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p
     e = hipMalloc(&P->dev_tables, total);
     if (e != hipSuccess) { P->dev_tables = nullptr; delete P; return fail(PACO_ERR_ALLOC, std::string("hipMalloc: ") + hipGetErrorString(e)); }
     std::vector<unsigned char> staging(total, 0);
-    for (auto &pc : pieces) std::memcpy(staging.data() + pc.off, pc.src, pc.bytes);
+    for (auto &pc : pieces)
+        if (pc.bytes) std::memcpy(staging.data() + pc.off, pc.src, pc.bytes);
     e = hipMemcpy(P->dev_tables, staging.data(), total, hipMemcpyHostToDevice);
     if (e != hipSuccess) { (void)hipFree(P->dev_tables); delete P; return hip_fail(e, "hipMemcpy"); }
     auto at = [&](int i) { return static_cast<unsigned char *>(P->dev_tables) + pieces[i].off; };
@@ -191,6 +201,7 @@ paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p
     const float2 *d_tlo = reinterpret_cast<const float2 *>(at(2));
     const float2 *d_ttile = reinterpret_cast<const float2 *>(at(3));
     const float2 *d_stw = reinterpret_cast<const float2 *>(at(4));
+    const float2 *d_tcw = reinterpret_cast<const float2 *>(at(5));
 
     auto base_pass = [&](int64_t ld, int64_t ncols, int log2n) {
         LocalPass q{};
@@ -287,27 +298,26 @@ paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p
     // 1 = one LDS group of T columns; 2 = two groups of T/2 (half the LDS, two
     // workgroups per CU); 3 = two groups of T, a tile twice as wide (512
     // threads with 64 items each).
-    {
-        auto pick = [](LocalPass &q, const char *env, int dflt) {
-            int g = dflt;
-            if (const char *e = std::getenv(env)) g = e[0] - '0';
-            if (g < 1 || g > 3 || q.log2n < 10 || q.log2T < 1 || q.no_fast) g = 1;
-            // split MFMA forms: no wide tile; 16^s-point passes use the one-group
-            // kernel that keeps the MFMA operand layout throughout
-            if (q.prec != 0 && !q.no_fast) g = q.log2n % 4 == 0 ? 1 : (g == 3 ? 2 : g);
-            if (g == 3) {
-                if ((int64_t(1) << (q.log2T + 1)) > q.ncols) g = 2;
-                else q.log2T += 1;  // twice as many columns per tile
-            }
-            q.groups = g;
-            if (g > 1 && paco::local_fft_fast_mode(q) < 0) {  // not a fast pass: plain tile
-                if (g == 3) q.log2T -= 1;
-                q.groups = 1;
-            }
-        };
-        for (auto &q : P->phase1) pick(q, "PACO_GROUPS1", q.log2n >= 12 ? 2 : 1);
-        for (auto &q : P->phase3) pick(q, "PACO_GROUPS3", q.log2n >= 12 ? 3 : 1);
-    }
+    auto pick = [](LocalPass &q, const char *env, int dflt) {
+        int g = dflt;
+        if (const char *e = std::getenv(env)) g = e[0] - '0';
+        if (g < 1 || g > 3 || q.log2n < 10 || q.log2T < 1 || q.no_fast) g = 1;
+        // split MFMA forms: no wide tile; 16^s-point passes use the one-group
+        // kernel that keeps the MFMA operand layout throughout
+        if (q.prec != 0 && !q.no_fast) g = q.log2n % 4 == 0 ? 1 : (g == 3 ? 2 : g);
+        if (g == 3) {
+            if ((int64_t(1) << (q.log2T + 1)) > q.ncols) g = 2;
+            else q.log2T += 1;  // twice as many columns per tile
+        }
+        q.groups = g;
+        if (g > 1 && paco::local_fft_fast_mode(q) < 0) {  // not a fast pass: plain tile
+            if (g == 3) q.log2T -= 1;
+            q.groups = 1;
+        }
+    };
+    for (auto &q : P->phase1) pick(q, "PACO_GROUPS1", q.log2n >= 12 ? 2 : 1);
+    const LocalPass phase3_base = P->phase3[0];
+    for (auto &q : P->phase3) pick(q, "PACO_GROUPS3", q.log2n >= 12 ? 3 : 1);
     // ---- fused pipeline: Phase I writes the packed slab transposed --------
     {
         const char *lay = std::getenv("PACO_LAYOUT");
@@ -320,6 +330,24 @@ paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p
             paco::local_fft_fast_mode(q) == 2) {
             P->fused = true;
             P->phase1_packed = q;
+        }
+    }
+    // ---- two-pass form: Phase III reads the packed buffer in natural row
+    // order and applies the top-level twiddle on load (no Phase-II pass) ----
+    if (P->fused && b3 == 0 && two_pass_tables) {
+        LocalPass q = phase3_base;
+        q.in_t = 0;
+        q.in_ell = 0;
+        q.top_tw = 1;
+        q.top_log2N = P->lN;
+        q.top_log2Lo = P->lLo;
+        q.top_hi = d_thi;
+        q.top_lo = d_tlo;
+        q.top_cw = d_tcw;
+        pick(q, "PACO_GROUPS3", q.log2n >= 12 ? 3 : 1);
+        if (!q.no_fast && paco::local_fft_fast_mode(q) == 3) {
+            P->two_pass = true;
+            P->phase3_two = q;
         }
     }
     for (auto *ph : {&P->phase1, &P->phase3})
@@ -356,6 +384,12 @@ paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p
         desc += " ]";
     }
     if (P->fused) desc = "fused[phase1 -> packed transposed slab, phase2 row unpack+twiddle] " + desc;
+    if (P->two_pass) {
+        const paco::LocalLaunch g = paco::local_fft_geometry(P->phase3_two);
+        std::snprintf(buf, sizeof buf, " two_pass[phase3 twiddle-on-load n=2^%d T=%d wg=%lld thr=%d lds=%zu]",
+                      P->phase3_two.log2n, 1 << P->phase3_two.log2T, (long long)g.tiles, g.threads, g.lds_bytes);
+        desc += buf;
+    }
     static const char *kPrecName[] = {"fp32", "fp16x3", "bf16x3", "bf16x6"};
     desc += std::string(" prec=") + kPrecName[int(dt)];
     P->desc = desc;
@@ -446,6 +480,35 @@ paco_status paco_execute(const paco_plan *plan, const void *in, void *out, void 
     return run_local(plan->phase3, out, out, s);
 }
 
+paco_status paco_execute_two_pass(const paco_plan *plan, const void *in, void *out, void *workspace,
+                                  size_t workspace_bytes, void *stream)
+{
+    if (!plan) return fail(PACO_ERR_INVALID_ARG, "plan is NULL");
+    if (!plan->two_pass)
+        return fail(PACO_ERR_UNSUPPORTED, "two-pass form needs the fused FP32 pipeline with a single-pass Phase III");
+    if (bad_ptr(in) || bad_ptr(out) || bad_ptr(workspace))
+        return fail(PACO_ERR_INVALID_ARG, "in/out/workspace must be non-NULL and 16-byte aligned");
+    const size_t need = size_t(plan->N1) * size_t(plan->N2) * 8;
+    if (workspace_bytes < need) return fail(PACO_ERR_WORKSPACE, "workspace smaller than N1*N2*8 bytes");
+    const size_t wb = reinterpret_cast<uintptr_t>(workspace), ib = reinterpret_cast<uintptr_t>(in),
+                 ob = reinterpret_cast<uintptr_t>(out);
+    if ((wb < ib + need && ib < wb + need) || (wb < ob + need && ob < wb + need))
+        return fail(PACO_ERR_INVALID_ARG, "workspace overlaps in or out");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    paco_status st = run_local({plan->phase1_packed}, in, workspace, s);
+    if (st != PACO_OK) return st;
+    return run_local({plan->phase3_two}, workspace, out, s);
+}
+
+paco_status paco_plan_has_two_pass(const paco_plan *plan, int32_t *yes)
+{
+    if (!yes) return fail(PACO_ERR_INVALID_ARG, "yes out-pointer is NULL");
+    *yes = 0;
+    if (!plan) return fail(PACO_ERR_INVALID_ARG, "plan is NULL");
+    *yes = plan->two_pass ? 1 : 0;
+    return PACO_OK;
+}
+
 paco_status paco_execute_stage(const paco_plan *plan, int stage, int flags, const void *src, void *dst,
                                void *stream)
 {
@@ -454,7 +517,9 @@ paco_status paco_execute_stage(const paco_plan *plan, int stage, int flags, cons
     if (flags & ~(PACO_NO_TWIDDLE | PACO_PACKED)) return fail(PACO_ERR_INVALID_ARG, "unknown flags");
     const bool packed = (flags & PACO_PACKED) != 0;
     if (packed && !plan->fused) return fail(PACO_ERR_UNSUPPORTED, "this plan has no packed Phase-I buffer");
-    if (packed && stage == 3) return fail(PACO_ERR_INVALID_ARG, "PACO_PACKED applies to stages 1 and 2");
+    if (packed && stage == 3 && !plan->two_pass)
+        return fail(PACO_ERR_UNSUPPORTED, "this plan has no two-pass Phase III");
+    if ((flags & PACO_NO_TWIDDLE) && stage != 2) return fail(PACO_ERR_INVALID_ARG, "PACO_NO_TWIDDLE applies to stage 2");
     hipStream_t s = static_cast<hipStream_t>(stream);
     switch (stage) {
     case 1: {
@@ -467,7 +532,7 @@ paco_status paco_execute_stage(const paco_plan *plan, int stage, int flags, cons
         if (a < b + need && b < a + need) return fail(PACO_ERR_INVALID_ARG, "stage 2 src and dst overlap");
         return run_middle(plan, src, dst, (flags & PACO_NO_TWIDDLE) ? 0 : 1, packed, s);
     }
-    case 3: return run_local(plan->phase3, src, dst, s);
+    case 3: return packed ? run_local({plan->phase3_two}, src, dst, s) : run_local(plan->phase3, src, dst, s);
     default: return fail(PACO_ERR_INVALID_ARG, "stage must be 1, 2 or 3");
     }
 }

@@ -478,8 +478,23 @@ constexpr int fast_threads(int l, int h, int eg)
     return (1 << (l + fast_tile_log2T(l, h, eg))) / (h * eg);
 }
 
+// The top-level twiddle w_N^{-v j} that a MODE 3 tile applies on load to the
+// item of column v and row j = j0 + r n/R0 (r < R0, R0 = the first stage's
+// radix), as a product of two FP64-generated FP32 values:
+//   a = w_N^{-(v j0 mod N)} = hi[e >> lshift] * lo[e & lomask], e = v j0 mod N,
+//   c = w_N^{-v r n/R0} = w_{16 N1}^{-v r 16/R0} = cw[v r 16/R0]  (N = N1 n).
+// c depends on the column alone (uniform across a wave when a tile group is
+// one column wide), so each item costs one cached load, not two gathers.
+struct TopTw {
+    const float2 *hi, *lo, *cw;
+    uint32_t nmask, lomask, cmask;
+    int lshift;
+};
+
 // One column tile of a single-pass local transform, the body of the fast
-// kernels.  MODE 0: natural input rows, digit-reversed
+// kernels.  MODE 3: natural input rows scaled by the top-level twiddle on
+// load (TopTw), natural output rows: Phase III of the two-pass form, which
+// reads the packed Phase-I buffer directly.  MODE 0: natural input rows, digit-reversed
 // output rows (Phase I, A = P_pi Omega).  MODE 1: digit-reversed input rows,
 // natural output rows (Phase III, B = Omega P_pi).  MODE 2: natural input
 // rows, output written transposed in natural frequency order (Phase I of the
@@ -497,7 +512,7 @@ constexpr int fast_threads(int l, int h, int eg)
 // (row length ld items); col0: the tile's first column.
 template <int LOG2N, int MODE, int TB, int H, int EG, int LT, bool COH = false, int PREC = kPrecFP32>
 __device__ __forceinline__ void fast_tile(const float2 *srcm, float2 *dstm, uint32_t ld, int64_t col0,
-                                          const float2 *stw, float2 *smem, int tid)
+                                          const float2 *stw, float2 *smem, int tid, const TopTw *top = nullptr)
 {
     constexpr int LTG = LT - (H == 2 ? 1 : 0);         // log2 of the columns of one group
     constexpr int NT = (1 << (LOG2N + LTG)) / EG;
@@ -518,21 +533,35 @@ __device__ __forceinline__ void fast_tile(const float2 *srcm, float2 *dstm, uint
     for (int q = 0; q < NB0; ++q) {
         const int g = tid + q * NT;
         const int t = (g & ((1 << LTG) - 1)) * H, j = g >> LTG;
+        constexpr bool NAT = MODE == 0 || MODE == 2 || MODE == 3;  // natural input rows
         uint32_t base;
-        if constexpr (MODE == 0 || MODE == 2)
+        if constexpr (NAT)
             base = uint32_t(j) * ld8 + uint32_t(t) * 8u;
         else  // row pi(j + r*2^LNR0) = pi(j)*2^LR0 + pi(r)
             base = (drev<TB, LNR0 / TB>(j) << LR0) * ld8 + uint32_t(t) * 8u;
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
-            const uint32_t row_off =
-                (MODE == 0 || MODE == 2) ? (uint32_t(r) << LNR0) * ld8 : uint32_t(crev(r, TB, LR0 / TB)) * ld8;
+            const uint32_t row_off = NAT ? (uint32_t(r) << LNR0) * ld8 : uint32_t(crev(r, TB, LR0 / TB)) * ld8;
             if constexpr (H == 2) {
                 const float4 a = *reinterpret_cast<const float4 *>(src + base + row_off);
                 v[q * R0 + r] = make_float2(a.x, a.y);
                 v[EG + q * R0 + r] = make_float2(a.z, a.w);
             } else {
                 v[q * R0 + r] = *reinterpret_cast<const float2 *>(src + base + row_off);
+            }
+        }
+        if constexpr (MODE == 3) {
+            // item (row j + r 2^LNR0, column col0 + t + h) times w_N^{-(column * row mod N)}
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                const uint32_t col = uint32_t(col0 + t + h);
+                const uint32_t e = (col * uint32_t(j)) & top->nmask;
+                const float2 a = cmul(top->hi[e >> top->lshift], top->lo[e & top->lomask]);
+#pragma unroll
+                for (int r = 0; r < R0; ++r) {
+                    const float2 c = top->cw[(col * uint32_t(r << (4 - LR0))) & top->cmask];
+                    v[h * EG + q * R0 + r] = cmul(v[h * EG + q * R0 + r], cmul(a, c));
+                }
             }
         }
     }
@@ -550,7 +579,7 @@ __device__ __forceinline__ void fast_tile(const float2 *srcm, float2 *dstm, uint
     c.out_t = 0;
     c.out_ell = 0;
     c.act = true;
-    run_stage<LOG2N, 0, EG, LTG, MODE, TB, false, H, COH, PREC>(v, c);
+    run_stage<LOG2N, 0, EG, LTG, MODE == 3 ? 1 : MODE, TB, false, H, COH, PREC>(v, c);
 }
 
 // One column tile of a single-pass transform of n = 16^s points (s <= 3)

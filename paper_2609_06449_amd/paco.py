@@ -32,7 +32,8 @@ PACO_PACKED = 2
 # every symbol include/paco.h declares
 EXPORTED = (
     "paco_plan_validate", "paco_plan_create", "paco_plan_workspace_size", "paco_execute",
-    "paco_execute_stage", "paco_plan_describe", "paco_plan_destroy", "paco_status_string",
+    "paco_execute_stage", "paco_execute_two_pass", "paco_plan_has_two_pass", "paco_plan_describe",
+    "paco_plan_destroy", "paco_status_string",
     "paco_last_error", "paco_batch_plan_create", "paco_batch_workspace_size", "paco_execute_batched",
     "paco_batch_plan_describe", "paco_batch_errors", "paco_batch_plan_destroy",
 )
@@ -64,6 +65,8 @@ def _load() -> ctypes.CDLL:
         "paco_plan_workspace_size": (st, [P, ctypes.POINTER(sz)]),
         "paco_execute": (st, [P, P, P, P, sz, P]),
         "paco_execute_stage": (st, [P, st, st, P, P, P]),
+        "paco_execute_two_pass": (st, [P, P, P, P, sz, P]),
+        "paco_plan_has_two_pass": (st, [P, ctypes.POINTER(i32)]),
         "paco_plan_describe": (st, [P, ctypes.POINTER(i32), ctypes.c_char_p, sz]),
         "paco_plan_destroy": (st, [P]),
         "paco_status_string": (ctypes.c_char_p, [st]),
@@ -128,6 +131,16 @@ def paco_execute_stage(plan: int, stage: int, flags: int, src: int, dst: int, st
     _check(_lib.paco_execute_stage(plan, stage, flags, src, dst, stream), "paco_execute_stage")
 
 
+def paco_execute_two_pass(plan: int, src: int, dst: int, workspace: int, workspace_bytes: int, stream: int = 0):
+    _check(_lib.paco_execute_two_pass(plan, src, dst, workspace, workspace_bytes, stream), "paco_execute_two_pass")
+
+
+def paco_plan_has_two_pass(plan: int) -> bool:
+    yes = ctypes.c_int32()
+    _check(_lib.paco_plan_has_two_pass(plan, ctypes.byref(yes)), "paco_plan_has_two_pass")
+    return bool(yes.value)
+
+
 def paco_plan_describe(plan: int):
     n = ctypes.c_int32()
     buf = ctypes.create_string_buffer(1024)
@@ -147,9 +160,13 @@ class Plan:
         self.handle = paco_plan_create(N1, N2, p, b, dt)
         self.workspace_bytes = paco_plan_workspace_size(self.handle)
         self.launches, self.description = paco_plan_describe(self.handle)
+        self.has_two_pass = paco_plan_has_two_pass(self.handle)
 
     def execute(self, src: int, dst: int, workspace: int, stream: int = 0):
         paco_execute(self.handle, src, dst, workspace, self.workspace_bytes, stream)
+
+    def execute_two_pass(self, src: int, dst: int, workspace: int, stream: int = 0):
+        paco_execute_two_pass(self.handle, src, dst, workspace, self.workspace_bytes, stream)
 
     def execute_stage(self, stage: int, src: int, dst: int, stream: int = 0, flags: int = 0):
         paco_execute_stage(self.handle, stage, flags, src, dst, stream)
