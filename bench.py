@@ -436,7 +436,8 @@ def main():
                    phase_us=[round(float(v), 2) for v in ph2_us],
                    phase3_roofline=dict(bound="hbm", achieved=round(p3_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                                         frac=round(p3_gbs / HBM_PEAK_GBS, 4),
-                                        kernel="phase3 local_fft_fast_kernel<12,3,1,2,32>",
+                                        traffic=load_traffic("local_fft_fast_kernel<12,3,1,2,32,0>"),
+                                        kernel="phase3 local_fft_fast_kernel<12,3,1,2,32,0>",
                                         alg_bytes_per_launch=int(16.0 * N)),
                    note="ablation: two HBM passes (32 B per item) instead of the paper's three; "
                         "not the headline metric")
@@ -452,11 +453,11 @@ def main():
 
     # the dominant kernel: the slowest of the three phases (each one launch)
     if fl:  # the kernels of the default (fused) plan for this workload
-        names = ["phase1 local_fft_fast_kernel<12,2,1,2,16>", "phase2 middle_packed2_kernel<false,true>",
-                 "phase3 local_fft_fast_kernel<12,1,4,2,32>"]
+        names = ["phase1 local_fft_fast_kernel<12,2,1,2,16,0>", "phase2 middle_packed2_kernel<false,true>",
+                 "phase3 local_fft_fast_kernel<12,1,4,2,32,0>"]
     else:
-        names = ["phase1 local_fft_fast_kernel<12,0,4,2,16>", "phase2 middle_kernel<false,true,true>",
-                 "phase3 local_fft_fast_kernel<12,1,4,2,32>"]
+        names = ["phase1 local_fft_fast_kernel<12,0,4,2,16,0>", "phase2 middle_kernel<false,true,true>",
+                 "phase3 local_fft_fast_kernel<12,1,4,2,32,0>"]
     dom = int(np.argmax(ph_us))
     alg_bytes = 16.0 * N  # each phase reads and writes N complex64 items once
     achieved = alg_bytes / (ph_us[dom] * 1e-6) / 1e9
