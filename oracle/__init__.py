@@ -64,7 +64,7 @@ def _load():
     i64 = ctypes.c_int64
     lib.oracle_digit_reverse.restype = i64
     lib.oracle_digit_reverse.argtypes = [i64, i64, ctypes.c_int32]
-    for name in ("oracle_dft_naive", "oracle_fft_radix2", "oracle_dft"):
+    for name in ("oracle_dft_naive", "oracle_fft_radix2", "oracle_dft", "oracle_idft"):
         getattr(lib, name).restype = ctypes.c_int
         getattr(lib, name).argtypes = [P, P, i64]
     lib.oracle_dft_at.restype = ctypes.c_int
@@ -148,6 +148,15 @@ def dft(x) -> np.ndarray:
     y = np.empty_like(x)
     _check(_load().oracle_dft(_ptr(x), _ptr(y), x.size), "dft")
     return y
+
+
+def idft(y) -> np.ndarray:
+    """x = Omega_N^{-1} y = (1/N) sum_k y[k] w_N^{+jk}: the inverse the paper
+    names (sections 1 and 5) for the forward convention of section 2."""
+    y = _c128(y)
+    x = np.empty_like(y)
+    _check(_load().oracle_idft(_ptr(y), _ptr(x), y.size), "idft")
+    return x
 
 
 def dft_at(x, ks) -> np.ndarray:

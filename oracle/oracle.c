@@ -157,15 +157,16 @@ int oracle_dft_at(const double *x, int64_t N, const int64_t *ks, int64_t nk, dou
  * the even- and odd-indexed halves are transformed, then combined with
  * w_n^{-k} = w_N^{-k*(N/n)}.  x is read with stride `xs` (in complex items),
  * y is written contiguously. */
-static void fft_r2_rec(const double *x, int64_t xs, double *y, int64_t n, int64_t N, const roots_t *t)
+static void fft_r2_rec(const double *x, int64_t xs, double *y, int64_t n, int64_t N, const roots_t *t, int pos)
 {
     if (n == 1) { y[0] = x[0]; y[1] = x[1]; return; }
     int64_t h = n / 2;
-    fft_r2_rec(x, 2 * xs, y, h, N, t);             /* even samples -> y[0..h)   */
-    fft_r2_rec(x + 2 * xs, 2 * xs, y + 2 * h, h, N, t); /* odd samples -> y[h..n) */
+    fft_r2_rec(x, 2 * xs, y, h, N, t, pos);             /* even samples -> y[0..h)   */
+    fft_r2_rec(x + 2 * xs, 2 * xs, y + 2 * h, h, N, t, pos); /* odd samples -> y[h..n) */
     for (int64_t k = 0; k < h; ++k) {
         double wr, wi;
         roots_get(t, k * (N / n), &wr, &wi);
+        if (pos) wi = -wi;                           /* w_n^{+k}: the inverse's roots */
         double er = y[2 * k], ei = y[2 * k + 1];
         double orr = y[2 * (k + h)], oi = y[2 * (k + h) + 1];
         double tr = orr * wr - oi * wi, ti = orr * wi + oi * wr;
@@ -181,7 +182,7 @@ int oracle_fft_radix2(const double *x, double *y, int64_t N)
     if (N < 1 || (N & (N - 1))) return -1;
     roots_t t;
     if (roots_init(&t, N)) return -2;
-    fft_r2_rec(x, 1, y, N, N, &t);
+    fft_r2_rec(x, 1, y, N, N, &t, 0);
     roots_free(&t);
     return 0;
 }
@@ -191,6 +192,38 @@ int oracle_dft(const double *x, double *y, int64_t N)
 {
     if (N <= 1024 || (N & (N - 1))) return oracle_dft_naive(x, y, N);
     return oracle_fft_radix2(x, y, N);
+}
+
+/* The inverse DFT x = Omega_N^{-1} y, (Omega_N^{-1})_{j,k} = w_N^{+jk} / N.
+ * The paper names the inverse transform without specifying it (sections 1
+ * and 5, Limitations); this is the textbook definition for its forward
+ * convention of section 2: the naive sum for small N, the same radix-2
+ * recursion with w_n^{+k} above, then the 1/N scale. */
+int oracle_idft(const double *y, double *x, int64_t N)
+{
+    if (N < 1) return -1;
+    roots_t t;
+    if (roots_init(&t, N)) return -2;
+    if (N <= 1024 || (N & (N - 1))) {
+        for (int64_t j = 0; j < N; ++j) {
+            double sr = 0.0, si = 0.0;
+            for (int64_t k = 0; k < N; ++k) {
+                double wr, wi;
+                roots_get(&t, (j * k) % N, &wr, &wi);
+                wi = -wi;                       /* w_N^{+jk} */
+                double yr = y[2 * k], yi = y[2 * k + 1];
+                sr += yr * wr - yi * wi;
+                si += yr * wi + yi * wr;
+            }
+            x[2 * j] = sr;
+            x[2 * j + 1] = si;
+        }
+    } else {
+        fft_r2_rec(y, 1, x, N, N, &t, 1);
+    }
+    for (int64_t j = 0; j < 2 * N; ++j) x[j] /= (double)N;
+    roots_free(&t);
+    return 0;
 }
 
 /* ------------------------------------------------------------------ */

@@ -107,3 +107,35 @@ def test_two_level_root_table_large_n():
     y = oracle.fft_radix2(x)
     y[k0] -= N
     assert np.max(np.abs(y)) < 1e-6 * N
+
+
+# ---- the inverse (oracle.idft): pinned by closed forms, numpy and round trips
+
+@pytest.mark.parametrize("N", [1, 2, 8, 64, 1024, 2048, 1 << 14])
+def test_idft_delta_gives_positive_exponential(N):
+    # y = delta_{k0}  =>  x[j] = exp(+2 pi i j k0 / N) / N  (small N: naive sum, large: radix-2)
+    for k0 in {k for k in (0, 1, N // 3, N - 1) if k < N}:
+        y = np.zeros(N, complex)
+        y[k0] = 1.0
+        j = np.arange(N)
+        want = np.exp(2j * np.pi * ((j * k0) % N) / N) / N
+        assert np.max(np.abs(oracle.idft(y) - want)) < 1e-12 / N
+
+
+@pytest.mark.parametrize("N", [1, 3, 12, 64, 1000, 2048, 1 << 16])
+def test_idft_matches_numpy_ifft(N):
+    y = _rand(N)
+    assert oracle.rel_l2(oracle.idft(y), np.fft.ifft(y)) < 1e-12
+
+
+@pytest.mark.parametrize("N", [16, 1024, 4096, 1 << 15])
+def test_idft_inverts_dft_both_ways(N):
+    x = _rand(N)
+    assert oracle.rel_l2(oracle.idft(oracle.dft(x)), x) < 1e-13
+    assert oracle.rel_l2(oracle.dft(oracle.idft(x)), x) < 1e-13
+
+
+def test_idft_is_not_the_forward_transform():
+    # a sign slip would make idft(y) = dft(y)/N; these differ for N >= 3
+    y = _rand(64)
+    assert oracle.rel_l2(oracle.idft(y), oracle.dft(y) / 64) > 0.5
