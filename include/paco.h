@@ -119,6 +119,27 @@ paco_status paco_plan_workspace_size(const paco_plan *plan, size_t *bytes);
 paco_status paco_execute(const paco_plan *plan, const void *in, void *out, void *workspace,
                          size_t workspace_bytes, void *stream);
 
+/* The inverse transform x = Omega_N^{-1} y, x[j] = (1/N) sum_k y[k] w_N^{+jk}
+ * (the paper names the inverse in sections 1 and 5 without specifying it;
+ * this is the textbook inverse of section 2's convention).  in = y in natural
+ * order, the buffer paco_execute writes; out = x in natural order, the
+ * layout paco_execute reads; the forward plan's arguments, alignment,
+ * workspace and overlap rules apply.
+ *
+ * Ownership.  The forward transform leaves y in the factor-swapped
+ * ownership: output slab q holds columns [q N1/p, (q+1) N1/p) of the N2 x N1
+ * matrix Y (section 2, eq. output-slab-owner).  The inverse runs the PACO
+ * phases on the swapped factorisation N2 x N1 (the plan builds its passes at
+ * creation; a square plan reuses its own), so its input slabs are exactly
+ * those output slabs and its output slabs, columns of the N1 x N2 matrix X,
+ * are exactly the forward input's: the ownership is restored by the inverse
+ * itself, with no further exchange.  The arithmetic is conj(Omega_N conj(y))
+ * / N, the two conjugations and the 1/N scale (a power of two, exact) folded
+ * into Phase I's loads and Phase III's stores: the same launches as
+ * paco_execute.  All dtypes. */
+paco_status paco_execute_inverse(const paco_plan *plan, const void *in, void *out, void *workspace,
+                                 size_t workspace_bytes, void *stream);
+
 /* The same transform in two HBM passes instead of three (an ablation of the
  * paper's pass structure, not the paper's schedule).  Phase I writes the
  * packed buffer workspace[c*N1 + k1] = A[k1, c] as in paco_execute; Phase III

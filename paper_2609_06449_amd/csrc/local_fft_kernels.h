@@ -46,6 +46,10 @@ __global__ __launch_bounds__(1024) void local_fft_kernel(LocalPass P)
             v[q * R0 + r] = *reinterpret_cast<const float2 *>(src + ((orow + m * j_in) * ld8 + uint32_t(t) * 8u));
         }
     }
+    if (P.conj_in) {  // the inverse transform's input map
+#pragma unroll
+        for (int k = 0; k < EG; ++k) v[k].y = -v[k].y;
+    }
     // the stage twiddle table is copied after the data loads are issued, so
     // waiting for it does not delay them
     copy_twiddles(twl, P.stw, TWN, tid, nt);
@@ -74,6 +78,7 @@ __global__ __launch_bounds__(1024) void local_fft_kernel(LocalPass P)
     c.out_t = P.out_t;
     c.out_ell = P.out_ell;
     c.act = true;
+    c.oscale = P.out_scale;
     run_stage<LOG2N, 0, EG, -1, -1, 1, GEN, 1, false, PREC>(v, c);
 }
 
@@ -94,7 +99,7 @@ __global__ __launch_bounds__(fast_threads(LOG2N, H, EG)) void local_fft_fast_ker
         top.lshift = P.top_log2Lo;
     }
     fast_tile<LOG2N, MODE, TB, H, EG, LT, false, PREC>(P.src, P.dst, uint32_t(P.ld), col0, P.stw, smem, threadIdx.x,
-                                                       &top);
+                                                       &top, P.conj_in != 0, P.out_scale);
 }
 
 // Single-pass tile of a 16^s-point transform with every butterfly on MFMA in
@@ -105,7 +110,8 @@ __global__ __launch_bounds__(fast_threads(LOG2N, 1, 16)) void local_fft_mf_kerne
     constexpr int LT = fast_tile_log2T(LOG2N, 1, 16);
     extern __shared__ float2 smem[];
     const int64_t col0 = tile_order(blockIdx.x, gridDim.x) << LT;
-    mf_tile<LOG2N, MODE, TB, PREC>(P.src, P.dst, uint32_t(P.ld), col0, P.stw, smem, threadIdx.x);
+    mf_tile<LOG2N, MODE, TB, PREC>(P.src, P.dst, uint32_t(P.ld), col0, P.stw, smem, threadIdx.x, P.conj_in != 0,
+                                   P.out_scale);
 }
 
 template <int L, bool PRE, bool GEN, int PREC>

@@ -140,6 +140,11 @@ struct LocalPass {
     int32_t top_tw;
     int32_t top_log2N, top_log2Lo;
     const float2 *top_hi, *top_lo, *top_cw;
+    // the inverse transform as conj(Omega conj(y)) / N: conj_in negates the
+    // imaginary part of every item the pass loads; out_scale != 0 stores
+    // conj(item) * out_scale
+    int32_t conj_in;
+    float out_scale;
 };
 
 // Phase II: out[pi2(c)*N1 + v] = ws[pi1(v)*N2 + c] * w_N^{-(v*c mod N)}, the

@@ -59,6 +59,7 @@ struct paco_plan_s {
     LocalPass phase1_packed{};
     bool two_pass = false;                  // Phase III can read the packed buffer itself
     LocalPass phase3_two{};
+    paco_plan_s *inv = nullptr;             // N2 x N1 passes of the inverse (NULL: square, this plan's)
     std::string desc;
 };
 
@@ -123,8 +124,13 @@ void split_local(int l, int t, int &la, int &lb)
 
 extern "C" {
 
-paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int32_t b,
-                             paco_dtype dt)
+}  // extern "C"
+
+namespace {
+
+// Builds the passes and tables of one factorisation N1 x N2 (the forward
+// transform's; paco_plan_create builds a second, N2 x N1, for the inverse).
+paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int32_t b, paco_dtype dt)
 {
     if (!plan) return fail(PACO_ERR_INVALID_ARG, "plan out-pointer is NULL");
     *plan = nullptr;
@@ -397,6 +403,30 @@ paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p
     return PACO_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int32_t b,
+                             paco_dtype dt)
+{
+    paco_status st = create_impl(plan, N1, N2, p, b, dt);
+    if (st != PACO_OK || N1 == N2) return st;  // square: the inverse reuses the forward passes
+    const std::string note = g_last_error;
+    paco_plan *inv = nullptr;
+    st = create_impl(&inv, N2, N1, p, b, dt);
+    if (st != PACO_OK) {
+        const std::string why = g_last_error;
+        paco_plan_destroy(*plan);
+        *plan = nullptr;
+        g_last_error = "inverse factorisation: " + why;
+        return st;
+    }
+    (*plan)->inv = inv;
+    g_last_error = note;
+    return PACO_OK;
+}
+
 paco_status paco_plan_workspace_size(const paco_plan *plan, size_t *bytes)
 {
     if (!bytes) return fail(PACO_ERR_INVALID_ARG, "bytes out-pointer is NULL");
@@ -420,6 +450,7 @@ paco_status paco_plan_describe(const paco_plan *plan, int32_t *launches, char *b
 paco_status paco_plan_destroy(paco_plan *plan)
 {
     if (!plan) return PACO_OK;
+    if (plan->inv) paco_plan_destroy(plan->inv);
     if (plan->dev_tables) (void)hipFree(plan->dev_tables);
     delete plan;
     return PACO_OK;
@@ -455,12 +486,7 @@ paco_status run_middle(const paco_plan *plan, const void *src, void *dst, int tw
     return PACO_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-paco_status paco_execute(const paco_plan *plan, const void *in, void *out, void *workspace,
-                         size_t workspace_bytes, void *stream)
+paco_status check_buffers(const paco_plan *plan, const void *in, void *out, void *workspace, size_t workspace_bytes)
 {
     if (!plan) return fail(PACO_ERR_INVALID_ARG, "plan is NULL");
     if (bad_ptr(in) || bad_ptr(out) || bad_ptr(workspace))
@@ -471,13 +497,44 @@ paco_status paco_execute(const paco_plan *plan, const void *in, void *out, void 
                  ob = reinterpret_cast<uintptr_t>(out);
     if ((wb < ib + need && ib < wb + need) || (wb < ob + need && ob < wb + need))
         return fail(PACO_ERR_INVALID_ARG, "workspace overlaps in or out");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    paco_status st = plan->fused ? run_local({plan->phase1_packed}, in, workspace, s)
-                                 : run_local(plan->phase1, in, workspace, s);
+    return PACO_OK;
+}
+
+// The three phases of one plan.  inverse: conj on Phase I's loads, conj and
+// 1/N on Phase III's stores, i.e. conj(Omega conj(in)) / N.
+paco_status run_three(const paco_plan *plan, const void *in, void *out, void *workspace, hipStream_t s, bool inverse)
+{
+    std::vector<LocalPass> p1 = plan->fused ? std::vector<LocalPass>{plan->phase1_packed} : plan->phase1;
+    std::vector<LocalPass> p3 = plan->phase3;
+    if (inverse) {
+        p1.front().conj_in = 1;
+        p3.back().out_scale = 1.0f / float(plan->N1 * plan->N2);  // 2^-log2 N: exact
+    }
+    paco_status st = run_local(p1, in, workspace, s);
     if (st != PACO_OK) return st;
     st = run_middle(plan, workspace, out, 1, plan->fused, s);
     if (st != PACO_OK) return st;
-    return run_local(plan->phase3, out, out, s);
+    return run_local(p3, out, out, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+paco_status paco_execute(const paco_plan *plan, const void *in, void *out, void *workspace,
+                         size_t workspace_bytes, void *stream)
+{
+    paco_status st = check_buffers(plan, in, out, workspace, workspace_bytes);
+    if (st != PACO_OK) return st;
+    return run_three(plan, in, out, workspace, static_cast<hipStream_t>(stream), false);
+}
+
+paco_status paco_execute_inverse(const paco_plan *plan, const void *in, void *out, void *workspace,
+                                 size_t workspace_bytes, void *stream)
+{
+    paco_status st = check_buffers(plan, in, out, workspace, workspace_bytes);
+    if (st != PACO_OK) return st;
+    return run_three(plan->inv ? plan->inv : plan, in, out, workspace, static_cast<hipStream_t>(stream), true);
 }
 
 paco_status paco_execute_two_pass(const paco_plan *plan, const void *in, void *out, void *workspace,
@@ -486,16 +543,10 @@ paco_status paco_execute_two_pass(const paco_plan *plan, const void *in, void *o
     if (!plan) return fail(PACO_ERR_INVALID_ARG, "plan is NULL");
     if (!plan->two_pass)
         return fail(PACO_ERR_UNSUPPORTED, "two-pass form needs the fused FP32 pipeline with a single-pass Phase III");
-    if (bad_ptr(in) || bad_ptr(out) || bad_ptr(workspace))
-        return fail(PACO_ERR_INVALID_ARG, "in/out/workspace must be non-NULL and 16-byte aligned");
-    const size_t need = size_t(plan->N1) * size_t(plan->N2) * 8;
-    if (workspace_bytes < need) return fail(PACO_ERR_WORKSPACE, "workspace smaller than N1*N2*8 bytes");
-    const size_t wb = reinterpret_cast<uintptr_t>(workspace), ib = reinterpret_cast<uintptr_t>(in),
-                 ob = reinterpret_cast<uintptr_t>(out);
-    if ((wb < ib + need && ib < wb + need) || (wb < ob + need && ob < wb + need))
-        return fail(PACO_ERR_INVALID_ARG, "workspace overlaps in or out");
+    paco_status st = check_buffers(plan, in, out, workspace, workspace_bytes);
+    if (st != PACO_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    paco_status st = run_local({plan->phase1_packed}, in, workspace, s);
+    st = run_local({plan->phase1_packed}, in, workspace, s);
     if (st != PACO_OK) return st;
     return run_local({plan->phase3_two}, workspace, out, s);
 }

@@ -132,7 +132,11 @@ struct Ctx {
     uint32_t orow_out, k_out;  // generic: output row = orow_out + pi_out(k) * k_out
     int out_t, out_ell;
     bool act;                  // runtime tile width: this thread owns butterflies (tid < nt)
+    float oscale = 0.f;        // nonzero: every output is stored as conj(y) * oscale
 };
+
+// conj(v) * s: the inverse transform's output map (s = 1/N, a power of two)
+__device__ __forceinline__ float2 conj_scale(float2 v, float s) { return make_float2(v.x * s, -v.y * s); }
 
 // ---- split-precision MFMA form of the radix-16 butterflies -----------------
 // A radix-16 butterfly y = W x, W[m][k] = w_16^{-mk}, is one real contraction
@@ -398,6 +402,10 @@ __device__ __forceinline__ void run_stage(float2 (&v)[H * EG], const Ctx &c)
     } else {
         // last stage: j < n/R = 2^LNS, outputs are the natural-order rows k = j + r*2^LNS.
         if (!act) return;
+        if (c.oscale != 0.f) {
+#pragma unroll
+            for (int k = 0; k < H * EG; ++k) v[k] = conj_scale(v[k], c.oscale);
+        }
         // With H = 2 the groups interleave: group h of tile column t holds
         // column 2t + h, so one 16-byte store writes both groups' items.
         if constexpr (H == 2 && (MODE == 0 || MODE == 1)) {
@@ -512,7 +520,8 @@ struct TopTw {
 // (row length ld items); col0: the tile's first column.
 template <int LOG2N, int MODE, int TB, int H, int EG, int LT, bool COH = false, int PREC = kPrecFP32>
 __device__ __forceinline__ void fast_tile(const float2 *srcm, float2 *dstm, uint32_t ld, int64_t col0,
-                                          const float2 *stw, float2 *smem, int tid, const TopTw *top = nullptr)
+                                          const float2 *stw, float2 *smem, int tid, const TopTw *top = nullptr,
+                                          bool conj_in = false, float oscale = 0.f)
 {
     constexpr int LTG = LT - (H == 2 ? 1 : 0);         // log2 of the columns of one group
     constexpr int NT = (1 << (LOG2N + LTG)) / EG;
@@ -550,6 +559,12 @@ __device__ __forceinline__ void fast_tile(const float2 *srcm, float2 *dstm, uint
                 v[q * R0 + r] = *reinterpret_cast<const float2 *>(src + base + row_off);
             }
         }
+        if (conj_in) {  // the inverse transform's input map
+#pragma unroll
+            for (int k = 0; k < R0; ++k)
+#pragma unroll
+                for (int h = 0; h < H; ++h) v[h * EG + q * R0 + k].y = -v[h * EG + q * R0 + k].y;
+        }
         if constexpr (MODE == 3) {
             // item (row j + r 2^LNR0, column col0 + t + h) times w_N^{-(column * row mod N)}
 #pragma unroll
@@ -579,6 +594,7 @@ __device__ __forceinline__ void fast_tile(const float2 *srcm, float2 *dstm, uint
     c.out_t = 0;
     c.out_ell = 0;
     c.act = true;
+    c.oscale = oscale;
     run_stage<LOG2N, 0, EG, LTG, MODE == 3 ? 1 : MODE, TB, false, H, COH, PREC>(v, c);
 }
 
@@ -595,7 +611,8 @@ __device__ __forceinline__ void fast_tile(const float2 *srcm, float2 *dstm, uint
 // columns with one 16-item butterfly per thread and stage (EG = 16).
 template <int LOG2N, int MODE, int TB, int PREC, int LT = fast_log2T(LOG2N)>
 __device__ __forceinline__ void mf_tile(const float2 *srcm, float2 *dstm, uint32_t ld, int64_t col0,
-                                        const float2 *stw, float2 *smem, int tid)
+                                        const float2 *stw, float2 *smem, int tid, bool conj_in = false,
+                                        float oscale = 0.f)
 {
     static_assert(LOG2N % 4 == 0 && LOG2N >= 4 && LOG2N <= 12, "radix-16 stages only");
     constexpr int NS = LOG2N / 4;
@@ -638,6 +655,12 @@ __device__ __forceinline__ void mf_tile(const float2 *srcm, float2 *dstm, uint32
             const uint32_t row = MODE == 1 ? uint32_t(digrev<false>(jj, TB, LOG2N / TB)) : jj;
             xin[G][i] = *reinterpret_cast<const float *>(src + row * ld8 + uint32_t(t) * 8u + uint32_t(comp) * 4u);
         }
+    }
+    if (conj_in && comp == 1) {  // the inverse transform's input map: negate the imaginary parts
+#pragma unroll
+        for (int G = 0; G < 4; ++G)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) xin[G][i] = -xin[G][i];
     }
     copy_twiddles(twl, stw, TWN, tid, NT);  // after the data loads are issued
 
@@ -727,7 +750,7 @@ __device__ __forceinline__ void mf_tile(const float2 *srcm, float2 *dstm, uint32
                 off = uint32_t(digrev<false>(k, TB, LOG2N / TB)) * ld8 + uint32_t(t) * 8u;
             else
                 off = k * ld8 + uint32_t(t) * 8u;
-            st2<false>(dst + off, o[G][i]);
+            st2<false>(dst + off, oscale != 0.f ? conj_scale(o[G][i], oscale) : o[G][i]);
         }
     }
 }

@@ -32,7 +32,7 @@ PACO_PACKED = 2
 # every symbol include/paco.h declares
 EXPORTED = (
     "paco_plan_validate", "paco_plan_create", "paco_plan_workspace_size", "paco_execute",
-    "paco_execute_stage", "paco_execute_two_pass", "paco_plan_has_two_pass", "paco_plan_describe",
+    "paco_execute_stage", "paco_execute_inverse", "paco_execute_two_pass", "paco_plan_has_two_pass", "paco_plan_describe",
     "paco_plan_destroy", "paco_status_string",
     "paco_last_error", "paco_batch_plan_create", "paco_batch_workspace_size", "paco_execute_batched",
     "paco_batch_plan_describe", "paco_batch_errors", "paco_batch_plan_destroy",
@@ -66,6 +66,7 @@ def _load() -> ctypes.CDLL:
         "paco_execute": (st, [P, P, P, P, sz, P]),
         "paco_execute_stage": (st, [P, st, st, P, P, P]),
         "paco_execute_two_pass": (st, [P, P, P, P, sz, P]),
+        "paco_execute_inverse": (st, [P, P, P, P, sz, P]),
         "paco_plan_has_two_pass": (st, [P, ctypes.POINTER(i32)]),
         "paco_plan_describe": (st, [P, ctypes.POINTER(i32), ctypes.c_char_p, sz]),
         "paco_plan_destroy": (st, [P]),
@@ -131,6 +132,10 @@ def paco_execute_stage(plan: int, stage: int, flags: int, src: int, dst: int, st
     _check(_lib.paco_execute_stage(plan, stage, flags, src, dst, stream), "paco_execute_stage")
 
 
+def paco_execute_inverse(plan: int, src: int, dst: int, workspace: int, workspace_bytes: int, stream: int = 0):
+    _check(_lib.paco_execute_inverse(plan, src, dst, workspace, workspace_bytes, stream), "paco_execute_inverse")
+
+
 def paco_execute_two_pass(plan: int, src: int, dst: int, workspace: int, workspace_bytes: int, stream: int = 0):
     _check(_lib.paco_execute_two_pass(plan, src, dst, workspace, workspace_bytes, stream), "paco_execute_two_pass")
 
@@ -164,6 +169,9 @@ class Plan:
 
     def execute(self, src: int, dst: int, workspace: int, stream: int = 0):
         paco_execute(self.handle, src, dst, workspace, self.workspace_bytes, stream)
+
+    def execute_inverse(self, src: int, dst: int, workspace: int, stream: int = 0):
+        paco_execute_inverse(self.handle, src, dst, workspace, self.workspace_bytes, stream)
 
     def execute_two_pass(self, src: int, dst: int, workspace: int, stream: int = 0):
         paco_execute_two_pass(self.handle, src, dst, workspace, self.workspace_bytes, stream)

@@ -80,6 +80,7 @@ def test_null_plan_and_pointer_errors():
     assert lib.paco_execute(None, 8, 8, 8, 1 << 20, None) == paco.PACO_ERR_INVALID_ARG
     assert lib.paco_execute_stage(None, 1, 0, 8, 8, None) == paco.PACO_ERR_INVALID_ARG
     assert lib.paco_execute_two_pass(None, 16, 16, 16, 1 << 20, None) == paco.PACO_ERR_INVALID_ARG
+    assert lib.paco_execute_inverse(None, 16, 16, 16, 1 << 20, None) == paco.PACO_ERR_INVALID_ARG
     yes = ctypes.c_int32(7)
     assert lib.paco_plan_has_two_pass(None, ctypes.byref(yes)) == paco.PACO_ERR_INVALID_ARG
     assert yes.value == 0
