@@ -64,6 +64,8 @@ def _load():
     i64 = ctypes.c_int64
     lib.oracle_digit_reverse.restype = i64
     lib.oracle_digit_reverse.argtypes = [i64, i64, ctypes.c_int32]
+    lib.oracle_digit_reverse_n.restype = i64
+    lib.oracle_digit_reverse_n.argtypes = [i64, i64, i64]
     for name in ("oracle_dft_naive", "oracle_fft_radix2", "oracle_dft", "oracle_idft"):
         getattr(lib, name).restype = ctypes.c_int
         getattr(lib, name).argtypes = [P, P, i64]
@@ -117,6 +119,48 @@ def digit_reverse_py(i: int, b: int, ell: int) -> int:
     out = 0
     for d in msb_first[::-1]:         # the reversed string d_0 .. d_{ell-1}
         out = out * b + d
+    return out
+
+
+def digit_reverse_n(i: int, b: int, n: int) -> int:
+    """pi(i) over [0, n), n = b^m * r (1 <= r < b): digit radices (b, ..., b, r)
+    least significant first, reversed and read back with the radices
+    reversed; for n = b^m the paper's pi_m (appendix A.1).  Sizes other than
+    powers of b lie outside the paper's preconditions (section 5,
+    Limitations): this is the mixed-radix reading."""
+    r = _load().oracle_digit_reverse_n(int(i), int(b), int(n))
+    if r < 0:
+        raise ValueError(f"bad digit reversal arguments i={i} b={b} n={n}")
+    return int(r)
+
+
+def radices(b: int, n: int) -> list:
+    """The digit radices of [0, n) in the mixed-radix reading, least
+    significant first: (b, ..., b, r)."""
+    out = []
+    while n > 1:
+        R = b if n % b == 0 else n
+        if R > b:
+            raise ValueError("n is not b^m * r with r < b")
+        out.append(R)
+        n //= R
+    return out
+
+
+def reverse_with_radices(i: int, rad) -> int:
+    """Digit reversal for an explicit radix list (least significant first),
+    in pure Python: split i into digits, reverse the list, read it back with
+    the reversed radix list."""
+    digits = []
+    for R in rad:
+        digits.append(i % R)
+        i //= R
+    if i:
+        raise ValueError("i out of range")
+    out, w = 0, 1
+    for d, R in zip(digits[::-1], rad[::-1]):
+        out += d * w
+        w *= R
     return out
 
 

@@ -101,6 +101,39 @@ int64_t oracle_digit_reverse(int64_t i, int64_t b, int32_t ell)
     return out;
 }
 
+/* Mixed-radix digit reversal of i in [0, n), for n = b^m * r with
+ * 1 <= r < b: the paper's preconditions (section 2) ask for n = b^m; the
+ * Limitations of section 5 name other sizes as outside its scope.  The
+ * reading used here: i has the digit radices (b, ..., b, r), least
+ * significant first (m digits of radix b, then one of radix r when r > 1);
+ * pi reverses the digit string and reads it back with the radices reversed,
+ * (r, b, ..., b).  For r = 1 this is pi_m of appendix A.1.  Brute force on
+ * the digit list; returns -1 on bad input. */
+int64_t oracle_digit_reverse_n(int64_t i, int64_t b, int64_t n)
+{
+    if (b < 2 || n < 1 || i < 0 || i >= n) return -1;
+    int64_t radix[64], digit[64];
+    int L = 0;
+    int64_t rest = n, v = i;
+    while (rest > 1) {                       /* radices, least significant first */
+        int64_t R = (rest % b == 0) ? b : rest;
+        if (R > b) return -1;                /* n is not b^m * r with r < b */
+        radix[L] = R;
+        digit[L] = v % R;
+        v /= R;
+        rest /= R;
+        ++L;
+    }
+    /* reversed string: digit[L-1] least significant (radix[L-1]), then
+     * digit[L-2] (radix[L-2]), ..., digit[0] most significant */
+    int64_t out = 0, w = 1;
+    for (int k = L - 1; k >= 0; --k) {
+        out += digit[k] * w;
+        w *= radix[k];
+    }
+    return out;
+}
+
 /* ------------------------------------------------------------------ */
 /* the DFT itself (section 2)                                           */
 /* ------------------------------------------------------------------ */
@@ -230,11 +263,16 @@ int oracle_idft(const double *y, double *x, int64_t N)
 /* stage-wise references (sections 3.1-3.4, 4.2)                       */
 /* ------------------------------------------------------------------ */
 
-static int ilog(int64_t n, int64_t b)
+/* In all three, pi_{m1} and pi_{m2} are oracle_digit_reverse_n over [0, N1)
+ * and [0, N2): the paper's base-b reversals when N1, N2 are powers of b, the
+ * mixed-radix reading above otherwise. */
+
+/* n = b^m * r with 1 <= r < b (r = 1: the paper's n = b^m). */
+static int digit_shape_ok(int64_t n, int64_t b)
 {
-    int e = 0;
-    while (n > 1) { if (n % b) return -1; n /= b; ++e; }
-    return n == 1 ? e : -1;
+    if (b < 2 || n < 1) return 0;
+    while (n % b == 0) n /= b;
+    return n < b;
 }
 
 /* Phase I, output layout A_{m1} (x) I_{N2} (Lemma 1; section 3.4):
@@ -247,8 +285,7 @@ static int ilog(int64_t n, int64_t b)
 int oracle_phase1(const double *x, int64_t N1, int64_t N2, int64_t b,
                   const int64_t *cols, int64_t ncols, double *out)
 {
-    int m1 = ilog(N1, b);
-    if (m1 < 0 || N2 < 1) return -1;
+    if (!digit_shape_ok(N1, b) || N2 < 1) return -1;
     if (!cols) ncols = N2;
     double *col = (double *)malloc(sizeof(double) * 2 * (size_t)N1);
     double *dft = (double *)malloc(sizeof(double) * 2 * (size_t)N1);
@@ -263,7 +300,7 @@ int oracle_phase1(const double *x, int64_t N1, int64_t N2, int64_t b,
         }
         rc = oracle_dft(col, dft, N1);
         for (int64_t a = 0; a < N1; ++a) {
-            int64_t k1 = oracle_digit_reverse(a, b, m1);
+            int64_t k1 = oracle_digit_reverse_n(a, b, N1);
             out[2 * (a * ncols + i)] = dft[2 * k1];
             out[2 * (a * ncols + i) + 1] = dft[2 * k1 + 1];
         }
@@ -282,15 +319,14 @@ int oracle_phase1(const double *x, int64_t N1, int64_t N2, int64_t b,
  * twiddle == 0 gives the bare permutation (values moved, not scaled). */
 int oracle_phase2(const double *ws, double *z, int64_t N1, int64_t N2, int64_t b, int twiddle)
 {
-    int m1 = ilog(N1, b), m2 = ilog(N2, b);
-    if (m1 < 0 || m2 < 0) return -1;
+    if (!digit_shape_ok(N1, b) || !digit_shape_ok(N2, b)) return -1;
     int64_t N = N1 * N2;
     roots_t t;
     if (twiddle && roots_init(&t, N)) return -2;
     for (int64_t a = 0; a < N1; ++a) {
-        int64_t v = oracle_digit_reverse(a, b, m1);
+        int64_t v = oracle_digit_reverse_n(a, b, N1);
         for (int64_t c = 0; c < N2; ++c) {
-            int64_t u = oracle_digit_reverse(c, b, m2);
+            int64_t u = oracle_digit_reverse_n(c, b, N2);
             double xr = ws[2 * (a * N2 + c)], xi = ws[2 * (a * N2 + c) + 1];
             double outr = xr, outi = xi;
             if (twiddle) {
@@ -316,8 +352,7 @@ int oracle_phase2(const double *ws, double *z, int64_t N1, int64_t N2, int64_t b
 int oracle_phase3(const double *z, int64_t N1, int64_t N2, int64_t b,
                   const int64_t *cols, int64_t ncols, double *out)
 {
-    int m2 = ilog(N2, b);
-    if (m2 < 0 || N1 < 1) return -1;
+    if (!digit_shape_ok(N2, b) || N1 < 1) return -1;
     if (!cols) ncols = N1;
     double *col = (double *)malloc(sizeof(double) * 2 * (size_t)N2);
     double *dft = (double *)malloc(sizeof(double) * 2 * (size_t)N2);
@@ -327,7 +362,7 @@ int oracle_phase3(const double *z, int64_t N1, int64_t N2, int64_t b,
         int64_t v = cols ? cols[i] : i;
         if (v < 0 || v >= N1) { rc = -1; break; }
         for (int64_t j2 = 0; j2 < N2; ++j2) {
-            int64_t u = oracle_digit_reverse(j2, b, m2);
+            int64_t u = oracle_digit_reverse_n(j2, b, N2);
             col[2 * j2] = z[2 * (u * N1 + v)];
             col[2 * j2 + 1] = z[2 * (u * N1 + v) + 1];
         }

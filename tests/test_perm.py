@@ -255,3 +255,92 @@ def test_phase3_input_layout(N1, N2, b):
     phys = logical[perm, :]                      # physical row u holds logical pi(u)
     want = np.fft.fft(logical, axis=0)
     assert np.max(np.abs(oracle.phase3(phys, N1, N2, b) - want)) < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# Mixed-radix reading: sizes n = b^m * r (1 < r < b) lie outside the paper's
+# preconditions (section 5, Limitations); digits (b, ..., b, r) least
+# significant first, reversed with the radices reversed
+# ---------------------------------------------------------------------------
+
+def test_mixed_digit_reverse_hand_values():
+    # n = 8, b = 4: radices (4, 2); i = d0 + 4 d1 maps to d1 + 2 d0
+    assert [oracle.digit_reverse_n(i, 4, 8) for i in range(8)] == [0, 2, 4, 6, 1, 3, 5, 7]
+    # n = 32, b = 16: radices (16, 2); i = d0 + 16 d1 maps to d1 + 2 d0
+    assert [oracle.digit_reverse_n(i, 16, 32) for i in (1, 15, 16, 17, 31)] == [2, 30, 1, 3, 31]
+    # n = 30, b = 10 (not a power of two): radices (10, 3); 27 = 7 + 10*2 maps to 2 + 3*7
+    assert oracle.digit_reverse_n(27, 10, 30) == 23
+    # n = 2^14, b = 16: radices (16, 16, 16, 4); i = 1 maps to 4 * 16^2 = 1024
+    assert oracle.digit_reverse_n(1, 16, 1 << 14) == 1024
+    assert oracle.digit_reverse_n(1 << 12, 16, 1 << 14) == 1    # the top (radix-4) digit comes first
+
+
+@pytest.mark.parametrize("b,n", [(4, 8), (16, 32), (16, 64), (16, 1 << 10), (8, 1 << 7), (8, 1 << 13),
+                                 (16, 1 << 14), (4, 2), (10, 30), (3, 18)])
+def test_mixed_matches_python_digit_lists(b, n):
+    rad = oracle.radices(b, n)
+    assert int(np.prod(rad)) == n and all(R == b for R in rad[:-1]) and rad[-1] <= b
+    got = [oracle.digit_reverse_n(i, b, n) for i in range(n)]
+    assert got == [oracle.reverse_with_radices(i, rad) for i in range(n)]
+    assert sorted(got) == list(range(n))                       # a permutation
+    inv = [oracle.reverse_with_radices(v, rad[::-1]) for v in got]
+    assert inv == list(range(n))                               # inverse: the reversed radices
+
+
+@pytest.mark.parametrize("b,m", [(2, 5), (4, 3), (8, 2), (16, 2), (3, 3)])
+def test_mixed_reduces_to_pi_m(b, m):
+    n = b ** m
+    assert [oracle.digit_reverse_n(i, b, n) for i in range(n)] == [oracle.digit_reverse(i, b, m) for i in range(n)]
+
+
+def test_mixed_is_not_an_involution():
+    # with a short digit the map and its inverse differ: the pipeline must
+    # use each where the layouts ask for it (pinned by the composition below)
+    n, b = 32, 16
+    fwd = [oracle.digit_reverse_n(i, b, n) for i in range(n)]
+    assert any(fwd[fwd[i]] != i for i in range(n))
+
+
+@pytest.mark.parametrize("N1,N2,b", [(8, 32, 16), (32, 8, 4), (128, 64, 8), (2, 8, 4)])
+def test_mixed_composition_identity(N1, N2, b):
+    # the global index a (+) c = a*N2 + c has the radices of c then those of a;
+    # reversing the whole string equals pi_{N2}(c) (+) pi_{N1}(a)
+    R = oracle.radices(b, N2) + oracle.radices(b, N1)
+    for a in range(N1):
+        for c in range(N2):
+            want = oracle.digit_reverse_n(c, b, N2) * N1 + oracle.digit_reverse_n(a, b, N1)
+            assert oracle.reverse_with_radices(a * N2 + c, R) == want
+
+
+@pytest.mark.parametrize("N1,N2,b", [(32, 64, 16), (64, 32, 16), (8, 8, 4), (128, 512, 8), (2, 16, 4),
+                                     (1024, 32, 16), (30, 9, 10)])
+def test_mixed_three_stages_compose_to_dft(N1, N2, b):
+    rng = np.random.default_rng(N1 + 3 * N2)
+    x = rng.standard_normal(N1 * N2) + 1j * rng.standard_normal(N1 * N2)
+    Y = oracle.paco_reference(x, N1, N2, b)
+    assert oracle.rel_l2(Y.ravel(), oracle.dft(x)) < 1e-12
+    assert oracle.rel_l2(Y.ravel(), np.fft.fft(x)) < 1e-12
+
+
+@pytest.mark.parametrize("N1,N2,b", [(32, 64, 16), (128, 16, 8)])
+def test_mixed_stage_layouts(N1, N2, b):
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(N1 * N2) + 1j * rng.standard_normal(N1 * N2)
+    p1 = [oracle.reverse_with_radices(a, oracle.radices(b, N1)) for a in range(N1)]
+    p2 = [oracle.reverse_with_radices(c, oracle.radices(b, N2)) for c in range(N2)]
+    # Phase I: row a holds frequency pi1(a) of each column's DFT
+    A = np.fft.fft(x.reshape(N1, N2), axis=0)
+    At = oracle.phase1(x, N1, N2, b)
+    assert np.max(np.abs(At - A[p1, :])) < 1e-9
+    # Phase II without the twiddle: item (a, c) lands at (pi2(c), pi1(a))
+    ws = rng.standard_normal((N1, N2)) + 1j * rng.standard_normal((N1, N2))
+    Z = oracle.phase2(ws, N1, N2, b, twiddle=False)
+    want = np.empty((N2, N1), complex)
+    for a in range(N1):
+        want[p2, p1[a]] = ws[a, :]
+    assert np.array_equal(Z, want)
+    # Phase III: physical row pi2(j) holds logical j
+    logical = rng.standard_normal((N2, N1)) + 1j * rng.standard_normal((N2, N1))
+    phys = np.empty_like(logical)
+    phys[p2, :] = logical
+    assert np.max(np.abs(oracle.phase3(phys, N1, N2, b) - np.fft.fft(logical, axis=0))) < 1e-9
