@@ -96,6 +96,23 @@ paco_status paco_plan_validate(int64_t N1, int64_t N2, int64_t p, int32_t b, pac
 paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int32_t b,
                              paco_dtype dt);
 
+/* Mixed-radix sizes, outside the paper's preconditions (section 5,
+ * Limitations name sizes that are not powers of b): N1 and N2 any powers of
+ * two >= 2, b = 2^t, N_i = b^{m_i} 2^{s_i} with 0 <= s_i < t.  An index of
+ * [0, N_i) then has the digit radices (b, ..., b, 2^{s_i}), least
+ * significant first, and pi_{m_i} of appendix A.1 becomes the reversal of
+ * that digit string read back with the radices reversed, (2^{s_i}, b, ...,
+ * b); it is no longer an involution, and each layout uses it in the
+ * direction its definition asks for (Phase-I row a holds frequency pi(a),
+ * Phase II moves (a, c) to (pi(c), pi(a)), Phase III reads logical j at row
+ * pi(j)).  With s1 = s2 = 0 the plan equals paco_plan_create's.  Two-pass
+ * local phases put the short digit into their first pass.  Otherwise as
+ * paco_plan_create / paco_plan_validate; every entry point that takes a
+ * plan accepts these. */
+paco_status paco_plan_validate_mixed(int64_t N1, int64_t N2, int64_t p, int32_t b, paco_dtype dt);
+paco_status paco_plan_create_mixed(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int32_t b,
+                                   paco_dtype dt);
+
 /* Bytes of device workspace paco_execute needs (N1*N2*8 for PACO_C64). */
 paco_status paco_plan_workspace_size(const paco_plan *plan, size_t *bytes);
 

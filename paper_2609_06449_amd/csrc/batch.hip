@@ -190,6 +190,8 @@ __device__ __forceinline__ MiddlePass middle_of(const BatchArgs &A, const BatchJ
     M.t = J.t;
     M.m1 = J.l1 / J.t;
     M.m2 = J.l2 / J.t;
+    M.s1 = 0;  // the batched plans use bases that divide both exponents
+    M.s2 = 0;
     M.tw_hi = T.hi;
     M.tw_lo = T.lo;
     M.tw_tile = T.tile;

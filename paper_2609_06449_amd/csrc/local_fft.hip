@@ -79,6 +79,7 @@ int32_t local_fft_fast_mode(const LocalPass &p)
 {
     // single-pass Phase I (pi on output rows) or Phase III (pi on input rows)
     if (p.pre_tw || p.n_outer != 1 || p.o_in || p.o_out || p.j_in != 1 || p.k_out != 1) return -1;
+    if (p.in_s || p.out_s) return -1;  // mixed-radix row maps: generic kernel
     if (p.log2T != fast_tile_log2T(p.log2n, p.groups >= 2 ? 2 : 1, p.groups == 3 ? 32 : 16)) return -1;
     int mode = -1, tb = 0;
     if (p.top_tw) {

@@ -42,7 +42,7 @@ __global__ __launch_bounds__(1024) void local_fft_kernel(LocalPass P)
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
             const uint32_t jj = j + (r << LNR0);
-            const uint32_t m = uint32_t(digrev<GEN>(jj, P.in_t, P.in_ell));
+            const uint32_t m = uint32_t(digmap<GEN>(jj, P.in_t, P.in_ell, P.in_s, false));
             v[q * R0 + r] = *reinterpret_cast<const float2 *>(src + ((orow + m * j_in) * ld8 + uint32_t(t) * 8u));
         }
     }
@@ -54,7 +54,7 @@ __global__ __launch_bounds__(1024) void local_fft_kernel(LocalPass P)
     // waiting for it does not delay them
     copy_twiddles(twl, P.stw, TWN, tid, nt);
     if constexpr (PRE) {
-        const int64_t f = digrev<GEN>(o, P.tw_t, P.tw_ell);
+        const int64_t f = digmap<GEN>(o, P.tw_t, P.tw_ell, P.tw_s, false);
         const int64_t Mm = (int64_t(1) << P.log2M) - 1;
         const int shM = P.log2L - P.log2M;
 #pragma unroll
@@ -77,6 +77,7 @@ __global__ __launch_bounds__(1024) void local_fft_kernel(LocalPass P)
     c.k_out = uint32_t(P.k_out);
     c.out_t = P.out_t;
     c.out_ell = P.out_ell;
+    c.out_s = P.out_s;
     c.act = true;
     c.oscale = P.out_scale;
     run_stage<LOG2N, 0, EG, -1, -1, 1, GEN, 1, false, PREC>(v, c);

@@ -56,7 +56,7 @@ __global__ __launch_bounds__(kThreads) void middle_kernel(MiddlePass P)
     for (int q = 0; q < kPerThread; ++q) {
         const int vi = rg + q * rstep;
         if (FULL || vi < TV) {
-            const int64_t a = digrev<GEN>(v0 + vi, P.t, P.m1);
+            const int64_t a = digmap<GEN>(v0 + vi, P.t, P.m1, P.s1, true);
             x[q] = P.ws[a * P.N2 + c];
             if (TW) t4[q] = P.tw_tile[vi * kTwTile + ci];
         }
@@ -89,7 +89,7 @@ __global__ __launch_bounds__(kThreads) void middle_kernel(MiddlePass P)
     for (int q = 0; q < kPerThread; ++q) {
         const int cj = cg + q * cstep;
         if (FULL || cj < TC) {
-            const int64_t u = digrev<GEN>(c0 + cj, P.t, P.m2);
+            const int64_t u = digmap<GEN>(c0 + cj, P.t, P.m2, P.s2, false);
             P.out[u * P.N1 + v0 + vi] = tile[cj * (kMidTile + 1) + vi];
         }
     }

@@ -46,7 +46,7 @@ __device__ __forceinline__ void middle_packed_tile(const MiddlePass &P, int64_t 
 #pragma unroll
     for (int q = 0; q < kMidPerThread; ++q) {
         const int64_t c = c0 + w + 4 * q;
-        const int64_t u = digrev<GEN>(c, P.t, P.m2);
+        const int64_t u = digmap<GEN>(c, P.t, P.m2, P.s2, false);
         float2 y = x[q];
         if (TW) {
             const int64_t r = (v0 * c) & Nm;  // w_N^{-v0 c}: one value per row
@@ -88,7 +88,7 @@ __device__ __forceinline__ void middle_packed2_tile(const MiddlePass &P, int64_t
 #pragma unroll
     for (int q = 0; q < kMidPerThread; ++q) {
         const int64_t c = c0 + w + 4 * q;
-        const int64_t u = digrev<GEN>(c, P.t, P.m2);
+        const int64_t u = digmap<GEN>(c, P.t, P.m2, P.s2, false);
         float2 y0 = make_float2(x[q].x, x[q].y), y1 = make_float2(x[q].z, x[q].w);
         if (TW) {
             const int64_t r = (v0 * c) & Nm;  // w_N^{-v0 c}: one value per row

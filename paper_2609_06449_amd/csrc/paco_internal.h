@@ -96,6 +96,21 @@ __device__ __forceinline__ int64_t digrev(int64_t x, int t, int ell)
     }
 }
 
+// Mixed-radix digit maps over [0, b^ell 2^s) (0 <= s < t): the digits are
+// (b, ..., b, 2^s), least significant first.  The forward map pi reverses
+// the digit string and reads it with the radices reversed:
+//     pi(x)     = (x >> t ell) + digrev(x mod b^ell) 2^s
+//     pi^-1(u)  = digrev(u >> s) + (u mod 2^s) b^ell      (inv = true)
+// s = 0: both are digrev (pi_ell is an involution).
+template <bool GEN = false>
+__device__ __forceinline__ int64_t digmap(int64_t x, int t, int ell, int s, bool inv)
+{
+    if (s == 0) return digrev<GEN>(x, t, ell);
+    const int nb = t * ell;
+    if (inv) return digrev<GEN>(x >> s, t, ell) | ((x & ((int64_t(1) << s) - 1)) << nb);
+    return (x >> nb) | (digrev<GEN>(x & ((int64_t(1) << nb) - 1), t, ell) << s);
+}
+
 // True when the branch-free device digit reversal covers digit width t.
 __host__ __device__ constexpr bool digrev_fast(int t) { return t == 1 || t == 2 || t == 4 || t == 8; }
 
@@ -106,7 +121,8 @@ __host__ __device__ constexpr bool digrev_fast(int t) { return t == 1 || t == 2 
 //     input  row of logical j : o*o_in  + pi_in(j)  * j_in
 //     output row of logical k : o*o_out + pi_out(k) * k_out
 // where pi_in / pi_out are base-2^t digit reversals over ell digits
-// (ell = 0: identity).  A row is ld complex64 items long; the column field C
+// (ell = 0: identity), with an extra short digit of s bits on top in the
+// mixed-radix case (digmap: pi_in forward, pi_out inverse).  A row is ld complex64 items long; the column field C
 // of the paper's view is the run of T items every access reads or writes
 // whole.  With pre_tw set, input j of tile o is first scaled by the
 // Cooley-Tukey twiddle w_M^{-f(o)*j}, f(o) = pi_tw(o) (the layout-aware
@@ -121,14 +137,14 @@ struct LocalPass {
     int64_t n_outer;       // outer batch count
     int64_t o_in, j_in;    // input row strides
     int64_t o_out, k_out;  // output row strides
-    int32_t in_t, in_ell;  // pi_in
-    int32_t out_t, out_ell;  // pi_out
+    int32_t in_t, in_ell, in_s;     // pi_in = digmap(., in_t, in_ell, in_s, forward)
+    int32_t out_t, out_ell, out_s;  // pi_out = digmap(., out_t, out_ell, out_s, inverse)
     const float2 *stw;     // stage twiddle tables of length n (stage_tw_total entries)
     const float2 *tw;      // w_L^{-r}, r < L = 2^log2L (pre-twiddle)
     int32_t log2L;
     int32_t pre_tw;        // 0: none; 1: w_M^{-f(o) j} before the DFT
     int32_t log2M;         // M of the pre-twiddle (M <= L)
-    int32_t tw_t, tw_ell;  // f(o) = pi_tw(o)
+    int32_t tw_t, tw_ell, tw_s;  // f(o) = digmap(o, tw_t, tw_ell, tw_s, forward)
     int32_t no_fast;       // 1: always use the generic kernel (testing)
     int32_t out_tr;        // 1: write the output transposed (row = column, n items; fast kernel only)
     int32_t groups;        // fast kernel: 1, or 2 column groups taking turns in LDS
@@ -158,7 +174,8 @@ struct MiddlePass {
     const float2 *ws;
     float2 *out;
     int64_t N1, N2;
-    int32_t t, m1, m2;        // b = 2^t, N1 = b^m1, N2 = b^m2
+    int32_t t, m1, m2;        // b = 2^t, N1 = b^m1 2^s1, N2 = b^m2 2^s2
+    int32_t s1, s2;           // short top digit (mixed-radix sizes; 0: N_i = b^m_i)
     const float2 *tw_hi;      // w_N^{-h*Lo}, h < N/Lo
     const float2 *tw_lo;      // w_N^{-l}, l < Lo
     const float2 *tw_tile;    // [i*128 + j] = w_N^{-(i*j mod N)}, i, j < 128

@@ -51,6 +51,8 @@ struct paco_plan_s {
     int32_t b = 0;
     paco_dtype dt = PACO_C64;
     int t = 0, m1 = 0, m2 = 0, l1 = 0, l2 = 0, lN = 0, lL = 0, lLo = 0;
+    int s1 = 0, s2 = 0;  // short top digit of N1 / N2 (mixed-radix plans)
+    bool mixed = false;
     int device = 0;
     void *dev_tables = nullptr;
     std::vector<LocalPass> phase1, phase3;  // src/dst filled per execution
@@ -82,15 +84,23 @@ const char *paco_status_string(paco_status st)
 
 const char *paco_last_error(void) { return g_last_error.c_str(); }
 
-paco_status paco_plan_validate(int64_t N1, int64_t N2, int64_t p, int32_t b, paco_dtype dt)
+}  // extern "C"
+
+namespace {
+
+paco_status validate_impl(int64_t N1, int64_t N2, int64_t p, int32_t b, paco_dtype dt, bool mixed)
 {
     if (dt != PACO_C64 && dt != PACO_C64_MFMA_FP16X3 && dt != PACO_C64_MFMA_BF16X3 && dt != PACO_C64_MFMA_BF16X6)
         return fail(PACO_ERR_INVALID_ARG, "unknown dtype");
     const int t = ilog2_exact(b);
     if (b < 2 || t < 1) return fail(PACO_ERR_NOT_POWER_OF_B, "b must be 2^t with t >= 1");
     const int l1 = ilog2_exact(N1), l2 = ilog2_exact(N2);
-    if (N1 < 2 || N2 < 2 || l1 < 0 || l2 < 0 || l1 % t || l2 % t)
+    if (mixed) {
+        if (N1 < 2 || N2 < 2 || l1 < 0 || l2 < 0)
+            return fail(PACO_ERR_NOT_POWER_OF_B, "mixed-radix plans need N1 and N2 powers of two >= 2");
+    } else if (N1 < 2 || N2 < 2 || l1 < 0 || l2 < 0 || l1 % t || l2 % t) {
         return fail(PACO_ERR_NOT_POWER_OF_B, "N1 and N2 must be powers of b (b^m with m >= 1)");
+    }
     if (p < 2 || N1 % p || N2 % p) return fail(PACO_ERR_DIVISIBILITY, "need p >= 2, p | N1, p | N2");
     if (l1 > kMaxLocalLog2 || l2 > kMaxLocalLog2 || l1 + l2 > kMaxTotalLog2)
         return fail(PACO_ERR_UNSUPPORTED, "this build supports N1, N2 <= 2^16 and N1*N2 <= 2^28");
@@ -101,13 +111,29 @@ paco_status paco_plan_validate(int64_t N1, int64_t N2, int64_t p, int32_t b, pac
     return PACO_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+paco_status paco_plan_validate(int64_t N1, int64_t N2, int64_t p, int32_t b, paco_dtype dt)
+{
+    return validate_impl(N1, N2, p, b, dt, false);
+}
+
+paco_status paco_plan_validate_mixed(int64_t N1, int64_t N2, int64_t p, int32_t b, paco_dtype dt)
+{
+    return validate_impl(N1, N2, p, b, dt, true);
+}
+
 }  // extern "C"
 
 namespace {
 
-// Digit-aligned split of a local transform of 2^l = b^m items into on-chip
-// passes: one pass up to 2^12 items, otherwise two passes n1 * n2 with
-// n1 = b^ceil(m/2) (the balanced split of section 4.1).
+// Digit-aligned split of a local transform of 2^l = b^m 2^s items into
+// on-chip passes: one pass up to 2^12 items, otherwise two passes n1 * n2
+// with n1 = b^ceil(m/2) 2^s (the balanced split of section 4.1; the short
+// digit of a mixed-radix length goes with n1, whose digit maps carry it) and
+// n2 = b^floor(m/2); if n1 would exceed one pass, n1 = b^floor(m/2) 2^s.
 void split_local(int l, int t, int &la, int &lb)
 {
     if (l <= paco::kMaxOnChipLog2) {
@@ -115,8 +141,9 @@ void split_local(int l, int t, int &la, int &lb)
         lb = 0;
         return;
     }
-    const int m = l / t;
-    la = ((m + 1) / 2) * t;
+    const int m = l / t, s = l % t;
+    la = ((m + 1) / 2) * t + s;
+    if (la > paco::kMaxOnChipLog2) la = (m / 2) * t + s;
     lb = l - la;
 }
 
@@ -130,11 +157,11 @@ namespace {
 
 // Builds the passes and tables of one factorisation N1 x N2 (the forward
 // transform's; paco_plan_create builds a second, N2 x N1, for the inverse).
-paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int32_t b, paco_dtype dt)
+paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int32_t b, paco_dtype dt, bool mixed)
 {
     if (!plan) return fail(PACO_ERR_INVALID_ARG, "plan out-pointer is NULL");
     *plan = nullptr;
-    paco_status st = paco_plan_validate(N1, N2, p, b, dt);
+    paco_status st = validate_impl(N1, N2, p, b, dt, mixed);
     if (st != PACO_OK) return st;
 
     paco_plan_s *P = new (std::nothrow) paco_plan_s();
@@ -149,6 +176,9 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
     P->l2 = ilog2_exact(N2);
     P->m1 = P->l1 / P->t;
     P->m2 = P->l2 / P->t;
+    P->s1 = P->l1 % P->t;
+    P->s2 = P->l2 % P->t;
+    P->mixed = mixed;
     P->lN = P->l1 + P->l2;
     P->lL = P->l1 > P->l2 ? P->l1 : P->l2;
     P->lLo = paco::middle_log2lo(P->lN);
@@ -236,8 +266,9 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
         LocalPass q = base_pass(N2, N2, a1);
         q.j_in = 1;
         q.k_out = 1;
-        q.out_t = t;                        // logical k1 -> row pi_{m1}(k1)
+        q.out_t = t;                        // logical k1 -> row pi_{m1}^-1(k1)
         q.out_ell = P->m1;
+        q.out_s = P->s1;
         P->phase1.push_back(q);
     } else {
         // first child: length n1 = 2^a1 over j1 (row stride n2), batch j2;
@@ -250,7 +281,8 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
         A.o_out = 1;
         A.k_out = n2;
         A.out_t = t;
-        A.out_ell = a1 / t;
+        A.out_ell = a1 / t;                 // n1 = b^(a1/t) 2^s1 carries the short digit
+        A.out_s = P->s1;
         // second child: length n2 over j2 for each physical a, twiddle
         // w_{N1}^{-pi(a) j2} from the represented k1 = pi(a) (appendix A.2)
         LocalPass B = base_pass(N2, N2, b1);
@@ -265,6 +297,7 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
         B.log2M = P->l1;
         B.tw_t = t;
         B.tw_ell = a1 / t;
+        B.tw_s = P->s1;
         P->phase1.push_back(A);
         P->phase1.push_back(B);
     }
@@ -275,6 +308,7 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
         q.k_out = 1;
         q.in_t = t;                         // logical j2 read from row pi_{m2}(j2)
         q.in_ell = P->m2;
+        q.in_s = P->s2;
         P->phase3.push_back(q);
     } else {
         // logical j = j1*s2 + j2 sits at row pi(j2)*s1 + pi(j1)
@@ -284,7 +318,8 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
         A.o_in = s1;
         A.j_in = 1;
         A.in_t = t;
-        A.in_ell = a3 / t;
+        A.in_ell = a3 / t;                  // s1 = b^(a3/t) 2^s2 carries the short digit
+        A.in_s = P->s2;
         A.o_out = s1;
         A.k_out = 1;
         LocalPass B = base_pass(N1, N1, b3);
@@ -321,6 +356,7 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
             q.groups = 1;
         }
     };
+    const LocalPass phase1_base = P->phase1[0];
     for (auto &q : P->phase1) pick(q, "PACO_GROUPS1", q.log2n >= 12 ? 2 : 1);
     const LocalPass phase3_base = P->phase3[0];
     for (auto &q : P->phase3) pick(q, "PACO_GROUPS3", q.log2n >= 12 ? 3 : 1);
@@ -328,10 +364,12 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
     {
         const char *lay = std::getenv("PACO_LAYOUT");
         const bool want = !(lay && std::strcmp(lay, "paper") == 0);
-        LocalPass q = P->phase1[0];
+        LocalPass q = phase1_base;
         q.out_tr = 1;
         q.out_t = 0;
         q.out_ell = 0;
+        q.out_s = 0;
+        pick(q, "PACO_GROUPS1", q.log2n >= 12 ? 2 : 1);
         if (want && b1 == 0 && N1 >= paco::kMidTile && N2 >= paco::kMidTile && !q.no_fast &&
             paco::local_fft_fast_mode(q) == 2) {
             P->fused = true;
@@ -344,6 +382,7 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
         LocalPass q = phase3_base;
         q.in_t = 0;
         q.in_ell = 0;
+        q.in_s = 0;
         q.top_tw = 1;
         q.top_log2N = P->lN;
         q.top_log2Lo = P->lLo;
@@ -369,6 +408,8 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
     P->mid.t = t;
     P->mid.m1 = P->m1;
     P->mid.m2 = P->m2;
+    P->mid.s1 = P->s1;
+    P->mid.s2 = P->s2;
     P->mid.tw_hi = d_thi;
     P->mid.tw_lo = d_tlo;
     P->mid.tw_tile = d_ttile;
@@ -396,6 +437,11 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
                       P->phase3_two.log2n, 1 << P->phase3_two.log2T, (long long)g.tiles, g.threads, g.lds_bytes);
         desc += buf;
     }
+    if (P->s1 || P->s2) {
+        std::snprintf(buf, sizeof buf, " mixed-radix[N1=%lld^%d*2^%d N2=%lld^%d*2^%d]", (long long)b, P->m1, P->s1,
+                      (long long)b, P->m2, P->s2);
+        desc += buf;
+    }
     static const char *kPrecName[] = {"fp32", "fp16x3", "bf16x3", "bf16x6"};
     desc += std::string(" prec=") + kPrecName[int(dt)];
     P->desc = desc;
@@ -407,14 +453,18 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
 
 extern "C" {
 
-paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int32_t b,
-                             paco_dtype dt)
+}  // extern "C"
+
+namespace {
+
+paco_status create_with_inverse(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int32_t b, paco_dtype dt,
+                                bool mixed)
 {
-    paco_status st = create_impl(plan, N1, N2, p, b, dt);
+    paco_status st = create_impl(plan, N1, N2, p, b, dt, mixed);
     if (st != PACO_OK || N1 == N2) return st;  // square: the inverse reuses the forward passes
     const std::string note = g_last_error;
     paco_plan *inv = nullptr;
-    st = create_impl(&inv, N2, N1, p, b, dt);
+    st = create_impl(&inv, N2, N1, p, b, dt, mixed);
     if (st != PACO_OK) {
         const std::string why = g_last_error;
         paco_plan_destroy(*plan);
@@ -425,6 +475,22 @@ paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p
     (*plan)->inv = inv;
     g_last_error = note;
     return PACO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int32_t b,
+                             paco_dtype dt)
+{
+    return create_with_inverse(plan, N1, N2, p, b, dt, false);
+}
+
+paco_status paco_plan_create_mixed(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int32_t b,
+                                   paco_dtype dt)
+{
+    return create_with_inverse(plan, N1, N2, p, b, dt, true);
 }
 
 paco_status paco_plan_workspace_size(const paco_plan *plan, size_t *bytes)

@@ -131,6 +131,7 @@ struct Ctx {
     uint32_t ld8;              // row length in bytes
     uint32_t orow_out, k_out;  // generic: output row = orow_out + pi_out(k) * k_out
     int out_t, out_ell;
+    int out_s = 0;             // generic: short top digit of pi_out (mixed radix)
     bool act;                  // runtime tile width: this thread owns butterflies (tid < nt)
     float oscale = 0.f;        // nonzero: every output is stored as conj(y) * oscale
 };
@@ -455,7 +456,7 @@ __device__ __forceinline__ void run_stage(float2 (&v)[H * EG], const Ctx &c)
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
                         const uint32_t k = j + (r << LNS);
-                        const uint32_t m = uint32_t(digrev<GEN>(k, c.out_t, c.out_ell));
+                        const uint32_t m = uint32_t(digmap<GEN>(k, c.out_t, c.out_ell, c.out_s, true));
                         const uint32_t off = (c.orow_out + m * c.k_out) * c.ld8 + uint32_t(t) * 8u;
                         st2<COH>(c.dst + off, u[r]);
                     }

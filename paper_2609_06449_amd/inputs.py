@@ -88,6 +88,10 @@ CONFIGS = {
     "c2":  dict(N1=4096, N2=4096, p=64, b=16, gen="normal", seed=2),
     "c3s": dict(N1=1 << 14, N2=1 << 14, p=256, b=4, gen="normal", seed=3),
     "c3n": dict(N1=1 << 13, N2=1 << 15, p=128, b=2, gen="normal", seed=4),
+    # the 2^28 shapes with their literal bases (mixed-radix: 2^14 = 16^3 * 4,
+    # 2^13 = 8^4 * 2)
+    "c3s16": dict(N1=1 << 14, N2=1 << 14, p=256, b=16, gen="normal", seed=3),
+    "c3n8": dict(N1=1 << 13, N2=1 << 15, p=128, b=8, gen="normal", seed=4),
     "c4a": dict(N1=4096, N2=4096, p=64, b=16, gen="loguniform", seed=5),
     "c4b": dict(N1=4096, N2=1 << 14, p=64, b=4, gen="loguniform", seed=5),
 }

@@ -31,7 +31,8 @@ PACO_PACKED = 2
 
 # every symbol include/paco.h declares
 EXPORTED = (
-    "paco_plan_validate", "paco_plan_create", "paco_plan_workspace_size", "paco_execute",
+    "paco_plan_validate", "paco_plan_create", "paco_plan_validate_mixed", "paco_plan_create_mixed",
+    "paco_plan_workspace_size", "paco_execute",
     "paco_execute_stage", "paco_execute_inverse", "paco_execute_two_pass", "paco_plan_has_two_pass", "paco_plan_describe",
     "paco_plan_destroy", "paco_status_string",
     "paco_last_error", "paco_batch_plan_create", "paco_batch_workspace_size", "paco_execute_batched",
@@ -62,6 +63,8 @@ def _load() -> ctypes.CDLL:
     sig = {
         "paco_plan_validate": (st, [i64, i64, i64, i32, st]),
         "paco_plan_create": (st, [ctypes.POINTER(P), i64, i64, i64, i32, st]),
+        "paco_plan_validate_mixed": (st, [i64, i64, i64, i32, st]),
+        "paco_plan_create_mixed": (st, [ctypes.POINTER(P), i64, i64, i64, i32, st]),
         "paco_plan_workspace_size": (st, [P, ctypes.POINTER(sz)]),
         "paco_execute": (st, [P, P, P, P, sz, P]),
         "paco_execute_stage": (st, [P, st, st, P, P, P]),
@@ -118,6 +121,16 @@ def paco_plan_create(N1: int, N2: int, p: int, b: int, dt: int = PACO_C64) -> in
     return h.value
 
 
+def paco_plan_validate_mixed(N1: int, N2: int, p: int, b: int, dt: int = PACO_C64) -> int:
+    return int(_lib.paco_plan_validate_mixed(N1, N2, p, b, dt))
+
+
+def paco_plan_create_mixed(N1: int, N2: int, p: int, b: int, dt: int = PACO_C64) -> int:
+    h = ctypes.c_void_p()
+    _check(_lib.paco_plan_create_mixed(ctypes.byref(h), N1, N2, p, b, dt), "paco_plan_create_mixed")
+    return h.value
+
+
 def paco_plan_workspace_size(plan: int) -> int:
     n = ctypes.c_size_t()
     _check(_lib.paco_plan_workspace_size(plan, ctypes.byref(n)), "paco_plan_workspace_size")
@@ -160,9 +173,9 @@ def paco_plan_destroy(plan: int):
 class Plan:
     """Owns one paco_plan handle (created on the current HIP device)."""
 
-    def __init__(self, N1: int, N2: int, p: int, b: int, dt: int = PACO_C64):
+    def __init__(self, N1: int, N2: int, p: int, b: int, dt: int = PACO_C64, mixed: bool = False):
         self.N1, self.N2, self.p, self.b, self.dt = N1, N2, p, b, dt
-        self.handle = paco_plan_create(N1, N2, p, b, dt)
+        self.handle = (paco_plan_create_mixed if mixed else paco_plan_create)(N1, N2, p, b, dt)
         self.workspace_bytes = paco_plan_workspace_size(self.handle)
         self.launches, self.description = paco_plan_describe(self.handle)
         self.has_two_pass = paco_plan_has_two_pass(self.handle)

@@ -60,6 +60,25 @@ def test_validate_rejects(N1, N2, p, b, status):
     assert paco.paco_last_error()
 
 
+@pytest.mark.parametrize("N1,N2,p,b", [
+    (1 << 14, 1 << 14, 256, 16), (1 << 13, 1 << 15, 128, 8), (64, 32, 4, 4), (2, 16, 2, 4), (8, 8, 2, 16),
+    (64, 64, 4, 4),                                                     # powers of b are accepted too
+])
+def test_validate_mixed_accepts(N1, N2, p, b):
+    assert paco.paco_plan_validate_mixed(N1, N2, p, b) == paco.PACO_OK
+
+
+@pytest.mark.parametrize("N1,N2,p,b,status", [
+    (48, 64, 4, 4, paco.PACO_ERR_NOT_POWER_OF_B),      # not a power of two
+    (1, 64, 2, 4, paco.PACO_ERR_NOT_POWER_OF_B),
+    (64, 64, 4, 3, paco.PACO_ERR_NOT_POWER_OF_B),      # b not a power of two
+    (64, 32, 3, 4, paco.PACO_ERR_DIVISIBILITY),
+    (1 << 20, 16, 2, 16, paco.PACO_ERR_UNSUPPORTED),
+])
+def test_validate_mixed_rejects(N1, N2, p, b, status):
+    assert paco.paco_plan_validate_mixed(N1, N2, p, b) == status
+
+
 def test_validate_rejects_unknown_dtype():
     assert paco.paco_plan_validate(64, 64, 4, 4, 99) == paco.PACO_ERR_INVALID_ARG
 
