@@ -254,8 +254,12 @@ def bench_precision(steps: int, warmup: int):
 
 
 LARGE_WORKLOADS = [  # the full-HBM-scale shapes: N = 2^28 (2 GiB per buffer), N(0,1) inputs
-    dict(name="2^28 square", N1=1 << 14, N2=1 << 14, p=256, b=4, seed=3),
-    dict(name="2^28 non-square", N1=1 << 13, N2=1 << 15, p=128, b=2, seed=4),
+    # literal bases (mixed radix: 2^14 = 16^3 * 4, 2^13 = 8^4 * 2) ...
+    dict(name="2^28 square b=16", N1=1 << 14, N2=1 << 14, p=256, b=16, seed=3, mixed=True),
+    dict(name="2^28 non-square b=8", N1=1 << 13, N2=1 << 15, p=128, b=8, seed=4, mixed=True),
+    # ... and the largest bases of which both sizes are powers
+    dict(name="2^28 square b=4", N1=1 << 14, N2=1 << 14, p=256, b=4, seed=3),
+    dict(name="2^28 non-square b=2", N1=1 << 13, N2=1 << 15, p=128, b=2, seed=4),
 ]
 
 
@@ -276,7 +280,7 @@ def bench_large(steps: int, warmup: int):
         xd = torch.randn(N, dtype=torch.complex64, device="cuda", generator=gen)
         out = torch.empty_like(xd)
         ws = torch.empty_like(xd)
-        plan = paco.Plan(w["N1"], w["N2"], w["p"], w["b"])
+        plan = paco.Plan(w["N1"], w["N2"], w["p"], w["b"], mixed=w.get("mixed", False))
         for _ in range(warmup):
             plan.execute(xd.data_ptr(), out.data_ptr(), ws.data_ptr(), sh)
         torch.cuda.synchronize()
@@ -285,7 +289,8 @@ def bench_large(steps: int, warmup: int):
             plan.execute(xd.data_ptr(), out.data_ptr(), ws.data_ptr(), sh)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / steps
-        rec[w["name"]] = dict(N1=w["N1"], N2=w["N2"], p=w["p"], b=w["b"], ms=round(ms, 4),
+        rec[w["name"]] = dict(N1=w["N1"], N2=w["N2"], p=w["p"], b=w["b"], mixed=w.get("mixed", False),
+                              ms=round(ms, 4),
                               gflops=round(5.0 * N * math.log2(N) / (ms * 1e-3) / 1e9, 1),
                               hbm_frac_passes=round(16.0 * N * plan.launches / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                               hbm_frac_3pass=round(48.0 * N / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),

@@ -131,9 +131,10 @@ namespace {
 
 // Digit-aligned split of a local transform of 2^l = b^m 2^s items into
 // on-chip passes: one pass up to 2^12 items, otherwise two passes n1 * n2
-// with n1 = b^ceil(m/2) 2^s (the balanced split of section 4.1; the short
-// digit of a mixed-radix length goes with n1, whose digit maps carry it) and
-// n2 = b^floor(m/2); if n1 would exceed one pass, n1 = b^floor(m/2) 2^s.
+// with n1 = b^k 2^s and n2 = b^(m-k) (the short digit of a mixed-radix
+// length goes with n1, whose digit maps carry it), k chosen so that the two
+// lengths are as close as the digits allow (section 4.1's balanced split;
+// for s = 0, n1 = b^ceil(m/2)).  la = 0 when no split fits two passes.
 void split_local(int l, int t, int &la, int &lb)
 {
     if (l <= paco::kMaxOnChipLog2) {
@@ -142,8 +143,14 @@ void split_local(int l, int t, int &la, int &lb)
         return;
     }
     const int m = l / t, s = l % t;
-    la = ((m + 1) / 2) * t + s;
-    if (la > paco::kMaxOnChipLog2) la = (m / 2) * t + s;
+    la = 0;
+    for (int k = 0; k <= m; ++k) {
+        const int a = k * t + s, c = l - a;
+        if (a < 1 || c < 1 || a > paco::kMaxOnChipLog2 || c > paco::kMaxOnChipLog2) continue;
+        const int d = a > c ? a - c : c - a, dbest = la > l - la ? 2 * la - l : l - 2 * la;
+        if (la == 0 || d < dbest || (d == dbest && a > la)) la = a;
+    }
+    if (la == 0) la = l;  // no two-pass split: rejected by the caller
     lb = l - la;
 }
 
