@@ -321,3 +321,20 @@ def test_packed_flag_rejected_on_paper_plan():
     lib = paco.lib()
     s = torch.cuda.current_stream().cuda_stream
     assert lib.paco_execute_stage(plan.handle, 1, paco.PACO_PACKED, buf.data_ptr(), ws.data_ptr(), s) == paco.PACO_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("N1,N2,p,b", [(64, 16, 4, 4), (32, 64, 2, 2), (256, 16, 4, 16)])
+def test_stages_match_the_view_model(N1, N2, p, b):
+    # Phase I and Phase III in the paper's layouts against the literal view
+    # model of the local scheduler (appendix A/B)
+    from oracle import view_model as vm
+    m1, m2 = round(np.log(N1) / np.log(b)), round(np.log(N2) / np.log(b))
+    x = inputs.normal(N1 * N2, seed=51)
+    plan = paco.Plan(N1, N2, p, b)
+    s1 = _host(_stage(plan, 1, _dev(x))).reshape(N1, N2)
+    want1, _ = vm.local_phase(x.reshape(N1, N2), b, m1, m2, vm.OUT)
+    assert oracle.rel_l2(s1, want1) <= TOL
+    z = inputs.normal(N1 * N2, seed=52)
+    s3 = _host(_stage(plan, 3, _dev(z))).reshape(N2, N1)
+    want3, _ = vm.local_phase(z.reshape(N2, N1), b, m2, m1, vm.IN)
+    assert oracle.rel_l2(s3, want3) <= TOL
