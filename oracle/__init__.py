@@ -10,10 +10,13 @@ arithmetic.
 Contents
 --------
 * ``liboracle.so`` (``oracle.c``): the DFT by its definition (section 2), a
-  textbook recursive radix-2 FFT, brute-force base-b digit reversal
-  (appendix A.1) and the three stage-wise references (Phase I output layout,
-  the fused middle permutation with the top-level twiddle, Phase III input
-  layout; sections 3.1-3.4 and 4.2).  All in FP64.
+  textbook recursive radix-2 FFT, the inverse DFT, brute-force base-b digit
+  reversal (appendix A.1) and its mixed-radix reading for sizes b^m * r, and
+  the three stage-wise references (Phase I output layout, the fused middle
+  permutation with the top-level twiddle, Phase III input layout; sections
+  3.1-3.4 and 4.2).  All in FP64.
+* ``view_model``: a literal model of the view-based local scheduler
+  (appendix A.3-A.8, appendix B), a second reference for the layout algebra.
 * ``para_co_drp``: a literal, per-processor model of the redistribution
   procedure of appendix C.5 (pack by fused macro-element digit reversal, one
   block exchange, block transposes, unpack by macro-element digit reversal),
@@ -34,7 +37,8 @@ _lib = None
 
 __all__ = [
     "build", "digit_reverse", "digit_reverse_py", "dft", "dft_naive", "fft_radix2",
-    "dft_at", "phase1", "phase2", "phase3", "paco_reference",
+    "dft_at", "idft", "digit_reverse_n", "radices", "reverse_with_radices", "phase1", "phase2", "phase3",
+    "paco_reference",
     "para_co_drp", "fused_macro_digit_reversal", "macro_digit_reversal",
     "rel_l2",
 ]
