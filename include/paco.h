@@ -153,7 +153,9 @@ paco_status paco_execute(const paco_plan *plan, const void *in, void *out, void 
  * itself, with no further exchange.  The arithmetic is conj(Omega_N conj(y))
  * / N, the two conjugations and the 1/N scale (a power of two, exact) folded
  * into Phase I's loads and Phase III's stores: the same launches as
- * paco_execute.  All dtypes. */
+ * paco_execute.  All dtypes.  Returns PACO_ERR_UNSUPPORTED (the forward
+ * plan still works) if the N2 x N1 passes could not be built at plan
+ * creation (e.g. device memory for their tables). */
 paco_status paco_execute_inverse(const paco_plan *plan, const void *in, void *out, void *workspace,
                                  size_t workspace_bytes, void *stream);
 

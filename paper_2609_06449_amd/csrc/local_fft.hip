@@ -141,6 +141,7 @@ hipError_t launch_local_fft(const LocalPass &p, hipStream_t s)
     if (!k) return hipErrorInvalidValue;
     const LocalLaunch g = local_fft_geometry(p);
     if (g.tiles < 1 || g.tiles > 0x7fffffff) return hipErrorInvalidValue;
+    if (mode < 0 && g.threads > generic_max_threads(p.prec)) return hipErrorInvalidValue;
     void *args[] = {const_cast<LocalPass *>(&p)};
     return hipLaunchKernel(k, dim3(unsigned(g.tiles)), dim3(unsigned(g.threads)), args, g.lds_bytes, s);
 }

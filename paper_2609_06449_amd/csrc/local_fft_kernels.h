@@ -10,9 +10,11 @@
 namespace paco {
 namespace {
 
-// Generic pass: any descriptor, runtime tile width.
+// Generic pass: any descriptor, runtime tile width (at most
+// generic_max_threads(PREC) threads: the split MFMA forms' butterflies need
+// more registers, so their tiles are kept to 512 threads).
 template <int LOG2N, bool PRE, bool GEN, int PREC>
-__global__ __launch_bounds__(1024) void local_fft_kernel(LocalPass P)
+__global__ __launch_bounds__(generic_max_threads(PREC)) void local_fft_kernel(LocalPass P)
 {
     constexpr int EG = LOG2N < 4 ? (1 << LOG2N) : 16;
     constexpr int LR0 = stage_log2radix(LOG2N, 0);

@@ -96,6 +96,11 @@ __device__ __forceinline__ int64_t digrev(int64_t x, int t, int ell)
     }
 }
 
+// Largest workgroup of the generic local-FFT kernel for butterfly
+// arithmetic prec (0: FP32 VALU; the split MFMA forms get 512 threads and
+// with them 256 VGPRs per lane).
+__host__ __device__ constexpr int generic_max_threads(int prec) { return prec == 0 ? 1024 : 512; }
+
 // Mixed-radix digit maps over [0, b^ell 2^s) (0 <= s < t): the digits are
 // (b, ..., b, 2^s), least significant first.  The forward map pi reverses
 // the digit string and reads it with the radices reversed:

@@ -62,6 +62,7 @@ struct paco_plan_s {
     bool two_pass = false;                  // Phase III can read the packed buffer itself
     LocalPass phase3_two{};
     paco_plan_s *inv = nullptr;             // N2 x N1 passes of the inverse (NULL: square, this plan's)
+    std::string inv_error;                  // non-empty: the inverse passes could not be built
     std::string desc;
 };
 
@@ -367,6 +368,12 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
     for (auto &q : P->phase1) pick(q, "PACO_GROUPS1", q.log2n >= 12 ? 2 : 1);
     const LocalPass phase3_base = P->phase3[0];
     for (auto &q : P->phase3) pick(q, "PACO_GROUPS3", q.log2n >= 12 ? 3 : 1);
+    // generic passes of the split MFMA forms: at most 512 threads per tile
+    for (auto *ph : {&P->phase1, &P->phase3})
+        for (auto &q : *ph)
+            while (q.log2T > 0 && (q.no_fast || paco::local_fft_fast_mode(q) < 0) &&
+                   paco::local_fft_geometry(q).threads > paco::generic_max_threads(q.prec))
+                --q.log2T;
     // ---- fused pipeline: Phase I writes the packed slab transposed --------
     {
         const char *lay = std::getenv("PACO_LAYOUT");
@@ -473,11 +480,10 @@ paco_status create_with_inverse(paco_plan **plan, int64_t N1, int64_t N2, int64_
     paco_plan *inv = nullptr;
     st = create_impl(&inv, N2, N1, p, b, dt, mixed);
     if (st != PACO_OK) {
-        const std::string why = g_last_error;
-        paco_plan_destroy(*plan);
-        *plan = nullptr;
-        g_last_error = "inverse factorisation: " + why;
-        return st;
+        // the forward plan stands; paco_execute_inverse reports the reason
+        (*plan)->inv_error = "inverse (N2 x N1 passes) unavailable: " + g_last_error;
+        g_last_error = note;
+        return PACO_OK;
     }
     (*plan)->inv = inv;
     g_last_error = note;
@@ -607,6 +613,7 @@ paco_status paco_execute_inverse(const paco_plan *plan, const void *in, void *ou
 {
     paco_status st = check_buffers(plan, in, out, workspace, workspace_bytes);
     if (st != PACO_OK) return st;
+    if (!plan->inv_error.empty()) return fail(PACO_ERR_UNSUPPORTED, plan->inv_error);
     return run_three(plan->inv ? plan->inv : plan, in, out, workspace, static_cast<hipStream_t>(stream), true);
 }
 
