@@ -22,7 +22,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "FFT GFLOP/s (5N·log2N/t) + % HBM roofline, N=2^24 c64; MFMA-split vs FP32"
-WORKLOAD = dict(name="c2", N1=4096, N2=4096, p=64, b=16, gen="normal", seed=2)
+WORKLOAD = dict(name="2^24 as 4096 x 4096", N1=4096, N2=4096, p=64, b=16, gen="normal", seed=2)
 KERNEL_SOURCES = ["paper_2609_06449_amd/csrc/" + f for f in ("local_fft.hip", "middle.hip", "stages.h", "middle_dev.h",
                                                                   "paco_internal.h")]
 
@@ -35,7 +35,7 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-TRAFFIC_PATH = os.path.join(ROOT, "profiles", "traffic_c2.json")
+TRAFFIC_PATH = os.path.join(ROOT, "profiles", "traffic_2p24_4096x4096.json")
 COPY_BYTES = 1 << 28  # the --calibrate-copy device-to-device copy
 
 

@@ -84,16 +84,16 @@ def batch_inputs(sizes, seed: int = 6) -> np.ndarray:
 
 # The configured problems: (name, N1, N2, p, b, generator, seed).
 CONFIGS = {
-    "c1":  dict(N1=64, N2=64, p=4, b=4, gen="uniform", seed=1),
-    "c2":  dict(N1=4096, N2=4096, p=64, b=16, gen="normal", seed=2),
-    "c3s": dict(N1=1 << 14, N2=1 << 14, p=256, b=4, gen="normal", seed=3),
-    "c3n": dict(N1=1 << 13, N2=1 << 15, p=128, b=2, gen="normal", seed=4),
+    "n4096_64x64_b4":  dict(N1=64, N2=64, p=4, b=4, gen="uniform", seed=1),
+    "n2p24_4096x4096_b16":  dict(N1=4096, N2=4096, p=64, b=16, gen="normal", seed=2),
+    "n2p28_16384x16384_b4": dict(N1=1 << 14, N2=1 << 14, p=256, b=4, gen="normal", seed=3),
+    "n2p28_8192x32768_b2": dict(N1=1 << 13, N2=1 << 15, p=128, b=2, gen="normal", seed=4),
     # the 2^28 shapes with their literal bases (mixed-radix: 2^14 = 16^3 * 4,
     # 2^13 = 8^4 * 2)
-    "c3s16": dict(N1=1 << 14, N2=1 << 14, p=256, b=16, gen="normal", seed=3),
-    "c3n8": dict(N1=1 << 13, N2=1 << 15, p=128, b=8, gen="normal", seed=4),
-    "c4a": dict(N1=4096, N2=4096, p=64, b=16, gen="loguniform", seed=5),
-    "c4b": dict(N1=4096, N2=1 << 14, p=64, b=4, gen="loguniform", seed=5),
+    "n2p28_16384x16384_b16": dict(N1=1 << 14, N2=1 << 14, p=256, b=16, gen="normal", seed=3),
+    "n2p28_8192x32768_b8": dict(N1=1 << 13, N2=1 << 15, p=128, b=8, gen="normal", seed=4),
+    "n2p24_4096x4096_b16_loguniform": dict(N1=4096, N2=4096, p=64, b=16, gen="loguniform", seed=5),
+    "n2p26_4096x16384_b4_loguniform": dict(N1=4096, N2=1 << 14, p=64, b=4, gen="loguniform", seed=5),
 }
 
 

@@ -118,7 +118,7 @@ def test_mixed_plans_need_the_mixed_entry_point():
     assert np.array_equal(a.view(np.uint64), c.view(np.uint64))
 
 
-@pytest.mark.parametrize("name", ["c3s16", "c3n8"])
+@pytest.mark.parametrize("name", ["n2p28_16384x16384_b16", "n2p28_8192x32768_b8"])
 def test_mixed_2p28_literal_bases(name):
     # N = 2^28 with b = 16 (2^14 x 2^14, p = 256) and b = 8 (2^13 x 2^15,
     # p = 128): round trip through the inverse, Parseval, sampled outputs

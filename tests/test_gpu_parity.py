@@ -80,7 +80,7 @@ def test_end_to_end_matches_oracle(N1, N2, p, b):
     assert err <= TOL
 
 
-def test_c1_config_and_stages():
+def test_4096_as_64x64_and_stages():
     # N = 2^12 viewed 64 x 64, p = 4 slabs, b = 4, uniform[-1,1] inputs, seed 1
     N1, N2, p, b = 64, 64, 4, 4
     x = inputs.uniform(N1 * N2, seed=1)
@@ -187,7 +187,7 @@ def test_execute_argument_errors_on_device():
 # full-size configurations
 # ---------------------------------------------------------------------------
 
-def test_c2_full_size_against_oracle():
+def test_2p24_full_size_against_oracle():
     # N = 2^24 as 4096 x 4096, p = 64, b = 16, N(0,1) inputs, seed 2: the
     # complete output against the FP64 radix-2 oracle
     N1, N2, p, b = 4096, 4096, 64, 16
@@ -198,7 +198,7 @@ def test_c2_full_size_against_oracle():
     y = _host(_run(plan, xd))
     ref = oracle.fft_radix2(x)
     err = oracle.rel_l2(y, ref)
-    print(f"c2 rel_l2={err:.3e}", flush=True)
+    print(f"2^24 rel_l2={err:.3e}", flush=True)
     assert err <= TOL
     # sampled single outputs by the O(N) definition, per-item bound
     ks = np.array([0, 1, 4095, 4096, N // 2, N - 1, 12345678, 9876543])
@@ -224,8 +224,8 @@ def _round_trip_error(plan, xd):
     return float(num / den), y
 
 
-@pytest.mark.parametrize("name", ["c3s", "c3n"])
-def test_c3_full_size_sampled(name):
+@pytest.mark.parametrize("name", ["n2p28_16384x16384_b4", "n2p28_8192x32768_b2"])
+def test_2p28_full_size_sampled(name):
     cfg = inputs.CONFIGS[name]
     N1, N2, p, b = cfg["N1"], cfg["N2"], cfg["p"], cfg["b"]
     N = N1 * N2
