@@ -240,7 +240,9 @@ paco_status paco_batch_workspace_size(const paco_batch_plan *bp, size_t *bytes);
  * graph and replayed.  Executions of one batch plan must not overlap in
  * time (they share the plan's work-queue counters): issue them on one
  * stream.  A completion wait that exceeds its poll limit is counted (see
- * paco_batch_errors) instead of hanging. */
+ * paco_batch_errors) instead of hanging; the launch then still completes,
+ * with unspecified results.  The limit is 2^22 polls; the environment
+ * variable PACO_BATCH_SPIN_LIMIT at plan creation lowers it (testing). */
 paco_status paco_execute_batched(const paco_batch_plan *bp, const void *in, void *out, void *workspace,
                                  size_t workspace_bytes, void *stream);
 

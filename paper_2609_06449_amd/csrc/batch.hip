@@ -104,6 +104,7 @@ struct BatchArgs {
     const uint32_t *qbeg;  // tasks of queue q: [qbeg[q], qbeg[q + 1])
     uint32_t *tickets;     // one counter per queue, kTicketStride apart
     uint32_t *exits, *done, *errors;
+    uint32_t spin_limit;   // polls before a completion wait gives up (kSpinLimit)
 };
 
 // Tile variant v of a local length 2^l: 2^(12 - l + v) columns per tile;
@@ -312,7 +313,7 @@ __device__ __forceinline__ void wait_for(const BatchArgs &A, int32_t dep, uint32
     uint32_t spins = 0;
     while (__hip_atomic_load(A.done + dep, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
         __builtin_amdgcn_s_sleep(8);
-        if (++spins >= kSpinLimit) {
+        if (++spins >= A.spin_limit) {
             atomicAdd(A.errors, 1u);
             break;
         }
@@ -731,6 +732,13 @@ paco_status build_batch(paco_batch_plan_s *P)
     A.tickets = reinterpret_cast<uint32_t *>(at(i_tick));
     A.exits = reinterpret_cast<uint32_t *>(at(i_cnt));
     A.errors = reinterpret_cast<uint32_t *>(at(i_cnt) + 256);
+    // testing knob: a tiny poll limit forces the give-up path from the host
+    // (every wave still exits; results are then unspecified)
+    A.spin_limit = kSpinLimit;
+    if (const char *e = std::getenv("PACO_BATCH_SPIN_LIMIT")) {
+        const long long v = std::atoll(e);
+        if (v >= 1 && v < (1ll << 31)) A.spin_limit = uint32_t(v);
+    }
     A.done = reinterpret_cast<uint32_t *>(at(i_done));
     P->grid = int(std::min<int64_t>(int64_t(resident), int64_t(tasks.size())));
 

@@ -231,3 +231,31 @@ def test_batched_shared_queue_mode(monkeypatch):
     assert np.array_equal(y1.view(np.uint64), y2.view(np.uint64))
     _check_against_oracle(shared, x, y2)
     assert shared.errors() == 0 and per_xcd.errors() == 0
+
+
+def test_batched_wait_limit_forced_from_the_host(monkeypatch):
+    """A poll limit of one makes completion waits give up while their
+    producers are still running: the launch must still finish (every wave
+    exits), the give-ups must be counted, and a plan with the default limit
+    on the same buffers must be correct again afterwards."""
+    monkeypatch.setenv("PACO_BATCH_TUNE", "0")
+    sizes = [1 << 20] * 4 + [1 << 16] * 16
+    x = inputs.batch_inputs(sizes, seed=23)
+    xd = _dev(x)
+    monkeypatch.setenv("PACO_BATCH_SPIN_LIMIT", "1")
+    hasty = paco.BatchPlan(sizes)
+    out = torch.empty(hasty.total, dtype=torch.complex64, device="cuda")
+    ws = torch.empty(hasty.total, dtype=torch.complex64, device="cuda")
+    for _ in range(3):                         # the count is cumulative; stop once it moved
+        _run(hasty, xd, out, ws)
+        torch.cuda.synchronize()              # the launch finished
+        if hasty.errors():
+            break
+    gave_up = hasty.errors()
+    print(f"waits that gave up at a limit of one poll: {gave_up}", flush=True)
+    assert gave_up > 0
+    monkeypatch.delenv("PACO_BATCH_SPIN_LIMIT")
+    patient = paco.BatchPlan(sizes)
+    y = _host(_run(patient, xd, out, ws))
+    assert patient.errors() == 0
+    _check_against_oracle(patient, x, y, idx=[0, 4, 19])
