@@ -80,7 +80,12 @@ int32_t local_fft_fast_mode(const LocalPass &p)
     // single-pass Phase I (pi on output rows) or Phase III (pi on input rows)
     if (p.pre_tw || p.n_outer != 1 || p.o_in || p.o_out || p.j_in != 1 || p.k_out != 1) return -1;
     if (p.in_s || p.out_s) return -1;  // mixed-radix row maps: generic kernel
-    if (p.log2T != fast_tile_log2T(p.log2n, p.groups >= 2 ? 2 : 1, p.groups == 3 ? 32 : 16)) return -1;
+    // tile width: the split forms' operand-layout tile (16^s points, one
+    // group) has its own (mf_log2T); every other fast tile fast_tile_log2T
+    const bool mf = p.prec != 0 && p.log2n >= 4 && p.log2n % 4 == 0 && p.groups < 2;
+    const int want = mf ? mf_log2T(p.log2n, p.out_tr ? 2 : 0)
+                        : fast_tile_log2T(p.log2n, p.groups >= 2 ? 2 : 1, p.groups == 3 ? 32 : 16);
+    if (p.log2T != want) return -1;
     int mode = -1, tb = 0;
     if (p.top_tw) {
         if (p.in_ell || p.out_ell || p.out_tr) return -1;

@@ -108,13 +108,13 @@ __global__ __launch_bounds__(fast_threads(LOG2N, H, EG)) void local_fft_fast_ker
 // Single-pass tile of a 16^s-point transform with every butterfly on MFMA in
 // the operand layout (the split forms' fast kernel for those lengths).
 template <int LOG2N, int MODE, int TB, int PREC>
-__global__ __launch_bounds__(fast_threads(LOG2N, 1, 16)) void local_fft_mf_kernel(LocalPass P)
+__global__ __launch_bounds__((1 << (LOG2N + mf_log2T(LOG2N, MODE))) / 16) void local_fft_mf_kernel(LocalPass P)
 {
-    constexpr int LT = fast_tile_log2T(LOG2N, 1, 16);
+    constexpr int LT = mf_log2T(LOG2N, MODE);
     extern __shared__ float2 smem[];
     const int64_t col0 = tile_order(blockIdx.x, gridDim.x) << LT;
-    mf_tile<LOG2N, MODE, TB, PREC>(P.src, P.dst, uint32_t(P.ld), col0, P.stw, smem, threadIdx.x, P.conj_in != 0,
-                                   P.out_scale);
+    mf_tile<LOG2N, MODE, TB, PREC, LT>(P.src, P.dst, uint32_t(P.ld), col0, P.stw, smem, threadIdx.x, P.conj_in != 0,
+                                       P.out_scale);
 }
 
 template <int L, bool PRE, bool GEN, int PREC>

@@ -96,6 +96,18 @@ __device__ __forceinline__ int64_t digrev(int64_t x, int t, int ell)
     }
 }
 
+// Tile width of the fast kernels: 4096 items per workgroup for short
+// transforms, 4 columns (32-byte row runs) for long ones.
+__host__ __device__ constexpr int fast_log2T(int l) { return l >= 10 ? 2 : 12 - l; }
+
+// Columns (log2) of the split forms' operand-layout tile (mode 2: the
+// transposed store of Phase I): a 4096-point Phase I takes 2 columns (512
+// threads, half the LDS, so two workgroups per CU overlap each other;
+// measured 18-20% faster than one 4-column workgroup per CU); every other
+// tile keeps fast_log2T columns (a 2-column row store, 16-byte runs, is
+// slower).
+__host__ __device__ constexpr int mf_log2T(int l, int mode) { return (mode == 2 && l == 12) ? 1 : fast_log2T(l); }
+
 // Largest workgroup of the generic local-FFT kernel for butterfly
 // arithmetic prec (0: FP32 VALU; the split MFMA forms get 512 threads and
 // with them 256 VGPRs per lane).

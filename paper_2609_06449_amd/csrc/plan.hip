@@ -384,6 +384,8 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
         q.out_ell = 0;
         q.out_s = 0;
         pick(q, "PACO_GROUPS1", q.log2n >= 12 ? 2 : 1);
+        if (q.prec != 0 && q.log2n >= 4 && q.log2n % 4 == 0)  // the operand-layout tile's own width
+            q.log2T = paco::mf_log2T(q.log2n, 2);
         if (want && b1 == 0 && N1 >= paco::kMidTile && N2 >= paco::kMidTile && !q.no_fast &&
             paco::local_fft_fast_mode(q) == 2) {
             P->fused = true;

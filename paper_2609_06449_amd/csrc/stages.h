@@ -119,9 +119,6 @@ constexpr int crev(int x, int tb, int nd)
     return r;
 }
 
-// Tile width of the fast kernels: 4096 items per workgroup for short
-// transforms, 4 columns (32-byte row runs) for long ones.
-constexpr int fast_log2T(int l) { return l >= 10 ? 2 : 12 - l; }
 
 struct Ctx {
     float2 *lds;

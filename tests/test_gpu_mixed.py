@@ -142,3 +142,18 @@ def test_mixed_2p28_literal_bases(name):
     assert abs(ey - N * ex) <= 2e-6 * N * ex
     ks = np.array([0, 1, N1 - 1, N1, N // 2 + 3, N - 1])
     assert np.max(np.abs(y[ks] - oracle.dft_at(x, ks))) < 1e-5 * np.sqrt(ex)
+
+
+@pytest.mark.parametrize("dt,tol", [(paco.PACO_C64_MFMA_FP16X3, 1e-6), (paco.PACO_C64_MFMA_BF16X3, 3e-5),
+                                    (paco.PACO_C64_MFMA_BF16X6, 1e-6)])
+@pytest.mark.parametrize("N1,N2,p,b", [(32, 64, 4, 16), (4096, 2048, 16, 16), (1 << 13, 16, 16, 8)])
+def test_mixed_split_forms(N1, N2, p, b, dt, tol):
+    # the split MFMA butterflies with mixed-radix row maps (generic passes)
+    x = inputs.loguniform(N1 * N2, seed=46)
+    plan = _plan(N1, N2, p, b, dt=dt)
+    y = _call(plan.execute, plan, _dev(x)).cpu().numpy()
+    err = oracle.rel_l2(y, oracle.dft(x))
+    print(f"mixed {N1}x{N2} b={b} dt={dt}: rel-L2 {err:.3e}", flush=True)
+    assert err <= tol
+    back = _call(plan.execute_inverse, plan, _dev(y)).cpu().numpy()
+    assert oracle.rel_l2(back, x) <= 2 * tol
