@@ -158,9 +158,11 @@ const void *fast_for_tb(int mode)
                          : reinterpret_cast<const void *>(&local_fft_mf_kernel<L, 1, TB, PREC>);
 
     } else {
-        if (mode == 3)  // the two-pass form's Phase III: FP32 only
-            return (TB == 1 && PREC == kPrecFP32) ? reinterpret_cast<const void *>(&local_fft_fast_kernel<L, 3, 1, H, EG, PREC>)
-                                                  : nullptr;
+        if (mode == 3) {  // the two-pass form's Phase III: FP32 only
+            if constexpr (TB == 1 && PREC == kPrecFP32)
+                return reinterpret_cast<const void *>(&local_fft_fast_kernel<L, 3, 1, H, EG, PREC>);
+            return nullptr;
+        }
         if (mode == 2) return TB == 1 ? reinterpret_cast<const void *>(&local_fft_fast_kernel<L, 2, 1, H, EG, PREC>) : nullptr;
         return mode == 0 ? reinterpret_cast<const void *>(&local_fft_fast_kernel<L, 0, TB, H, EG, PREC>)
                          : reinterpret_cast<const void *>(&local_fft_fast_kernel<L, 1, TB, H, EG, PREC>);
