@@ -57,7 +57,7 @@ __global__ __launch_bounds__(kThreads) void middle_kernel(MiddlePass P)
         const int vi = rg + q * rstep;
         if (FULL || vi < TV) {
             const int64_t a = digmap<GEN>(v0 + vi, P.t, P.m1, P.s1, true);
-            x[q] = P.ws[a * P.N2 + c];
+            x[q] = ld2_last(P.ws + a * P.N2 + c);
             if (TW) t4[q] = P.tw_tile[vi * kTwTile + ci];
         }
     }

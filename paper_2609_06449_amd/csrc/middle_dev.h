@@ -40,7 +40,7 @@ __device__ __forceinline__ void middle_packed_tile(const MiddlePass &P, int64_t 
 #pragma unroll
     for (int q = 0; q < kMidPerThread; ++q) {
         const int ci = w + 4 * q;
-        x[q] = P.ws[(c0 + ci) * P.N1 + v0 + lane];
+        x[q] = ld2_last(P.ws + (c0 + ci) * P.N1 + v0 + lane);
         if (TW) t4[q] = P.tw_tile[ci * kTwTile + lane];
     }
 #pragma unroll
@@ -82,7 +82,7 @@ __device__ __forceinline__ void middle_packed2_tile(const MiddlePass &P, int64_t
 #pragma unroll
     for (int q = 0; q < kMidPerThread; ++q) {
         const int ci = w + 4 * q;
-        x[q] = *reinterpret_cast<const float4 *>(P.ws + (c0 + ci) * P.N1 + v0 + vi);
+        x[q] = ld4_last(P.ws + (c0 + ci) * P.N1 + v0 + vi);
         if (TW) t4[q] = *reinterpret_cast<const float4 *>(P.tw_tile + ci * kTwTile + vi);
     }
 #pragma unroll

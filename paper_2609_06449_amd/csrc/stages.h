@@ -77,6 +77,25 @@ __device__ __forceinline__ void dft_regs(float2 *v)
 // through this XCD's L2), for results another workgroup of the same launch
 // reads after a completion counter says they are there; the 16-byte form
 // becomes two such 8-byte stores.
+// Loads of data the transform never reads again (Phase II's source buffer):
+// non-temporal, so they do not push out of the caches the lines just written
+// for the next phase (on a 2^24 transform, whose three 128 MB buffers
+// overflow the 256 MB MALL, this keeps Phase III's input resident: measured
+// 13% faster end to end; the same hint on other phases' loads or on stores
+// measured slower).
+typedef float nt_f2 __attribute__((ext_vector_type(2)));
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float2 ld2_last(const float2 *p)
+{
+    const nt_f2 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f2 *>(p));
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ float4 ld4_last(const float2 *p)
+{
+    const nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4 *>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
 template <bool COH>
 __device__ __forceinline__ void st2(char *p, float2 v)
 {
