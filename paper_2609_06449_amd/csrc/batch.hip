@@ -755,6 +755,8 @@ paco_status build_batch(paco_batch_plan_s *P)
                       1 << var_log2T(sp.l1, sp.v1), 1 << var_log2T(sp.l2, sp.v3), is_small(kv.first) ? "(wg)" : "");
         P->desc += buf;
     }
+    if (const char *lg = std::getenv("PACO_LOG"))  // plan summary on stderr
+        if (lg[0] == '1') std::fprintf(stderr, "paco batch plan: %s\n", P->desc.c_str());
     return PACO_OK;
 }
 
@@ -841,13 +843,34 @@ bool valid_plan(int k, const SizePlan &sp)
     return false;
 }
 
-// Tuning cache: text lines "log2N l1 l2 t v1 v3"; '#' starts a comment.
-void read_cache(const char *path, std::map<int, SizePlan> &plans)
+// The device a tuning cache was measured on: its entries are reused only on
+// the same architecture, CU count and cache format.
+std::string cache_key()
+{
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string arch = prop.gcnArchName;
+    for (char &ch : arch)
+        if (ch == ' ') ch = '_';
+    return arch + " cus=" + std::to_string(prop.multiProcessorCount) + " format=1";
+}
+
+// Tuning cache: a "key <device key>" line, then lines "log2N l1 l2 t v1 v3";
+// '#' starts a comment.  A file with another key (or none) is ignored, and
+// rewritten after tuning.
+void read_cache(const char *path, const std::string &key, std::map<int, SizePlan> &plans)
 {
     std::ifstream f(path);
     std::string line;
+    bool keyed = false;
     while (std::getline(f, line)) {
         if (line.empty() || line[0] == '#') continue;
+        if (line.compare(0, 4, "key ") == 0) {
+            keyed = line.substr(4) == key;
+            continue;
+        }
+        if (!keyed) continue;
         std::istringstream is(line);
         int k;
         SizePlan sp;
@@ -856,11 +879,12 @@ void read_cache(const char *path, std::map<int, SizePlan> &plans)
     }
 }
 
-bool write_cache(const char *path, const std::map<int, SizePlan> &plans)
+bool write_cache(const char *path, const std::string &key, const std::map<int, SizePlan> &plans)
 {
     std::ofstream f(path);
     if (!f) return false;
     f << "# paco batched plan cache: log2N l1 l2 t v1 v3 (N1 = 2^l1, N2 = 2^l2, b = 2^t, tile variants)\n";
+    f << "key " << key << '\n';
     for (auto &kv : plans)
         f << kv.first << ' ' << kv.second.l1 << ' ' << kv.second.l2 << ' ' << kv.second.t << ' ' << kv.second.v1 << ' '
           << kv.second.v3 << '\n';
@@ -914,7 +938,8 @@ paco_status paco_batch_plan_create(paco_batch_plan **bp, int32_t count, const in
     }
     // per-size plans: cache file, then tuning (unless PACO_BATCH_TUNE=0), else defaults
     std::map<int, SizePlan> plans;
-    if (tune_cache_path) read_cache(tune_cache_path, plans);
+    const std::string key = cache_key();
+    if (tune_cache_path) read_cache(tune_cache_path, key, plans);
     std::vector<int> missing;
     for (int k : ks)
         if (!plans.count(k)) missing.push_back(k);
@@ -930,7 +955,7 @@ paco_status paco_batch_plan_create(paco_batch_plan **bp, int32_t count, const in
     for (int k : ks)
         if (!plans.count(k)) plans[k] = paco::candidates(k).front();
     for (int k : ks) P->plans[k] = plans[k];
-    if (tune_cache_path && !missing.empty() && tuning && !write_cache(tune_cache_path, plans)) {
+    if (tune_cache_path && !missing.empty() && tuning && !write_cache(tune_cache_path, key, plans)) {
         free_plan(P);
         return bfail(PACO_ERR_INVALID_ARG, std::string("cannot write the tuning cache ") + tune_cache_path);
     }

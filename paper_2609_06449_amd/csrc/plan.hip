@@ -461,6 +461,10 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
     static const char *kPrecName[] = {"fp32", "fp16x3", "bf16x3", "bf16x6"};
     desc += std::string(" prec=") + kPrecName[int(dt)];
     P->desc = desc;
+    if (const char *lg = std::getenv("PACO_LOG"))  // plan summary on stderr
+        if (lg[0] == '1')
+            std::fprintf(stderr, "paco plan N1=%lld N2=%lld p=%lld b=%d: %s\n", (long long)N1, (long long)N2,
+                         (long long)p, b, desc.c_str());
     *plan = P;
     return PACO_OK;
 }

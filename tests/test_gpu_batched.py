@@ -79,7 +79,10 @@ def test_batched_tuned_cache_roundtrip(tmp_path):
     sizes = [1 << k for k in (5, 12, 13, 17, 20)]
     cache = str(tmp_path / "tune.txt")
     plan = paco.BatchPlan(sizes, tune_cache_path=cache)
-    lines = [ln for ln in open(cache).read().splitlines() if ln and not ln.startswith("#")]
+    text = open(cache).read().splitlines()
+    keys = [ln for ln in text if ln.startswith("key ")]
+    assert len(keys) == 1 and "gfx950" in keys[0], keys      # measured on this device
+    lines = [ln for ln in text if ln and not ln.startswith("#") and not ln.startswith("key ")]
     assert sorted(int(ln.split()[0]) for ln in lines) == [5, 12, 13, 17, 20]
     choices = [plan.transform_plan(i) for i in range(len(sizes))]
     for (n1, n2, p, b), n in zip(choices, sizes):
@@ -90,6 +93,11 @@ def test_batched_tuned_cache_roundtrip(tmp_path):
     x = inputs.batch_inputs(sizes, seed=13)
     y = _host(_run(again, _dev(x)))
     _check_against_oracle(again, x, y)
+    # a cache measured elsewhere is not trusted: retuned and rewritten with this device's key
+    with open(cache, "w") as f:
+        f.write("key some-other-device cus=1 format=1\n" + "\n".join(lines) + "\n")
+    paco.BatchPlan(sizes[:2], tune_cache_path=cache)
+    assert [ln for ln in open(cache).read().splitlines() if ln.startswith("key ")] == keys
 
 
 def test_batched_bit_identical_to_single_plans(untuned):

@@ -338,3 +338,15 @@ def test_stages_match_the_view_model(N1, N2, p, b):
     s3 = _host(_stage(plan, 3, _dev(z))).reshape(N2, N1)
     want3, _ = vm.local_phase(z.reshape(N2, N1), b, m2, m1, vm.IN)
     assert oracle.rel_l2(s3, want3) <= TOL
+
+
+def test_plan_log_on_stderr():
+    # PACO_LOG=1: the plan summary goes to stderr at plan creation
+    import subprocess
+    import sys
+    code = ("import torch; torch.zeros(1, device='cuda');"
+            "from paper_2609_06449_amd import paco; paco.Plan(64, 64, 4, 4)")
+    env = dict(__import__("os").environ, PACO_LOG="1")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    assert "paco plan N1=64 N2=64 p=4 b=4:" in r.stderr, r.stderr

@@ -10,6 +10,7 @@ pipeline against the paper's worked example, identities and counts.
   source/destination slab pair moves exactly N/p^2 items (section 4.2).
 * Theorem 3: the three stage references composed equal the plain DFT.
 """
+import math
 import os
 
 import numpy as np
@@ -344,3 +345,66 @@ def test_mixed_stage_layouts(N1, N2, b):
     phys = np.empty_like(logical)
     phys[p2, :] = logical
     assert np.max(np.abs(oracle.phase3(phys, N1, N2, b) - np.fft.fft(logical, axis=0))) < 1e-9
+
+
+# ---------------------------------------------------------------------------
+# Operator identities of the proof of Theorem 3 (section 3.4), as matrices
+# ---------------------------------------------------------------------------
+
+def _perm_matrix(perm):
+    # layout operator P_pi: (P z)[i] = z[pi(i)]
+    n = len(perm)
+    P = np.zeros((n, n))
+    P[np.arange(n), perm] = 1.0
+    return P
+
+
+def _omega_exact(n):
+    k = np.arange(n)
+    return np.exp(-2j * np.pi * ((np.outer(k, k)) % n) / n)
+
+
+def _swap(n1, n2):
+    # Pi_swap: C^{n1} (x) C^{n2} -> C^{n2} (x) C^{n1}, (Pi z)[u, v] = z[v, u]
+    S = np.zeros((n1 * n2, n1 * n2))
+    for u in range(n2):
+        for v in range(n1):
+            S[u * n1 + v, v * n2 + u] = 1.0
+    return S
+
+
+@pytest.mark.parametrize("N1,N2,b", [(4, 8, 2), (16, 4, 4), (8, 8, 8), (16, 16, 4), (9, 27, 3)])
+def test_middle_permutation_factorisation(N1, N2, b):
+    # P_{pi_m} = (P_{pi_m2} (x) I_N1) Pi_swap (P_{pi_m1} (x) I_N2)
+    m1, m2 = round(math.log(N1, b)), round(math.log(N2, b))
+    N = N1 * N2
+    pim = _perm_matrix([oracle.digit_reverse_py(i, b, m1 + m2) for i in range(N)])
+    p1 = _perm_matrix([oracle.digit_reverse_py(a, b, m1) for a in range(N1)])
+    p2 = _perm_matrix([oracle.digit_reverse_py(c, b, m2) for c in range(N2)])
+    rhs = np.kron(p2, np.eye(N1)) @ _swap(N1, N2) @ np.kron(p1, np.eye(N2))
+    assert np.array_equal(pim, rhs)
+
+
+@pytest.mark.parametrize("N1,N2,b", [(4, 8, 2), (16, 4, 4), (8, 8, 8), (9, 27, 3)])
+def test_twiddle_conjugation_and_four_step(N1, N2, b):
+    m1 = round(math.log(N1, b))
+    N = N1 * N2
+    P1 = np.kron(_perm_matrix([oracle.digit_reverse_py(a, b, m1) for a in range(N1)]), np.eye(N2))
+    k1 = np.repeat(np.arange(N1), N2)
+    j2 = np.tile(np.arange(N2), N1)
+    Dt = np.diag(np.exp(-2j * np.pi * ((k1 * j2) % N) / N))              # D~_{(k1, j2)} = w_N^{-k1 j2}
+    pk = np.repeat([oracle.digit_reverse_py(a, b, m1) for a in range(N1)], N2)
+    Dtw = np.diag(np.exp(-2j * np.pi * ((pk * j2) % N) / N))             # w_N^{-pi(a) c} at (a, c)
+    assert np.max(np.abs(Dtw - P1 @ Dt @ P1)) < 1e-12
+    # the four-step operator (Omega_N2 (x) I) Pi_swap D~ (Omega_N1 (x) I) is the DFT
+    # with output (k2, k1) = y[k1 + k2 N1], i.e. Omega_N itself on the flat vectors
+    F = np.kron(_omega_exact(N2), np.eye(N1)) @ _swap(N1, N2) @ Dt @ np.kron(_omega_exact(N1), np.eye(N2))
+    assert np.max(np.abs(F - _omega_exact(N))) < 1e-9
+    # and PACO's composite (B (x) I) P_{pi_m} D_tw (A (x) I), A = P_pi Omega, B = Omega P_pi
+    m2 = round(math.log(N2, b))
+    pi1 = _perm_matrix([oracle.digit_reverse_py(a, b, m1) for a in range(N1)])
+    pi2 = _perm_matrix([oracle.digit_reverse_py(c, b, m2) for c in range(N2)])
+    pim = _perm_matrix([oracle.digit_reverse_py(i, b, m1 + m2) for i in range(N)])
+    A = np.kron(pi1 @ _omega_exact(N1), np.eye(N2))
+    B = np.kron(_omega_exact(N2) @ pi2, np.eye(N1))
+    assert np.max(np.abs(B @ pim @ Dtw @ A - _omega_exact(N))) < 1e-9
