@@ -6,6 +6,19 @@ permutation -> Phase III LocalFFT) of the N = 2^24 complex64 workload
 ABI.  Inputs are resident in HBM before the timed region.  Prints one JSON
 line: GFLOP/s = 5 N log2 N / t, plus the dominant kernel's roofline (HIP
 events on the stream the kernels run on) and the CPU oracle baseline.
+
+Further fields of the same line (each leg can be skipped by a flag):
+  two_pass   the two-HBM-pass form of the same transform (an ablation,
+             reported beside the three-pass value, never as it)
+  batched    4096 transforms, N_i = 2^k, k ~ U{8..20}, in one persistent
+             launch replayed from a graph, against a loop of single calls
+  large      N = 2^28 in two shapes, with their literal (mixed-radix) bases
+             and with the largest bases of which both sizes are powers
+  precision  FP32 and the split MFMA forms at 2^24 and 2^26 on log-uniform
+             inputs, with their rel-L2 and worst-output errors vs FP64
+--calibrate-copy adds the device copy that scales rocprofv3's FETCH_SIZE /
+WRITE_SIZE counters; --traffic-from turns two such counter files into
+profiles/traffic_2p24_4096x4096.json (the roofline's traffic field).
 """
 from __future__ import annotations
 
