@@ -93,7 +93,7 @@ int32_t local_fft_fast_mode(const LocalPass &p)
         tb = 1;
     } else if (p.out_tr) {
         if (p.in_ell || p.out_ell) return -1;
-        mode = 2;
+        mode = p.src_last ? 4 : 2;
         tb = 1;
     } else {
         if (p.out_ell && !p.in_ell) { mode = 0; tb = p.out_t; }
@@ -126,7 +126,7 @@ hipError_t local_fft_prepare()
                                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
             if (e != hipSuccess) return e;
         }
-        for (int mode = 0; mode < 4; ++mode)
+        for (int mode = 0; mode < 5; ++mode)
             for (int tb : {1, 2, 4})
                 for (int grp : {1, 2, 3}) {
                 const void *k = fast_kernel(prec, l, mode, tb, grp);

@@ -152,15 +152,16 @@ const void *fast_for_tb(int mode)
                   (EG == 32 && H != 2) || (EG == 32 && PREC != kPrecFP32)) {
         return nullptr;
     } else if constexpr (PREC != kPrecFP32 && L % 4 == 0 && H == 1 && EG == 16) {
-        if (mode == 3) return nullptr;
+        if (mode == 3 || mode == 4) return nullptr;
         if (mode == 2) return TB == 1 ? reinterpret_cast<const void *>(&local_fft_mf_kernel<L, 2, 1, PREC>) : nullptr;
         return mode == 0 ? reinterpret_cast<const void *>(&local_fft_mf_kernel<L, 0, TB, PREC>)
                          : reinterpret_cast<const void *>(&local_fft_mf_kernel<L, 1, TB, PREC>);
 
     } else {
-        if (mode == 3) {  // the two-pass form's Phase III: FP32 only
+        if (mode == 3 || mode == 4) {  // the two-pass form's Phase III and Phase I: FP32 only
             if constexpr (TB == 1 && PREC == kPrecFP32)
-                return reinterpret_cast<const void *>(&local_fft_fast_kernel<L, 3, 1, H, EG, PREC>);
+                return mode == 3 ? reinterpret_cast<const void *>(&local_fft_fast_kernel<L, 3, 1, H, EG, PREC>)
+                                 : reinterpret_cast<const void *>(&local_fft_fast_kernel<L, 4, 1, H, EG, PREC>);
             return nullptr;
         }
         if (mode == 2) return TB == 1 ? reinterpret_cast<const void *>(&local_fft_fast_kernel<L, 2, 1, H, EG, PREC>) : nullptr;

@@ -164,6 +164,7 @@ struct LocalPass {
     int32_t tw_t, tw_ell, tw_s;  // f(o) = digmap(o, tw_t, tw_ell, tw_s, forward)
     int32_t no_fast;       // 1: always use the generic kernel (testing)
     int32_t out_tr;        // 1: write the output transposed (row = column, n items; fast kernel only)
+    int32_t src_last;      // with out_tr: the source is read for the last time (non-temporal loads)
     int32_t groups;        // fast kernel: 1, or 2 column groups taking turns in LDS
     int32_t prec;          // radix-16 butterflies: 0 FP32 VALU, 1 FP16x3, 2 BF16x3, 3 BF16x6 (MFMA)
     // top-level twiddle on load (the two-pass form of Phase III): input item

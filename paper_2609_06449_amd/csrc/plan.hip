@@ -60,7 +60,7 @@ struct paco_plan_s {
     bool fused = false;                     // packed Phase-I buffer (see paco_execute)
     LocalPass phase1_packed{};
     bool two_pass = false;                  // Phase III can read the packed buffer itself
-    LocalPass phase3_two{};
+    LocalPass phase1_two{}, phase3_two{};   // the two-pass form's passes
     paco_plan_s *inv = nullptr;             // N2 x N1 passes of the inverse (NULL: square, this plan's)
     std::string inv_error;                  // non-empty: the inverse passes could not be built
     std::string desc;
@@ -409,6 +409,10 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
         if (!q.no_fast && paco::local_fft_fast_mode(q) == 3) {
             P->two_pass = true;
             P->phase3_two = q;
+            // its Phase I: the packed pass, reading x for the last time
+            P->phase1_two = P->phase1_packed;
+            P->phase1_two.src_last = 1;
+            if (paco::local_fft_fast_mode(P->phase1_two) != 4) P->phase1_two = P->phase1_packed;
         }
     }
     for (auto *ph : {&P->phase1, &P->phase3})
@@ -632,7 +636,7 @@ paco_status paco_execute_two_pass(const paco_plan *plan, const void *in, void *o
     paco_status st = check_buffers(plan, in, out, workspace, workspace_bytes);
     if (st != PACO_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    st = run_local({plan->phase1_packed}, in, workspace, s);
+    st = run_local({plan->phase1_two}, in, workspace, s);
     if (st != PACO_OK) return st;
     return run_local({plan->phase3_two}, workspace, out, s);
 }

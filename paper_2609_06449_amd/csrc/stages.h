@@ -517,7 +517,10 @@ struct TopTw {
 };
 
 // One column tile of a single-pass local transform, the body of the fast
-// kernels.  MODE 3: natural input rows scaled by the top-level twiddle on
+// kernels.  MODE 4: MODE 2 reading its source with last-use (non-temporal)
+// loads: Phase I of the two-pass form, whose next pass reads only what this
+// one writes (in the three-pass pipeline the same hint measured slower).
+// MODE 3: natural input rows scaled by the top-level twiddle on
 // load (TopTw), natural output rows: Phase III of the two-pass form, which
 // reads the packed Phase-I buffer directly.  MODE 0: natural input rows, digit-reversed
 // output rows (Phase I, A = P_pi Omega).  MODE 1: digit-reversed input rows,
@@ -559,7 +562,7 @@ __device__ __forceinline__ void fast_tile(const float2 *srcm, float2 *dstm, uint
     for (int q = 0; q < NB0; ++q) {
         const int g = tid + q * NT;
         const int t = (g & ((1 << LTG) - 1)) * H, j = g >> LTG;
-        constexpr bool NAT = MODE == 0 || MODE == 2 || MODE == 3;  // natural input rows
+        constexpr bool NAT = MODE == 0 || MODE == 2 || MODE == 3 || MODE == 4;  // natural input rows
         uint32_t base;
         if constexpr (NAT)
             base = uint32_t(j) * ld8 + uint32_t(t) * 8u;
@@ -568,12 +571,15 @@ __device__ __forceinline__ void fast_tile(const float2 *srcm, float2 *dstm, uint
 #pragma unroll
         for (int r = 0; r < R0; ++r) {
             const uint32_t row_off = NAT ? (uint32_t(r) << LNR0) * ld8 : uint32_t(crev(r, TB, LR0 / TB)) * ld8;
+            const char *pa = src + base + row_off;
             if constexpr (H == 2) {
-                const float4 a = *reinterpret_cast<const float4 *>(src + base + row_off);
+                const float4 a = MODE == 4 ? ld4_last(reinterpret_cast<const float2 *>(pa))
+                                           : *reinterpret_cast<const float4 *>(pa);
                 v[q * R0 + r] = make_float2(a.x, a.y);
                 v[EG + q * R0 + r] = make_float2(a.z, a.w);
             } else {
-                v[q * R0 + r] = *reinterpret_cast<const float2 *>(src + base + row_off);
+                v[q * R0 + r] = MODE == 4 ? ld2_last(reinterpret_cast<const float2 *>(pa))
+                                          : *reinterpret_cast<const float2 *>(pa);
             }
         }
         if (conj_in) {  // the inverse transform's input map
@@ -604,7 +610,7 @@ __device__ __forceinline__ void fast_tile(const float2 *srcm, float2 *dstm, uint
     c.tid = tid;
     c.nt = NT;
     c.log2T = LTG;
-    c.dst = reinterpret_cast<char *>(MODE == 2 ? dstm + (col0 << LOG2N) : dstm + col0);
+    c.dst = reinterpret_cast<char *>(MODE == 2 || MODE == 4 ? dstm + (col0 << LOG2N) : dstm + col0);
     c.ld8 = ld8;
     c.orow_out = 0;
     c.k_out = 1;
@@ -612,7 +618,7 @@ __device__ __forceinline__ void fast_tile(const float2 *srcm, float2 *dstm, uint
     c.out_ell = 0;
     c.act = true;
     c.oscale = oscale;
-    run_stage<LOG2N, 0, EG, LTG, MODE == 3 ? 1 : MODE, TB, false, H, COH, PREC>(v, c);
+    run_stage<LOG2N, 0, EG, LTG, MODE == 3 ? 1 : (MODE == 4 ? 2 : MODE), TB, false, H, COH, PREC>(v, c);
 }
 
 // One column tile of a single-pass transform of n = 16^s points (s <= 3)
