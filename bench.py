@@ -440,7 +440,7 @@ def main():
         for i in range(args.steps):
             e = ev2[i]
             e[0].record(stream)
-            plan.execute_stage(1, xd.data_ptr(), ws.data_ptr(), sh, paco.PACO_PACKED)
+            plan.execute_stage(1, xd.data_ptr(), ws.data_ptr(), sh, paco.PACO_PACKED | paco.PACO_TWO_PASS)
             e[1].record(stream)
             plan.execute_stage(3, ws.data_ptr(), out.data_ptr(), sh, paco.PACO_PACKED)
             e[2].record(stream)

@@ -78,6 +78,7 @@ typedef enum {
 /* paco_execute_stage flags */
 #define PACO_NO_TWIDDLE 1       /* stage 2 only: apply the bare permutation pi_m */
 #define PACO_PACKED 2           /* the fused pipeline's Phase-I buffer (below) */
+#define PACO_TWO_PASS 4         /* with PACO_PACKED, stage 1: the two-pass form's Phase I */
 
 typedef struct paco_plan_s paco_plan;
 
@@ -193,7 +194,11 @@ paco_status paco_plan_has_two_pass(const paco_plan *plan, int32_t *yes);
  *            paco_execute_two_pass (twiddle on load), src == dst allowed
  * Stage 1 also allows src == dst.  PACO_PACKED on a plan that is not fused
  * (stage 3: that has no two-pass form) returns PACO_ERR_UNSUPPORTED;
- * PACO_NO_TWIDDLE on stage 1 or 3 returns PACO_ERR_INVALID_ARG. */
+ * PACO_NO_TWIDDLE on stage 1 or 3 returns PACO_ERR_INVALID_ARG.
+ * Stage 1 with PACO_PACKED | PACO_TWO_PASS is the two-pass form's Phase I:
+ * the same output as PACO_PACKED alone, its source read with last-use
+ * (non-temporal) loads (PACO_ERR_UNSUPPORTED without a two-pass form;
+ * PACO_TWO_PASS elsewhere: PACO_ERR_INVALID_ARG). */
 paco_status paco_execute_stage(const paco_plan *plan, int stage, int flags, const void *src,
                                void *dst, void *stream);
 

@@ -655,7 +655,10 @@ paco_status paco_execute_stage(const paco_plan *plan, int stage, int flags, cons
 {
     if (!plan) return fail(PACO_ERR_INVALID_ARG, "plan is NULL");
     if (bad_ptr(src) || bad_ptr(dst)) return fail(PACO_ERR_INVALID_ARG, "src/dst must be non-NULL and 16-byte aligned");
-    if (flags & ~(PACO_NO_TWIDDLE | PACO_PACKED)) return fail(PACO_ERR_INVALID_ARG, "unknown flags");
+    if (flags & ~(PACO_NO_TWIDDLE | PACO_PACKED | PACO_TWO_PASS)) return fail(PACO_ERR_INVALID_ARG, "unknown flags");
+    if ((flags & PACO_TWO_PASS) && !(stage == 1 && (flags & PACO_PACKED)))
+        return fail(PACO_ERR_INVALID_ARG, "PACO_TWO_PASS applies to stage 1 with PACO_PACKED");
+    if ((flags & PACO_TWO_PASS) && !plan->two_pass) return fail(PACO_ERR_UNSUPPORTED, "this plan has no two-pass form");
     const bool packed = (flags & PACO_PACKED) != 0;
     if (packed && !plan->fused) return fail(PACO_ERR_UNSUPPORTED, "this plan has no packed Phase-I buffer");
     if (packed && stage == 3 && !plan->two_pass)
@@ -665,6 +668,7 @@ paco_status paco_execute_stage(const paco_plan *plan, int stage, int flags, cons
     switch (stage) {
     case 1: {
         if (packed && src == dst) return fail(PACO_ERR_INVALID_ARG, "packed stage 1 is out of place");
+        if (flags & PACO_TWO_PASS) return run_local({plan->phase1_two}, src, dst, s);
         return packed ? run_local({plan->phase1_packed}, src, dst, s) : run_local(plan->phase1, src, dst, s);
     }
     case 2: {

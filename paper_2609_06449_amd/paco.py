@@ -28,6 +28,7 @@ PACO_C64_MFMA_BF16X6 = 3
 
 PACO_NO_TWIDDLE = 1
 PACO_PACKED = 2
+PACO_TWO_PASS = 4
 
 # every symbol include/paco.h declares
 EXPORTED = (

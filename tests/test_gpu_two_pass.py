@@ -140,10 +140,15 @@ def test_two_pass_phase3_stage(N1, N2, p, b):
     x = _dev(inputs.normal(N1 * N2, seed=23))
     ws = torch.empty_like(x)
     y = torch.empty_like(x)
-    plan.execute_stage(1, x.data_ptr(), ws.data_ptr(), s, paco.PACO_PACKED)
+    plan.execute_stage(1, x.data_ptr(), ws.data_ptr(), s, paco.PACO_PACKED | paco.PACO_TWO_PASS)
     plan.execute_stage(3, ws.data_ptr(), y.data_ptr(), s, paco.PACO_PACKED)
     ref = _two_pass(plan, x)
     assert np.array_equal(y.cpu().numpy().view(np.uint64), ref.view(np.uint64))
+    # the two-pass Phase I writes the same packed buffer as the three-pass one
+    ws3 = torch.empty_like(x)
+    plan.execute_stage(1, x.data_ptr(), ws3.data_ptr(), s, paco.PACO_PACKED)
+    torch.cuda.synchronize()
+    assert np.array_equal(ws.cpu().numpy().view(np.uint64), ws3.cpu().numpy().view(np.uint64))
 
 
 def test_packed_stage3_flag_errors():
@@ -163,3 +168,8 @@ def test_packed_stage3_flag_errors():
     for stage in (1, 3):
         assert lib.paco_execute_stage(fused.handle, stage, paco.PACO_NO_TWIDDLE, buf.data_ptr(), out.data_ptr(), s) == \
             paco.PACO_ERR_INVALID_ARG
+    for stage, fl in ((1, paco.PACO_TWO_PASS), (3, paco.PACO_TWO_PASS | paco.PACO_PACKED), (2, paco.PACO_TWO_PASS | paco.PACO_PACKED)):
+        assert lib.paco_execute_stage(fused.handle, stage, fl, buf.data_ptr(), out.data_ptr(), s) == \
+            paco.PACO_ERR_INVALID_ARG
+    assert lib.paco_execute_stage(paper.handle, 1, paco.PACO_PACKED | paco.PACO_TWO_PASS, buf.data_ptr(),
+                                  out.data_ptr(), s) == paco.PACO_ERR_UNSUPPORTED
