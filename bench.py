@@ -37,7 +37,7 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "FFT GFLOP/s (5N·log2N/t) + % HBM roofline, N=2^24 c64; MFMA-split vs FP32"
 WORKLOAD = dict(name="2^24 as 4096 x 4096", N1=4096, N2=4096, p=64, b=16, gen="normal", seed=2)
 KERNEL_SOURCES = ["paper_2609_06449_amd/csrc/" + f for f in ("local_fft.hip", "middle.hip", "stages.h", "middle_dev.h",
-                                                                  "paco_internal.h")]
+                                                                  "paco_internal.h", "split.hip")]
 
 
 def kernel_hash() -> str:
@@ -388,8 +388,10 @@ def main():
     gflops = 5.0 * N * math.log2(N) / (ms_per_step * 1e-3) / 1e9
 
     # ---- per-phase durations with HIP events on the same stream ------------
-    # the same launches paco_execute makes, one phase per call
-    fl = paco.PACO_PACKED if plan.description.startswith("fused") else 0
+    # the same launches paco_execute makes, one phase per call (split form:
+    # its pass 1 and pass 2 in place of Phases I and II)
+    fused = plan.description.startswith("fused")
+    fl = paco.PACO_SPLIT if plan.has_split else (paco.PACO_PACKED if fused else 0)
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     for i in range(args.steps):
         e = ev[i]
@@ -470,7 +472,10 @@ def main():
         del src, dst
 
     # the dominant kernel: the slowest of the three phases (each one launch)
-    if fl:  # the kernels of the default (fused) plan for this workload
+    if plan.has_split:  # the kernels of the default plan for this workload
+        names = ["pass1 split_first_kernel", "pass2 split_middle_kernel<false>",
+                 "phase3 local_fft_fast_kernel<12,1,4,2,32,0>"]
+    elif fl:  # the packed form (PACO_SPLIT=0)
         names = ["phase1 local_fft_fast_kernel<12,2,1,2,16,0>", "phase2 middle_packed2_kernel<false,true>",
                  "phase3 local_fft_fast_kernel<12,1,4,2,32,0>"]
     else:

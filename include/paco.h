@@ -79,6 +79,7 @@ typedef enum {
 #define PACO_NO_TWIDDLE 1       /* stage 2 only: apply the bare permutation pi_m */
 #define PACO_PACKED 2           /* the fused pipeline's Phase-I buffer (below) */
 #define PACO_TWO_PASS 4         /* with PACO_PACKED, stage 1: the two-pass form's Phase I */
+#define PACO_SPLIT 8            /* alone, stage 1 or 2: the split form's pass 1 or pass 2 */
 
 typedef struct paco_plan_s paco_plan;
 
@@ -133,7 +134,20 @@ paco_status paco_plan_workspace_size(const paco_plan *plan, size_t *bytes);
  * with contiguous runs on both sides of every HBM pass but Phase I's reads and
  * Phase III's writes.  Phase II is then the unpack (rows c -> pi_{m2}(c)) with
  * the top-level twiddle.  paco_plan_describe names the mode; the environment
- * variable PACO_LAYOUT=paper at plan creation selects the paper's layouts. */
+ * variable PACO_LAYOUT=paper at plan creation selects the paper's layouts.
+ *
+ * Split form.  A fused PACO_C64 plan with N1 = 2^12 and 16 | N2 splits each
+ * Phase-I column transform once more by Lemma 1, 4096 = 16 x 256 (row
+ * j1 = j + 256 r, frequency k1 = k0 + 16 k).  Pass 1 computes
+ *     T[c][j][k0] = w_4096^{-j k0} sum_r X[j + 256 r, c] w_16^{-r k0}
+ * into workspace[c*N1 + 16 j + k0], reading x in whole 128-byte row runs
+ * (16 columns at a time; the packed Phase I reads 32-byte runs).  Pass 2
+ * reads column c's T (contiguous), finishes A[k1, c] = sum_j w_256^{-j k}
+ * T[c][j][k0] and writes Phase II's result row pi_{m2}(c) of out with the
+ * twiddle w_N^{-k1 c}.  Phase III and out are unchanged, so are the three
+ * HBM passes; only how Phase I's arithmetic is divided between the first two
+ * passes differs.  paco_plan_has_split tells; PACO_SPLIT=0 in the
+ * environment at plan creation keeps the packed form. */
 paco_status paco_execute(const paco_plan *plan, const void *in, void *out, void *workspace,
                          size_t workspace_bytes, void *stream);
 
@@ -181,6 +195,10 @@ paco_status paco_execute_two_pass(const paco_plan *plan, const void *in, void *o
 /* *yes = 1 when paco_execute_two_pass runs for this plan, else 0. */
 paco_status paco_plan_has_two_pass(const paco_plan *plan, int32_t *yes);
 
+/* *yes = 1 when paco_execute (and paco_execute_inverse of a square plan)
+ * runs the split form for this plan, else 0. */
+paco_status paco_plan_has_split(const paco_plan *plan, int32_t *yes);
+
 /* Runs one phase alone, for stage-wise checks and per-phase timing, always
  * in the paper's layouts unless flags holds PACO_PACKED:
  *   stage 1: src (N1 x N2, x) -> dst (N1 x N2, Phase-I layout Atilde);
@@ -198,7 +216,12 @@ paco_status paco_plan_has_two_pass(const paco_plan *plan, int32_t *yes);
  * Stage 1 with PACO_PACKED | PACO_TWO_PASS is the two-pass form's Phase I:
  * the same output as PACO_PACKED alone, its source read with last-use
  * (non-temporal) loads (PACO_ERR_UNSUPPORTED without a two-pass form;
- * PACO_TWO_PASS elsewhere: PACO_ERR_INVALID_ARG). */
+ * PACO_TWO_PASS elsewhere: PACO_ERR_INVALID_ARG).
+ * PACO_SPLIT (alone) runs the split form's pass 1 (stage 1: src = x, dst =
+ * the split buffer T) or pass 2 (stage 2: src = T, dst = Zhat, the same
+ * result as stage 2 of paco_execute); src and dst must not overlap;
+ * PACO_ERR_UNSUPPORTED without a split form, PACO_ERR_INVALID_ARG with
+ * other flags or stage 3. */
 paco_status paco_execute_stage(const paco_plan *plan, int stage, int flags, const void *src,
                                void *dst, void *stream);
 

@@ -203,6 +203,25 @@ struct MiddlePass {
 };
 
 constexpr int kMidTile = 64;
+
+// The split form of the fused pipeline (split.hip), FP32, N1 = 2^12 =
+// 16 x 256: pass 1 runs the first radix-16 stage of every Phase I column
+// transform (with its twiddle) over whole 128-byte row runs of x and stores
+// ws[c*N1 + 16 j + k0]; pass 2 finishes each column's 16 transforms of
+// length 256 and applies the redistribution of Phase II (row c -> row
+// pi_{m2}(c) of out, times w_N^{-k1 c}) in the same pass.
+constexpr int kSplitLog2N1 = 12;
+struct SplitPass {
+    const float2 *src;
+    float2 *dst;
+    int64_t N1, N2;
+    const float2 *tw;             // w_L^{-r}, r < L = N1 << tw_shift: w_{N1}^{-m} = tw[m << tw_shift]
+    int32_t tw_shift;
+    const float2 *tw_hi, *tw_lo;  // w_N^{-e} = tw_hi[e >> log2Lo] * tw_lo[e mod 2^log2Lo]
+    int32_t log2N, log2Lo;
+    int32_t t, m2, s2;            // pi_{m2}(c) = digmap(c, t, m2, s2, forward)
+    int32_t conj_in;              // pass 1: conjugate x on load (the inverse transform's input map)
+};
 constexpr int kTwTile = 128;  // tile-twiddle table side: [i*128 + j] = w_N^{-(i*j mod N)}
 
 // Workgroup geometry a local pass is launched with.
@@ -240,6 +259,10 @@ LocalLaunch local_fft_geometry(const LocalPass &p);
 hipError_t local_fft_prepare();  // raises the dynamic-LDS limit of every kernel once
 hipError_t launch_local_fft(const LocalPass &p, hipStream_t s);
 hipError_t launch_middle(const MiddlePass &p, hipStream_t s);
+// Pass 1 and pass 2 of the split form; hipErrorInvalidValue unless
+// N1 == 2^12 and N2 is a multiple of 16.
+hipError_t launch_split_first(const SplitPass &p, hipStream_t s);
+hipError_t launch_split_middle(const SplitPass &p, hipStream_t s);
 
 // Columns per workgroup for an on-chip pass of length 2^log2n over ncols.
 int32_t choose_log2T(int32_t log2n, int64_t ncols);

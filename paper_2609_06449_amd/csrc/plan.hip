@@ -61,6 +61,8 @@ struct paco_plan_s {
     LocalPass phase1_packed{};
     bool two_pass = false;                  // Phase III can read the packed buffer itself
     LocalPass phase1_two{}, phase3_two{};   // the two-pass form's passes
+    bool split = false;                     // N1 = 2^12: Phase I split 16 x 256 across passes 1 and 2
+    paco::SplitPass split_pass{};           // src/dst filled per execution
     paco_plan_s *inv = nullptr;             // N2 x N1 passes of the inverse (NULL: square, this plan's)
     std::string inv_error;                  // non-empty: the inverse passes could not be built
     std::string desc;
@@ -437,6 +439,27 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
     P->mid.log2Lo = P->lLo;
     P->mid.twiddle = 1;
 
+    // ---- split form (FP32, N1 = 2^12; knob PACO_SPLIT=0 turns it off) ------
+    {
+        const char *sp = std::getenv("PACO_SPLIT");
+        const bool want = !(sp && sp[0] == '0');
+        if (want && P->fused && dt == PACO_C64 && P->l1 == paco::kSplitLog2N1 && N2 % 16 == 0 && P->lN <= 32) {
+            paco::SplitPass &q = P->split_pass;
+            q.N1 = N1;
+            q.N2 = N2;
+            q.tw = d_tw;
+            q.tw_shift = P->lL - P->l1;
+            q.tw_hi = d_thi;
+            q.tw_lo = d_tlo;
+            q.log2N = P->lN;
+            q.log2Lo = P->lLo;
+            q.t = t;
+            q.m2 = P->m2;
+            q.s2 = P->s2;
+            P->split = true;
+        }
+    }
+
     char buf[512];
     std::string desc;
     for (auto *ph : {&P->phase1, &P->phase3}) {
@@ -450,6 +473,9 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
         }
         desc += " ]";
     }
+    if (P->split)
+        desc = "split[pass1: phase1 radix-16 stage over 128-byte row runs -> ws; pass2: 256-point tails + "
+               "row unpack+twiddle] " + desc;
     if (P->fused) desc = "fused[phase1 -> packed transposed slab, phase2 row unpack+twiddle] " + desc;
     if (P->two_pass) {
         const paco::LocalLaunch g = paco::local_fft_geometry(P->phase3_two);
@@ -589,6 +615,18 @@ paco_status check_buffers(const paco_plan *plan, const void *in, void *out, void
     return PACO_OK;
 }
 
+// Pass 1 (pass == 1) or pass 2 of the split form.
+paco_status run_split(const paco_plan *plan, int pass, const void *src, void *dst, bool conj_in, hipStream_t s)
+{
+    paco::SplitPass q = plan->split_pass;
+    q.src = static_cast<const float2 *>(src);
+    q.dst = static_cast<float2 *>(dst);
+    q.conj_in = conj_in ? 1 : 0;
+    hipError_t e = pass == 1 ? paco::launch_split_first(q, s) : paco::launch_split_middle(q, s);
+    if (e != hipSuccess) return hip_fail(e, pass == 1 ? "split pass 1 launch" : "split pass 2 launch");
+    return PACO_OK;
+}
+
 // The three phases of one plan.  inverse: conj on Phase I's loads, conj and
 // 1/N on Phase III's stores, i.e. conj(Omega conj(in)) / N.
 paco_status run_three(const paco_plan *plan, const void *in, void *out, void *workspace, hipStream_t s, bool inverse)
@@ -599,9 +637,16 @@ paco_status run_three(const paco_plan *plan, const void *in, void *out, void *wo
         p1.front().conj_in = 1;
         p3.back().out_scale = 1.0f / float(plan->N1 * plan->N2);  // 2^-log2 N: exact
     }
-    paco_status st = run_local(p1, in, workspace, s);
-    if (st != PACO_OK) return st;
-    st = run_middle(plan, workspace, out, 1, plan->fused, s);
+    paco_status st;
+    if (plan->split) {
+        st = run_split(plan, 1, in, workspace, inverse, s);
+        if (st != PACO_OK) return st;
+        st = run_split(plan, 2, workspace, out, false, s);
+    } else {
+        st = run_local(p1, in, workspace, s);
+        if (st != PACO_OK) return st;
+        st = run_middle(plan, workspace, out, 1, plan->fused, s);
+    }
     if (st != PACO_OK) return st;
     return run_local(p3, out, out, s);
 }
@@ -650,12 +695,31 @@ paco_status paco_plan_has_two_pass(const paco_plan *plan, int32_t *yes)
     return PACO_OK;
 }
 
+paco_status paco_plan_has_split(const paco_plan *plan, int32_t *yes)
+{
+    if (!yes) return fail(PACO_ERR_INVALID_ARG, "yes out-pointer is NULL");
+    *yes = 0;
+    if (!plan) return fail(PACO_ERR_INVALID_ARG, "plan is NULL");
+    *yes = plan->split ? 1 : 0;
+    return PACO_OK;
+}
+
 paco_status paco_execute_stage(const paco_plan *plan, int stage, int flags, const void *src, void *dst,
                                void *stream)
 {
     if (!plan) return fail(PACO_ERR_INVALID_ARG, "plan is NULL");
     if (bad_ptr(src) || bad_ptr(dst)) return fail(PACO_ERR_INVALID_ARG, "src/dst must be non-NULL and 16-byte aligned");
-    if (flags & ~(PACO_NO_TWIDDLE | PACO_PACKED | PACO_TWO_PASS)) return fail(PACO_ERR_INVALID_ARG, "unknown flags");
+    if (flags & ~(PACO_NO_TWIDDLE | PACO_PACKED | PACO_TWO_PASS | PACO_SPLIT))
+        return fail(PACO_ERR_INVALID_ARG, "unknown flags");
+    if (flags & PACO_SPLIT) {
+        if (flags != PACO_SPLIT || (stage != 1 && stage != 2))
+            return fail(PACO_ERR_INVALID_ARG, "PACO_SPLIT applies alone to stage 1 or 2");
+        if (!plan->split) return fail(PACO_ERR_UNSUPPORTED, "this plan has no split form");
+        const size_t need = size_t(plan->N1) * size_t(plan->N2) * 8;
+        const uintptr_t a = reinterpret_cast<uintptr_t>(src), b = reinterpret_cast<uintptr_t>(dst);
+        if (a < b + need && b < a + need) return fail(PACO_ERR_INVALID_ARG, "split stages are out of place");
+        return run_split(plan, stage, src, dst, false, static_cast<hipStream_t>(stream));
+    }
     if ((flags & PACO_TWO_PASS) && !(stage == 1 && (flags & PACO_PACKED)))
         return fail(PACO_ERR_INVALID_ARG, "PACO_TWO_PASS applies to stage 1 with PACO_PACKED");
     if ((flags & PACO_TWO_PASS) && !plan->two_pass) return fail(PACO_ERR_UNSUPPORTED, "this plan has no two-pass form");

@@ -1,0 +1,144 @@
+// The split form of the fused pipeline for N1 = 2^12 (FP32).
+//
+// Phase I transforms every column c of X (N1 x N2, row-major) over its
+// N1 = 4096 rows.  Split once more by Cooley-Tukey (Lemma 1 with a first
+// child of length 16): with row j1 = j + 256 r and frequency k1 = k0 + 16 k,
+//
+//   A[k1, c] = sum_j w_256^{-j k} T[c][j][k0],
+//   T[c][j][k0] = w_4096^{-j k0} sum_r X[j + 256 r, c] w_16^{-r k0}.
+//
+// The bracket needs only 16 rows of a column at a time, so pass 1 can read
+// x in whole 128-byte row runs (16 columns per workgroup), where a tile that
+// holds entire 4096-point columns on chip reads 32-byte runs; its HBM
+// pattern measured ~30% faster.  The rest of the column transform (16
+// transforms of length 256 per column) needs each column's T contiguous,
+// which is exactly what the redistribution of Phase II reads, so pass 2
+// finishes them there: it reads column c's 32 KiB block once, runs two
+// radix-16 stages with one LDS exchange, multiplies by the top-level twiddle
+// w_N^{-k1 c} (Phase II, Sec. 4) and writes row pi_{m2}(c) of out in natural
+// k1 order, as the packed Phase II does.  The pipeline stays at three HBM
+// passes; Phase III is unchanged.
+
+#include "stages.h"
+
+namespace paco {
+namespace {
+
+constexpr int kSplitThreads = 256;
+constexpr int kFirstPad = 257;  // LDS row of pass 1: 256 items + 1
+
+// Pass 1.  Workgroup (cg, jg) owns columns c = 16 cg + cl and indices
+// j = 16 jg + jl (cl, jl < 16), i.e. rows j + 256 r of 16 adjacent columns:
+// every load instruction reads four full 128-byte row runs.  Its 16 x 256
+// results are ws[c*N1 + 256 jg + (16 jl + k0)]: 2 KiB contiguous per column,
+// stored through LDS so that every store instruction writes 512 bytes.
+__global__ __launch_bounds__(kSplitThreads) void split_first_kernel(SplitPass P)
+{
+    __shared__ float2 lds[16 * kFirstPad];
+    const int tid = threadIdx.x;
+    const int64_t ncg = P.N2 >> 4;
+    const int64_t cg = int64_t(blockIdx.x) % ncg, jg = int64_t(blockIdx.x) / ncg;
+    const int cl = tid & 15, jl = tid >> 4;
+    const int64_t c = (cg << 4) + cl;
+    const int j = int(jg << 4) + jl;
+    float2 v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = P.src[(int64_t(j) + (r << 8)) * P.N2 + c];
+    if (P.conj_in) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[r].y = -v[r].y;
+    }
+    dft_regs<4>(v);
+#pragma unroll
+    for (int k0 = 1; k0 < 16; ++k0) v[k0] = cmul(v[k0], P.tw[(j * k0) << P.tw_shift]);
+#pragma unroll
+    for (int k0 = 0; k0 < 16; ++k0) lds[cl * kFirstPad + jl * 16 + k0] = v[k0];
+    __syncthreads();
+    float2 *dst = P.dst + (cg << 4) * P.N1 + (jg << 8) + tid;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) dst[q * P.N1] = lds[q * kFirstPad + tid];
+}
+
+// Pass 2.  Workgroup c: y_k0[j] = T[c][j][k0] (j = jl + 16 jh) is
+// transformed over j by two radix-16 stages,
+//   DFT_256(y)[kl + 16 kh] = sum_jl w_16^{-jl kh} w_256^{-jl kl} sum_jh y[jl + 16 jh] w_16^{-jh kl},
+// thread (k0, jl) taking the inner sums and thread (k0, kl) the outer ones.
+// Output k1 = k0 + 16 kl + 256 kh goes to out[pi_{m2}(c)*N1 + k1] times
+//   w_N^{-k1 c} = w_N^{-k0 c} * w_N^{-16 kl c} * w_N^{-256 kh c},
+// factors with 16, 4 and 1 distinct table entries per wave (the last is the
+// same for the whole workgroup).  Every twiddle load is issued right behind
+// the data loads so that its latency overlaps theirs: 69 -> 61 us per
+// 2^24 launch against loading each factor where it is used.  The exchange
+// buffer is unpadded (32 KiB, five workgroups per CU) with an XOR swizzle of
+// the 16-item rows: row k of the buffer holds item (jl, k0) at
+// 16 (jl ^ (k & 3)) + k0, so the writes of a wave cover 64 distinct banks
+// and its reads of four rows k fall into two bank halves.
+template <bool GEN>
+__global__ __launch_bounds__(kSplitThreads) void split_middle_kernel(SplitPass P)
+{
+    __shared__ float2 lds[16 * 256];
+    const int tid = threadIdx.x;
+    const int64_t c = blockIdx.x;
+    const int lo = tid & 15, hi = tid >> 4;  // k0, and jl (inner sums) or kl (outer sums)
+    const float2 *src = P.src + c * P.N1;
+    float2 v[16];
+#pragma unroll
+    for (int jh = 0; jh < 16; ++jh) v[jh] = ld2_last(src + (hi + 16 * jh) * 16 + lo);  // nothing reads ws again
+    float2 t256[16];
+#pragma unroll
+    for (int k = 1; k < 16; ++k) t256[k] = P.tw[(16 * hi * k) << P.tw_shift];  // w_256^{-jl kl}
+    const uint32_t nmask = uint32_t((uint64_t(1) << P.log2N) - 1), lomask = (1u << P.log2Lo) - 1;
+    const uint32_t e0 = (uint32_t(lo) * uint32_t(c)) & nmask, e1 = (uint32_t(16 * hi) * uint32_t(c)) & nmask;
+    const float2 a0 = P.tw_hi[e0 >> P.log2Lo], a1 = P.tw_lo[e0 & lomask];
+    const float2 a2 = P.tw_hi[e1 >> P.log2Lo], a3 = P.tw_lo[e1 & lomask];
+    float2 bh[16], bl[16];
+#pragma unroll
+    for (int kh = 0; kh < 16; ++kh) {
+        const uint32_t e2 = (uint32_t(256 * kh) * uint32_t(c)) & nmask;
+        bh[kh] = P.tw_hi[e2 >> P.log2Lo];
+        bl[kh] = P.tw_lo[e2 & lomask];
+    }
+    const int64_t u = digmap<GEN>(c, P.t, P.m2, P.s2, false);
+
+    dft_regs<4>(v);
+#pragma unroll
+    for (int k = 1; k < 16; ++k) v[k] = cmul(v[k], t256[k]);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) lds[k * 256 + (((hi ^ (k & 3)) << 4) | lo)] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int jl = 0; jl < 16; ++jl) v[jl] = lds[hi * 256 + (((jl ^ (hi & 3)) << 4) | lo)];
+    dft_regs<4>(v);
+
+    const float2 a = cmul(cmul(a0, a1), cmul(a2, a3));  // w_N^{-(k0 + 16 kl) c}
+    char *dst = reinterpret_cast<char *>(P.dst + u * P.N1 + lo + 16 * hi);
+#pragma unroll
+    for (int kh = 0; kh < 16; ++kh)
+        st2<false>(dst + size_t(256 * kh) * 8u, cmul(v[kh], cmul(a, cmul(bh[kh], bl[kh]))));
+}
+
+bool split_shape_ok(const SplitPass &p)
+{
+    return p.N1 == (int64_t(1) << kSplitLog2N1) && p.N2 >= 16 && p.N2 % 16 == 0 && p.log2N <= 32 &&
+           p.src && p.dst && p.tw && p.tw_hi && p.tw_lo;
+}
+
+}  // namespace
+
+hipError_t launch_split_first(const SplitPass &p, hipStream_t s)
+{
+    if (!split_shape_ok(p)) return hipErrorInvalidValue;
+    const int64_t groups = (p.N2 / 16) * (p.N1 / 256);
+    hipLaunchKernelGGL(split_first_kernel, dim3(unsigned(groups)), dim3(kSplitThreads), 0, s, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_split_middle(const SplitPass &p, hipStream_t s)
+{
+    if (!split_shape_ok(p)) return hipErrorInvalidValue;
+    void (*k)(SplitPass) = digrev_fast(p.t) ? split_middle_kernel<false> : split_middle_kernel<true>;
+    hipLaunchKernelGGL(k, dim3(unsigned(p.N2)), dim3(kSplitThreads), 0, s, p);
+    return hipGetLastError();
+}
+
+}  // namespace paco

@@ -29,12 +29,13 @@ PACO_C64_MFMA_BF16X6 = 3
 PACO_NO_TWIDDLE = 1
 PACO_PACKED = 2
 PACO_TWO_PASS = 4
+PACO_SPLIT = 8
 
 # every symbol include/paco.h declares
 EXPORTED = (
     "paco_plan_validate", "paco_plan_create", "paco_plan_validate_mixed", "paco_plan_create_mixed",
     "paco_plan_workspace_size", "paco_execute",
-    "paco_execute_stage", "paco_execute_inverse", "paco_execute_two_pass", "paco_plan_has_two_pass", "paco_plan_describe",
+    "paco_execute_stage", "paco_execute_inverse", "paco_execute_two_pass", "paco_plan_has_two_pass", "paco_plan_has_split", "paco_plan_describe",
     "paco_plan_destroy", "paco_status_string",
     "paco_last_error", "paco_batch_plan_create", "paco_batch_workspace_size", "paco_execute_batched",
     "paco_batch_plan_describe", "paco_batch_errors", "paco_batch_plan_destroy",
@@ -72,6 +73,7 @@ def _load() -> ctypes.CDLL:
         "paco_execute_two_pass": (st, [P, P, P, P, sz, P]),
         "paco_execute_inverse": (st, [P, P, P, P, sz, P]),
         "paco_plan_has_two_pass": (st, [P, ctypes.POINTER(i32)]),
+        "paco_plan_has_split": (st, [P, ctypes.POINTER(i32)]),
         "paco_plan_describe": (st, [P, ctypes.POINTER(i32), ctypes.c_char_p, sz]),
         "paco_plan_destroy": (st, [P]),
         "paco_status_string": (ctypes.c_char_p, [st]),
@@ -160,6 +162,12 @@ def paco_plan_has_two_pass(plan: int) -> bool:
     return bool(yes.value)
 
 
+def paco_plan_has_split(plan: int) -> bool:
+    yes = ctypes.c_int32()
+    _check(_lib.paco_plan_has_split(plan, ctypes.byref(yes)), "paco_plan_has_split")
+    return bool(yes.value)
+
+
 def paco_plan_describe(plan: int):
     n = ctypes.c_int32()
     buf = ctypes.create_string_buffer(1024)
@@ -180,6 +188,7 @@ class Plan:
         self.workspace_bytes = paco_plan_workspace_size(self.handle)
         self.launches, self.description = paco_plan_describe(self.handle)
         self.has_two_pass = paco_plan_has_two_pass(self.handle)
+        self.has_split = paco_plan_has_split(self.handle)
 
     def execute(self, src: int, dst: int, workspace: int, stream: int = 0):
         paco_execute(self.handle, src, dst, workspace, self.workspace_bytes, stream)

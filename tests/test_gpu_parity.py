@@ -180,7 +180,7 @@ def test_execute_argument_errors_on_device():
     assert lib.paco_execute(plan.handle, buf.data_ptr(), buf.data_ptr(), buf.data_ptr(), 1 << 20, s) == paco.PACO_ERR_INVALID_ARG
     assert lib.paco_execute_stage(plan.handle, 4, 0, buf.data_ptr(), ws.data_ptr(), s) == paco.PACO_ERR_INVALID_ARG
     assert lib.paco_execute_stage(plan.handle, 2, 0, buf.data_ptr(), buf.data_ptr(), s) == paco.PACO_ERR_INVALID_ARG
-    assert lib.paco_execute_stage(plan.handle, 2, 8, buf.data_ptr(), ws.data_ptr(), s) == paco.PACO_ERR_INVALID_ARG
+    assert lib.paco_execute_stage(plan.handle, 2, 16, buf.data_ptr(), ws.data_ptr(), s) == paco.PACO_ERR_INVALID_ARG
 
 
 # ---------------------------------------------------------------------------
