@@ -187,6 +187,8 @@ def test_which_plans_split():
     assert paco.Plan(4096, 64, 4, 4).has_split
     assert not paco.Plan(256, 4096, 4, 16).has_split          # N1 != 4096
     assert not paco.Plan(1024, 4096, 4, 4).has_split
+    assert paco.Plan(4096, 8192, 64, 2).has_split
+    assert not paco.Plan(4096, 16384, 64, 4).has_split        # N2 above 2^13: the packed form measured faster
     assert not paco.Plan(4096, 256, 16, 16, paco.PACO_C64_MFMA_BF16X3).has_split  # FP32 only
     os.environ["PACO_LAYOUT"] = "paper"
     try:
