@@ -69,12 +69,15 @@ __global__ __launch_bounds__(kSplitThreads) void split_first_kernel(SplitPass P)
 // same for the whole workgroup).  Every twiddle load is issued right behind
 // the data loads so that its latency overlaps theirs: 69 -> 61 us per
 // 2^24 launch against loading each factor where it is used.  The exchange
-// buffer is unpadded (32 KiB, five workgroups per CU) with an XOR swizzle of
+// buffer is unpadded (32 KiB: five workgroups fit a CU) with an XOR swizzle of
 // the 16-item rows: row k of the buffer holds item (jl, k0) at
 // 16 (jl ^ (k & 3)) + k0, so the writes of a wave cover 64 distinct banks
-// and its reads of four rows k fall into two bank halves.
+// and its reads of four rows k fall into two bank halves.  A 96-VGPR budget
+// (five waves per SIMD, which that buffer allows) took the launch from 60
+// to 55 us (no spills).
 template <bool GEN>
-__global__ __launch_bounds__(kSplitThreads) void split_middle_kernel(SplitPass P)
+__global__ __launch_bounds__(kSplitThreads) __attribute__((amdgpu_waves_per_eu(5))) void split_middle_kernel(
+    SplitPass P)
 {
     __shared__ float2 lds[16 * 256];
     const int tid = threadIdx.x;
