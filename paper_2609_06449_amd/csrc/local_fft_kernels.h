@@ -101,8 +101,13 @@ __global__ __launch_bounds__(fast_threads(LOG2N, H, EG)) void local_fft_fast_ker
         top.lomask = (1u << P.top_log2Lo) - 1;
         top.lshift = P.top_log2Lo;
     }
+    // MODE 2 streams the packed buffer out (Phase II reads it back in 1 KB
+    // runs); the two-pass form's MODE 4 keeps plain stores, its Phase III
+    // reads that buffer in column tiles and finds it in the MALL
+    // (streaming there measured 160 -> 180 us per 2^24 transform, against
+    // 194 -> 177 us for the packed three-pass form)
     fast_tile<LOG2N, MODE, TB, H, EG, LT, false, PREC>(P.src, P.dst, uint32_t(P.ld), col0, P.stw, smem, threadIdx.x,
-                                                       &top, P.conj_in != 0, P.out_scale);
+                                                       &top, P.conj_in != 0, P.out_scale, MODE == 2);
 }
 
 // Single-pass tile of a 16^s-point transform with every butterfly on MFMA in

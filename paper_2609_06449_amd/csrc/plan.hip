@@ -440,9 +440,10 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
     P->mid.twiddle = 1;
 
     // ---- split form (FP32, N1 = 2^12; knob PACO_SPLIT=0 turns it off) ------
-    // Measured per transform (one launch, MI355X): N2 = 2^10 49 against
-    // 60 us for the packed form, 2^12 183 against 197 us, 2^13 421 against
-    // 438 us, but 2^14 944 against 926 us, so N2 <= 2^13.
+    // Measured per transform (one launch, MI355X, both forms with plain
+    // stores): N2 = 2^10 49 against 60 us for the packed form, 2^12 183
+    // against 197 us, 2^13 421 against 438 us, but 2^14 944 against 926 us,
+    // so N2 <= 2^13.
     {
         const char *sp = std::getenv("PACO_SPLIT");
         const bool want = !(sp && sp[0] == '0');

@@ -31,7 +31,12 @@ constexpr int kFirstPad = 257;  // LDS row of pass 1: 256 items + 1
 // j = 16 jg + jl (cl, jl < 16), i.e. rows j + 256 r of 16 adjacent columns:
 // every load instruction reads four full 128-byte row runs.  Its 16 x 256
 // results are ws[c*N1 + 256 jg + (16 jl + k0)]: 2 KiB contiguous per column,
-// stored through LDS so that every store instruction writes 512 bytes.
+// stored through LDS so that every store instruction writes 512 bytes, with
+// streaming stores.  Pass 2 reads ws once, in whole 32 KiB blocks that HBM
+// serves at copy speed; left out of the 256 MiB MALL, ws no longer pushes x
+// (read again by the next transform) and out (Phase III's input) out of
+// it: 2^24 back to back, pass 1 59 -> 47 us, pass 2 56 -> 53 us, Phase III
+// 67 -> 65 us, the transform 175 -> 157 us.
 __global__ __launch_bounds__(kSplitThreads) void split_first_kernel(SplitPass P)
 {
     __shared__ float2 lds[16 * kFirstPad];
@@ -56,7 +61,7 @@ __global__ __launch_bounds__(kSplitThreads) void split_first_kernel(SplitPass P)
     __syncthreads();
     float2 *dst = P.dst + (cg << 4) * P.N1 + (jg << 8) + tid;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) dst[q * P.N1] = lds[q * kFirstPad + tid];
+    for (int q = 0; q < 16; ++q) st2_stream(dst + q * P.N1, lds[q * kFirstPad + tid]);
 }
 
 // Pass 2.  Workgroup c: y_k0[j] = T[c][j][k0] (j = jl + 16 jh) is

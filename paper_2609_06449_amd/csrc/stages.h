@@ -73,6 +73,21 @@ __device__ __forceinline__ void dft_regs(float2 *v)
     for (int k = 0; k < R; ++k) v[k] = t[k];
 }
 
+// A streaming (non-temporal) 8-byte store, for a buffer whose one reader
+// streams it back in long contiguous runs (the packed Phase-I buffer and the
+// split form's buffer, read by the redistribution pass): HBM serves such
+// reads at copy speed, and keeping these lines out of the 256 MiB MALL
+// leaves room there for the input of the next transform and for Phase III's
+// input.
+__device__ __forceinline__ void st2_stream(void *p, float2 v)
+{
+    typedef float sf2 __attribute__((ext_vector_type(2)));
+    sf2 t;
+    t.x = v.x;
+    t.y = v.y;
+    __builtin_nontemporal_store(t, reinterpret_cast<sf2 *>(p));
+}
+
 // HBM stores of a tile's results.  COH: a device-coherent store (written
 // through this XCD's L2), for results another workgroup of the same launch
 // reads after a completion counter says they are there; the 16-byte form
@@ -150,6 +165,7 @@ struct Ctx {
     int out_s = 0;             // generic: short top digit of pi_out (mixed radix)
     bool act;                  // runtime tile width: this thread owns butterflies (tid < nt)
     float oscale = 0.f;        // nonzero: every output is stored as conj(y) * oscale
+    bool stream = false;       // MODE 2: streaming stores (st2_stream)
 };
 
 // conj(v) * s: the inverse transform's output map (s = 1/N, a power of two)
@@ -461,8 +477,12 @@ __device__ __forceinline__ void run_stage(float2 (&v)[H * EG], const Ctx &c)
                     // transposed output: row (col0 + t) holds all n frequencies in order
                     const uint32_t base = (uint32_t(t) << (LOG2N + 3)) + uint32_t(j) * 8u;
 #pragma unroll
-                    for (int r = 0; r < R; ++r)
-                        st2<COH>(c.dst + base + (uint32_t(r) << (LNS + 3)), u[r]);
+                    for (int r = 0; r < R; ++r) {
+                        if (c.stream)
+                            st2_stream(c.dst + base + (uint32_t(r) << (LNS + 3)), u[r]);
+                        else
+                            st2<COH>(c.dst + base + (uint32_t(r) << (LNS + 3)), u[r]);
+                    }
                 } else if constexpr (MODE == 1) {
                     const uint32_t base = uint32_t(j) * c.ld8 + uint32_t(t) * 8u;
 #pragma unroll
@@ -541,7 +561,7 @@ struct TopTw {
 template <int LOG2N, int MODE, int TB, int H, int EG, int LT, bool COH = false, int PREC = kPrecFP32>
 __device__ __forceinline__ void fast_tile(const float2 *srcm, float2 *dstm, uint32_t ld, int64_t col0,
                                           const float2 *stw, float2 *smem, int tid, const TopTw *top = nullptr,
-                                          bool conj_in = false, float oscale = 0.f)
+                                          bool conj_in = false, float oscale = 0.f, bool stream_out = false)
 {
     constexpr int LTG = LT - (H == 2 ? 1 : 0);         // log2 of the columns of one group
     constexpr int NT = (1 << (LOG2N + LTG)) / EG;
@@ -618,6 +638,7 @@ __device__ __forceinline__ void fast_tile(const float2 *srcm, float2 *dstm, uint
     c.out_ell = 0;
     c.act = true;
     c.oscale = oscale;
+    c.stream = stream_out;
     run_stage<LOG2N, 0, EG, LTG, MODE == 3 ? 1 : (MODE == 4 ? 2 : MODE), TB, false, H, COH, PREC>(v, c);
 }
 
@@ -788,7 +809,11 @@ __device__ __forceinline__ void mf_tile(const float2 *srcm, float2 *dstm, uint32
                 off = uint32_t(digrev<false>(k, TB, LOG2N / TB)) * ld8 + uint32_t(t) * 8u;
             else
                 off = k * ld8 + uint32_t(t) * 8u;
-            st2<false>(dst + off, oscale != 0.f ? conj_scale(o[G][i], oscale) : o[G][i]);
+            const float2 w = oscale != 0.f ? conj_scale(o[G][i], oscale) : o[G][i];
+            if constexpr (MODE == 2)
+                st2_stream(dst + off, w);  // the packed buffer, streamed back by Phase II
+            else
+                st2<false>(dst + off, w);
         }
     }
 }
