@@ -3,9 +3,12 @@
 One step = one complete transform (Phase I LocalFFT -> Phase II fused
 permutation -> Phase III LocalFFT) of the N = 2^24 complex64 workload
 (N1 = N2 = 4096, p = 64 slabs, b = 16, N(0,1) inputs, seed 2) through the C
-ABI.  Inputs are resident in HBM before the timed region.  Prints one JSON
-line: GFLOP/s = 5 N log2 N / t, plus the dominant kernel's roofline (HIP
-events on the stream the kernels run on) and the CPU oracle baseline.
+ABI, in the plan's default (split) form: three HBM passes, the first two
+sharing Phase I's butterflies.  Inputs are resident in HBM before the timed
+region.  Prints one JSON line: GFLOP/s = 5 N log2 N / t, plus the dominant
+kernel's roofline (HIP events on the stream the kernels run on; phase_us
+times pass 1, pass 2 and Phase III one launch each) and the CPU oracle
+baseline.
 
 Further fields of the same line (each leg can be skipped by a flag):
   two_pass   the two-HBM-pass form of the same transform (an ablation,
