@@ -136,7 +136,7 @@ paco_status paco_plan_workspace_size(const paco_plan *plan, size_t *bytes);
  * the top-level twiddle.  paco_plan_describe names the mode; the environment
  * variable PACO_LAYOUT=paper at plan creation selects the paper's layouts.
  *
- * Split form.  A fused PACO_C64 plan with N1 = 2^12 and 16 | N2 <= 2^13 splits each
+ * Split form.  A fused PACO_C64 plan with N1 = 2^12 and 16 | N2 <= 2^14 splits each
  * Phase-I column transform once more by Lemma 1, 4096 = 16 x 256 (row
  * j1 = j + 256 r, frequency k1 = k0 + 16 k).  Pass 1 computes
  *     T[c][j][k0] = w_4096^{-j k0} sum_r X[j + 256 r, c] w_16^{-r k0}

@@ -440,14 +440,16 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
     P->mid.twiddle = 1;
 
     // ---- split form (FP32, N1 = 2^12; knob PACO_SPLIT=0 turns it off) ------
-    // Measured per transform (one launch, MI355X, both forms with plain
-    // stores): N2 = 2^10 49 against 60 us for the packed form, 2^12 183
-    // against 197 us, 2^13 421 against 438 us, but 2^14 944 against 926 us,
-    // so N2 <= 2^13.
+    // Measured per transform (MI355X): with plain stores in both forms,
+    // N2 = 2^10 49 against 60 us for the packed form, 2^12 183 against
+    // 197 us, 2^13 421 against 438 us, 2^14 944 against 926 us; with the
+    // streaming stores of the buffer between the first two passes, 2^14
+    // 914 against 922 us (b = 4) and 947 against 953 us (b = 2).  Larger N2
+    // (up to 2^16) was not measured: N2 <= 2^14.
     {
         const char *sp = std::getenv("PACO_SPLIT");
         const bool want = !(sp && sp[0] == '0');
-        if (want && P->fused && dt == PACO_C64 && P->l1 == paco::kSplitLog2N1 && N2 % 16 == 0 && P->l2 <= 13 &&
+        if (want && P->fused && dt == PACO_C64 && P->l1 == paco::kSplitLog2N1 && N2 % 16 == 0 && P->l2 <= 14 &&
             P->lN <= 32) {
             paco::SplitPass &q = P->split_pass;
             q.N1 = N1;

@@ -67,7 +67,8 @@ def _split_buffer(x, N1, N2):
     return T.ravel()
 
 
-SHAPES = [(4096, 64, 4, 4), (4096, 256, 16, 16), (4096, 512, 8, 2), (4096, 1024, 16, 4), (4096, 128, 64, 2)]
+SHAPES = [(4096, 64, 4, 4), (4096, 256, 16, 16), (4096, 512, 8, 2), (4096, 1024, 16, 4), (4096, 128, 64, 2),
+          (4096, 16384, 64, 4)]
 
 
 @pytest.mark.parametrize("N1,N2,p,b", SHAPES)
@@ -188,7 +189,8 @@ def test_which_plans_split():
     assert not paco.Plan(256, 4096, 4, 16).has_split          # N1 != 4096
     assert not paco.Plan(1024, 4096, 4, 4).has_split
     assert paco.Plan(4096, 8192, 64, 2).has_split
-    assert not paco.Plan(4096, 16384, 64, 4).has_split        # N2 above 2^13: the packed form measured faster
+    assert paco.Plan(4096, 16384, 64, 4).has_split
+    assert not paco.Plan(4096, 32768, 64, 2).has_split        # N2 above 2^14: not measured, the packed form
     assert not paco.Plan(4096, 256, 16, 16, paco.PACO_C64_MFMA_BF16X3).has_split  # FP32 only
     os.environ["PACO_LAYOUT"] = "paper"
     try:
