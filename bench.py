@@ -490,6 +490,12 @@ def main():
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=load_traffic(names[dom].split()[1]),
                     kernel=names[dom], alg_bytes_per_launch=int(alg_bytes))
+    # the same figures for every launch of the step
+    phase_roofline = []
+    for k in range(3):
+        gbs = alg_bytes / (ph_us[k] * 1e-6) / 1e9
+        phase_roofline.append(dict(kernel=names[k], us=round(float(ph_us[k]), 2), achieved_gbs=round(gbs, 1),
+                                   frac=round(gbs / HBM_PEAK_GBS, 4), traffic=load_traffic(names[k].split()[1])))
 
     rec = dict(metric=METRIC, value=round(gflops, 1), unit="GFLOP/s", n_gpus=1, steps=args.steps,
                warmup=args.warmup, ms_per_step=round(ms_per_step, 5), higher_is_better=True,
@@ -500,6 +506,7 @@ def main():
                roofline=roofline,
                hbm_frac_3pass=round(48.0 * N / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                phase_us=[round(float(v), 2) for v in ph_us],
+               phase_roofline=phase_roofline,
                cold_ms_per_step=round(cold_ms, 5),
                cold_hbm_frac_3pass=round(48.0 * N / (cold_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                plan=plan.description)
