@@ -68,7 +68,7 @@ def _split_buffer(x, N1, N2):
 
 
 SHAPES = [(4096, 64, 4, 4), (4096, 256, 16, 16), (4096, 512, 8, 2), (4096, 1024, 16, 4), (4096, 128, 64, 2),
-          (4096, 16384, 64, 4)]
+          (4096, 16384, 64, 4), (4096, 512, 8, 8)]  # b = 8: the general digit reversal in pass 2
 
 
 @pytest.mark.parametrize("N1,N2,p,b", SHAPES)
