@@ -136,18 +136,21 @@ paco_status paco_plan_workspace_size(const paco_plan *plan, size_t *bytes);
  * the top-level twiddle.  paco_plan_describe names the mode; the environment
  * variable PACO_LAYOUT=paper at plan creation selects the paper's layouts.
  *
- * Split form.  A fused PACO_C64 plan with N1 = 2^12 and 16 | N2 <= 2^14 splits each
- * Phase-I column transform once more by Lemma 1, 4096 = 16 x 256 (row
- * j1 = j + 256 r, frequency k1 = k0 + 16 k).  Pass 1 computes
- *     T[c][j][k0] = w_4096^{-j k0} sum_r X[j + 256 r, c] w_16^{-r k0}
+ * Split form.  A fused PACO_C64 plan with N1 = 2^12 and 16 | N2 <= 2^14, and
+ * a PACO_C64 plan with N1 = 2^13 or 2^14 and 64 <= N2, 16 | N2, splits each
+ * Phase-I column transform once more by Lemma 1, N1 = 16 x M (row
+ * j1 = j + M r, frequency k1 = k0 + 16 k).  Pass 1 computes
+ *     T[c][j][k0] = w_N1^{-j k0} sum_r X[j + M r, c] w_16^{-r k0}
  * into workspace[c*N1 + 16 j + k0], reading x in whole 128-byte row runs
  * (16 columns at a time; the packed Phase I reads 32-byte runs).  Pass 2
- * reads column c's T (contiguous), finishes A[k1, c] = sum_j w_256^{-j k}
+ * reads column c's T (contiguous), finishes A[k1, c] = sum_j w_M^{-j k}
  * T[c][j][k0] and writes Phase II's result row pi_{m2}(c) of out with the
- * twiddle w_N^{-k1 c}.  Phase III and out are unchanged, so are the three
- * HBM passes; only how Phase I's arithmetic is divided between the first two
- * passes differs.  paco_plan_has_split tells; PACO_SPLIT=0 in the
- * environment at plan creation keeps the packed form. */
+ * twiddle w_N^{-k1 c}.  Phase III and out are unchanged.  With N1 = 2^12
+ * the HBM passes stay three and only how Phase I's arithmetic is divided
+ * between the first two differs; with N1 = 2^13 or 2^14, where Phase I takes
+ * two on-chip passes otherwise, the split form saves one HBM pass.
+ * paco_plan_has_split tells; PACO_SPLIT=0 in the environment at plan
+ * creation keeps the other plan. */
 paco_status paco_execute(const paco_plan *plan, const void *in, void *out, void *workspace,
                          size_t workspace_bytes, void *stream);
 

@@ -204,12 +204,12 @@ struct MiddlePass {
 
 constexpr int kMidTile = 64;
 
-// The split form of the fused pipeline (split.hip), FP32, N1 = 2^12 =
-// 16 x 256: pass 1 runs the first radix-16 stage of every Phase I column
-// transform (with its twiddle) over whole 128-byte row runs of x and stores
-// ws[c*N1 + 16 j + k0]; pass 2 finishes each column's 16 transforms of
-// length 256 and applies the redistribution of Phase II (row c -> row
-// pi_{m2}(c) of out, times w_N^{-k1 c}) in the same pass.
+// The split form (split.hip), FP32, N1 = 16 M (M = 2^8, 2^9, 2^10): pass 1
+// runs the first radix-16 stage of every Phase I column transform (with its
+// twiddle) over whole 128-byte row runs of x and stores ws[c*N1 + 16 j + k0];
+// pass 2 finishes each column's 16 transforms of length M and applies the
+// redistribution of Phase II (row c -> row pi_{m2}(c) of out, times
+// w_N^{-k1 c}) in the same pass.
 constexpr int kSplitLog2N1 = 12;
 struct SplitPass {
     const float2 *src;
@@ -259,10 +259,11 @@ LocalLaunch local_fft_geometry(const LocalPass &p);
 hipError_t local_fft_prepare();  // raises the dynamic-LDS limit of every kernel once
 hipError_t launch_local_fft(const LocalPass &p, hipStream_t s);
 hipError_t launch_middle(const MiddlePass &p, hipStream_t s);
-// Pass 1 and pass 2 of the split form; hipErrorInvalidValue unless
-// N1 == 2^12 and N2 is a multiple of 16.
+// Pass 1 and pass 2 of the split form; hipErrorInvalidValue unless N1 is
+// 2^12, 2^13 or 2^14 and N2 is a multiple of 16.
 hipError_t launch_split_first(const SplitPass &p, hipStream_t s);
 hipError_t launch_split_middle(const SplitPass &p, hipStream_t s);
+hipError_t split_prepare();  // raises the dynamic-LDS limit of the three-stage pass 2 once
 
 // Columns per workgroup for an on-chip pass of length 2^log2n over ncols.
 int32_t choose_log2T(int32_t log2n, int64_t ncols);

@@ -233,6 +233,7 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
     hipError_t e = hipGetDevice(&P->device);
     if (e != hipSuccess) { delete P; return hip_fail(e, "hipGetDevice"); }
     e = paco::local_fft_prepare();
+    if (e == hipSuccess) e = paco::split_prepare();
     if (e != hipSuccess) { delete P; return hip_fail(e, "hipFuncSetAttribute"); }
     e = hipMalloc(&P->dev_tables, total);
     if (e != hipSuccess) { P->dev_tables = nullptr; delete P; return fail(PACO_ERR_ALLOC, std::string("hipMalloc: ") + hipGetErrorString(e)); }
@@ -449,8 +450,12 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
     {
         const char *sp = std::getenv("PACO_SPLIT");
         const bool want = !(sp && sp[0] == '0');
-        if (want && P->fused && dt == PACO_C64 && P->l1 == paco::kSplitLog2N1 && N2 % 16 == 0 && P->l2 <= 14 &&
-            P->lN <= 32) {
+        // N1 = 2^13, 2^14: Phase I takes two on-chip passes there, so the split
+        // form also saves one HBM pass (pass 2 runs its M-point transforms in
+        // three stages; see split.hip)
+        const bool n4096 = P->fused && P->l1 == paco::kSplitLog2N1 && P->l2 <= 14;
+        const bool nlong = (P->l1 == 13 || P->l1 == 14) && N2 >= 64;
+        if (want && dt == PACO_C64 && (n4096 || nlong) && N2 % 16 == 0 && P->lN <= 32) {
             paco::SplitPass &q = P->split_pass;
             q.N1 = N1;
             q.N2 = N2;
@@ -480,9 +485,13 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
         }
         desc += " ]";
     }
-    if (P->split)
-        desc = "split[pass1: phase1 radix-16 stage over 128-byte row runs -> ws; pass2: 256-point tails + "
-               "row unpack+twiddle] " + desc;
+    if (P->split) {
+        std::snprintf(buf, sizeof buf,
+                      "split[pass1: phase1 radix-16 stage over 128-byte row runs -> ws; pass2: %lld-point tails + "
+                      "row unpack+twiddle] ",
+                      (long long)(N1 / 16));
+        desc = buf + desc;
+    }
     if (P->fused) desc = "fused[phase1 -> packed transposed slab, phase2 row unpack+twiddle] " + desc;
     if (P->two_pass) {
         const paco::LocalLaunch g = paco::local_fft_geometry(P->phase3_two);

@@ -28,7 +28,8 @@ constexpr int kSplitThreads = 256;
 constexpr int kFirstPad = 257;  // LDS row of pass 1: 256 items + 1
 
 // Pass 1.  Workgroup (cg, jg) owns columns c = 16 cg + cl and indices
-// j = 16 jg + jl (cl, jl < 16), i.e. rows j + 256 r of 16 adjacent columns:
+// j = 16 jg + jl (cl, jl < 16), i.e. rows j + M r (M = N1 / 16) of 16
+// adjacent columns:
 // every load instruction reads four full 128-byte row runs.  Its 16 x 256
 // results are ws[c*N1 + 256 jg + (16 jl + k0)]: 2 KiB contiguous per column,
 // stored through LDS so that every store instruction writes 512 bytes, with
@@ -46,9 +47,10 @@ __global__ __launch_bounds__(kSplitThreads) void split_first_kernel(SplitPass P)
     const int cl = tid & 15, jl = tid >> 4;
     const int64_t c = (cg << 4) + cl;
     const int j = int(jg << 4) + jl;
+    const int64_t M = P.N1 >> 4;  // rows j + M r of the first radix-16 stage
     float2 v[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = P.src[(int64_t(j) + (r << 8)) * P.N2 + c];
+    for (int r = 0; r < 16; ++r) v[r] = P.src[(int64_t(j) + r * M) * P.N2 + c];
     if (P.conj_in) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) v[r].y = -v[r].y;
@@ -125,13 +127,119 @@ __global__ __launch_bounds__(kSplitThreads) __attribute__((amdgpu_waves_per_eu(5
         st2<false>(dst + size_t(256 * kh) * 8u, cmul(v[kh], cmul(a, cmul(bh[kh], bl[kh]))));
 }
 
+// Pass 2 for N1 = 16 M with M = 256 R (R = 2^LR = 2 or 4: N1 = 2^13, 2^14).
+// Workgroup c, M threads, 16 items each; the M-point transforms over
+// j = jl + (M/16) jh (jl < M/16) run as three stages:
+//   A  thread (k0, jl): radix 16 over jh -> ka, times w_M^{-jl ka};
+//   B  thread (k0, ka, jlo) (jl = jlo + R jhi): radix 16 over jhi -> kb,
+//      times w_{16R}^{-jlo kb};
+//   C  thread (k0, q), pairs (ka, kb) = q + (M/16) i (i < 16/R): radix R
+//      over jlo -> kc,
+// so k1 = k0 + 16 ka + 256 kb + 4096 kc = k0 + 16 (ka + 16 kb) + 4096 kc.
+// Both exchanges go through the same 32R KiB of dynamic LDS, in 16-item
+// rows whose index is XOR-swizzled by ka & 3 (a wave's four ka values then
+// fall into two bank halves).  The top-level twiddle is
+//   w_N^{-k1 c} = w_N^{-k0 c} * w_N^{-16 (ka + 16 kb) c} * w_N^{-4096 kc c}.
+template <bool GEN, int LR>
+__global__ __launch_bounds__(256 << LR) void split_middle3_kernel(SplitPass P)
+{
+    extern __shared__ float2 xbuf[];
+    constexpr int R = 1 << LR, JL = (256 << LR) / 16, NPAIR = 16 / R;
+    const int tid = threadIdx.x;
+    const int64_t c = blockIdx.x;
+    const int k0 = tid & 15;
+    const float2 *src = P.src + c * P.N1;
+    const uint32_t nmask = uint32_t((uint64_t(1) << P.log2N) - 1), lomask = (1u << P.log2Lo) - 1;
+
+    // stage A operands, then every twiddle, issued before the first butterfly
+    const int jl = tid >> 4;
+    float2 v[16];
+#pragma unroll
+    for (int jh = 0; jh < 16; ++jh) v[jh] = ld2_last(src + (jl + JL * jh) * 16 + k0);  // nothing reads ws again
+    // stage B: (k0, ka, jlo); jlo is the same for a whole wave (its twiddles
+    // are scalar loads)
+    const int kab = (tid >> 4) & 15, jlo = __builtin_amdgcn_readfirstlane(tid >> 8);
+    const int q = tid >> 4;                           // stage C: (k0, q)
+    float2 tA[16], tB[16];
+#pragma unroll
+    for (int k = 1; k < 16; ++k) {
+        tA[k] = P.tw[(16 * jl * k) << P.tw_shift];    // w_M^{-jl ka}
+        tB[k] = P.tw[(256 * jlo * k) << P.tw_shift];  // w_{16R}^{-jlo kb}
+    }
+    float2 h0, l0, hp[NPAIR], lp[NPAIR], hc[R], lc[R];
+    {
+        const uint32_t e = (uint32_t(k0) * uint32_t(c)) & nmask;
+        h0 = P.tw_hi[e >> P.log2Lo];
+        l0 = P.tw_lo[e & lomask];
+    }
+#pragma unroll
+    for (int i = 0; i < NPAIR; ++i) {
+        const uint32_t e = (uint32_t(16 * (q + JL * i)) * uint32_t(c)) & nmask;
+        hp[i] = P.tw_hi[e >> P.log2Lo];
+        lp[i] = P.tw_lo[e & lomask];
+    }
+#pragma unroll
+    for (int kc = 0; kc < R; ++kc) {
+        const uint32_t e = (uint32_t(4096 * kc) * uint32_t(c)) & nmask;
+        hc[kc] = P.tw_hi[e >> P.log2Lo];
+        lc[kc] = P.tw_lo[e & lomask];
+    }
+    const int64_t u = digmap<GEN>(c, P.t, P.m2, P.s2, false);
+
+    // A: Y[ka][jl][k0] in row ka JL + (jl ^ (ka & 3))
+    dft_regs<4>(v);
+#pragma unroll
+    for (int k = 1; k < 16; ++k) v[k] = cmul(v[k], tA[k]);
+#pragma unroll
+    for (int ka = 0; ka < 16; ++ka) xbuf[((ka * JL + (jl ^ (ka & 3))) << 4) | k0] = v[ka];
+    __syncthreads();
+    // B: items jhi of (ka, jlo), jl = jlo + R jhi
+#pragma unroll
+    for (int jhi = 0; jhi < 16; ++jhi) v[jhi] = xbuf[((kab * JL + ((jlo + R * jhi) ^ (kab & 3))) << 4) | k0];
+    dft_regs<4>(v);
+#pragma unroll
+    for (int k = 1; k < 16; ++k) v[k] = cmul(v[k], tB[k]);
+    __syncthreads();  // every wave has read its stage-B operands
+    // Z[pr = ka + 16 kb][jlo][k0] in row ((pr R + jlo) ^ (ka & 3))
+#pragma unroll
+    for (int kb = 0; kb < 16; ++kb) xbuf[(((((kb << 4) + kab) << LR) + jlo) ^ (kab & 3)) << 4 | k0] = v[kb];
+    __syncthreads();
+    // C: NPAIR radix-R butterflies per thread, stored straight to row pi_{m2}(c)
+    const float2 a0 = cmul(h0, l0);
+    char *dst = reinterpret_cast<char *>(P.dst + u * P.N1 + k0);
+#pragma unroll
+    for (int i = 0; i < NPAIR; ++i) {
+        const int pr = q + JL * i, ka = pr & 15;
+        float2 z[R];
+#pragma unroll
+        for (int j2 = 0; j2 < R; ++j2) z[j2] = xbuf[((((pr << LR) + j2) ^ (ka & 3)) << 4) | k0];
+        dft_regs<LR>(z);
+        const float2 a = cmul(a0, cmul(hp[i], lp[i]));
+#pragma unroll
+        for (int kc = 0; kc < R; ++kc)
+            st2<false>(dst + (size_t(16 * pr) + size_t(4096 * kc)) * 8u, cmul(z[kc], cmul(a, cmul(hc[kc], lc[kc]))));
+    }
+}
+
 bool split_shape_ok(const SplitPass &p)
 {
-    return p.N1 == (int64_t(1) << kSplitLog2N1) && p.N2 >= 16 && p.N2 % 16 == 0 && p.log2N <= 32 &&
+    return (p.N1 == 4096 || p.N1 == 8192 || p.N1 == 16384) && p.N2 >= 16 && p.N2 % 16 == 0 && p.log2N <= 32 &&
            p.src && p.dst && p.tw && p.tw_hi && p.tw_lo;
 }
 
 }  // namespace
+
+hipError_t split_prepare()
+{
+    for (const void *k : {reinterpret_cast<const void *>(&split_middle3_kernel<false, 1>),
+                          reinterpret_cast<const void *>(&split_middle3_kernel<true, 1>),
+                          reinterpret_cast<const void *>(&split_middle3_kernel<false, 2>),
+                          reinterpret_cast<const void *>(&split_middle3_kernel<true, 2>)}) {
+        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
 
 hipError_t launch_split_first(const SplitPass &p, hipStream_t s)
 {
@@ -144,7 +252,14 @@ hipError_t launch_split_first(const SplitPass &p, hipStream_t s)
 hipError_t launch_split_middle(const SplitPass &p, hipStream_t s)
 {
     if (!split_shape_ok(p)) return hipErrorInvalidValue;
-    void (*k)(SplitPass) = digrev_fast(p.t) ? split_middle_kernel<false> : split_middle_kernel<true>;
+    const bool f = digrev_fast(p.t);
+    if (p.N1 != 4096) {  // three stages: 512 or 1024 threads, 64 or 128 KiB of LDS
+        void (*k3)(SplitPass) = p.N1 == 8192 ? (f ? split_middle3_kernel<false, 1> : split_middle3_kernel<true, 1>)
+                                             : (f ? split_middle3_kernel<false, 2> : split_middle3_kernel<true, 2>);
+        hipLaunchKernelGGL(k3, dim3(unsigned(p.N2)), dim3(unsigned(p.N1 / 16)), size_t(p.N1) * 8u, s, p);
+        return hipGetLastError();
+    }
+    void (*k)(SplitPass) = f ? split_middle_kernel<false> : split_middle_kernel<true>;
     hipLaunchKernelGGL(k, dim3(unsigned(p.N2)), dim3(kSplitThreads), 0, s, p);
     return hipGetLastError();
 }

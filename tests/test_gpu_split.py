@@ -83,6 +83,46 @@ def test_split_matches_oracle(N1, N2, p, b):
     assert err <= TOL
 
 
+# N1 = 2^13, 2^14: pass 2 runs 512- / 1024-point tails in three stages and
+# replaces Phase I's two on-chip passes and Phase II
+LONG_SHAPES = [(8192, 64, 4, 2), (16384, 64, 4, 4), (16384, 256, 16, 4), (8192, 128, 8, 2), (16384, 128, 64, 2)]
+
+
+@pytest.mark.parametrize("N1,N2,p,b", LONG_SHAPES)
+def test_split_long_columns_match_oracle(N1, N2, p, b):
+    x = inputs.normal(N1 * N2, seed=N1 // 64 + N2)
+    plan = paco.Plan(N1, N2, p, b)
+    assert plan.has_split and f"pass2: {N1 // 16}-point tails" in plan.description, plan.description
+    y = _execute(plan, _dev(x))
+    err = oracle.rel_l2(y, oracle.dft(x))
+    print(f"split {N1}x{N2} p={p} b={b}: rel-L2 {err:.3e}", flush=True)
+    assert err <= TOL
+
+
+@pytest.mark.parametrize("N1,N2,p,b", [(16384, 256, 16, 16), (8192, 512, 8, 8)])
+def test_split_long_columns_mixed_radix(N1, N2, p, b):
+    # 2^14 = 16^3 * 4 and 2^13 = 8^4 * 2: mixed-radix plans (b = 8: the general digit reversal)
+    x = inputs.normal(N1 * N2, seed=N1 // 128 + N2)
+    plan = paco.Plan(N1, N2, p, b, mixed=True)
+    assert plan.has_split, plan.description
+    err = oracle.rel_l2(_execute(plan, _dev(x)), oracle.dft(x))
+    print(f"split mixed {N1}x{N2} b={b}: rel-L2 {err:.3e}", flush=True)
+    assert err <= TOL
+
+
+def test_split_long_stage_hooks_compose_to_execute():
+    N1, N2, p, b = 16384, 64, 4, 4
+    x = _dev(inputs.normal(N1 * N2, seed=78))
+    plan = paco.Plan(N1, N2, p, b)
+    t = _stage(plan, 1, x, paco.PACO_SPLIT)
+    z = _stage(plan, 2, t, paco.PACO_SPLIT)
+    want = oracle.phase2(oracle.phase1(x.cpu().numpy(), N1, N2, b), N1, N2, b).ravel()
+    assert oracle.rel_l2(z.cpu().numpy(), want) <= TOL  # pass 2's output is Phase II's
+    plan.execute_stage(3, z.data_ptr(), z.data_ptr(), _stream(), 0)
+    torch.cuda.synchronize()
+    assert np.array_equal(z.cpu().numpy().view(np.uint64), _execute(plan, x).view(np.uint64))
+
+
 def test_split_mixed_radix_matches_oracle():
     # N2 = 2048 = 16^2 * 2^3 with b = 16: the redistribution's digit map has a short digit
     N1, N2, p, b = 4096, 2048, 16, 16
@@ -191,6 +231,9 @@ def test_which_plans_split():
     assert paco.Plan(4096, 8192, 64, 2).has_split
     assert paco.Plan(4096, 16384, 64, 4).has_split
     assert not paco.Plan(4096, 32768, 64, 2).has_split        # N2 above 2^14: not measured, the packed form
+    assert paco.Plan(16384, 64, 4, 4).has_split and paco.Plan(8192, 64, 4, 2).has_split
+    assert not paco.Plan(16384, 32, 2, 2).has_split           # N2 below 64
+    assert not paco.Plan(16384, 64, 4, 4, paco.PACO_C64_MFMA_FP16X3).has_split
     assert not paco.Plan(4096, 256, 16, 16, paco.PACO_C64_MFMA_BF16X3).has_split  # FP32 only
     os.environ["PACO_LAYOUT"] = "paper"
     try:
