@@ -570,7 +570,8 @@ paco_status paco_plan_workspace_size(const paco_plan *plan, size_t *bytes)
 paco_status paco_plan_describe(const paco_plan *plan, int32_t *launches, char *buf, size_t buflen)
 {
     if (!plan) return fail(PACO_ERR_INVALID_ARG, "plan is NULL");
-    if (launches) *launches = int32_t(plan->phase1.size() + 1 + plan->phase3.size());
+    if (launches)  // the split form runs its two passes in place of Phase I's passes and Phase II
+        *launches = int32_t((plan->split ? 2 : plan->phase1.size() + 1) + plan->phase3.size());
     if (buf && buflen) {
         std::strncpy(buf, plan->desc.c_str(), buflen - 1);
         buf[buflen - 1] = 0;

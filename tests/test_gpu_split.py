@@ -232,6 +232,10 @@ def test_which_plans_split():
     assert paco.Plan(4096, 16384, 64, 4).has_split
     assert not paco.Plan(4096, 32768, 64, 2).has_split        # N2 above 2^14: not measured, the packed form
     assert paco.Plan(16384, 64, 4, 4).has_split and paco.Plan(8192, 64, 4, 2).has_split
+    # launches paco_execute makes: pass 1, pass 2 and Phase III's passes
+    assert paco.Plan(4096, 4096, 64, 16).launches == 3
+    assert paco.Plan(16384, 64, 4, 4).launches == 3
+    assert paco.Plan(16384, 16384, 256, 4).launches == 4
     assert not paco.Plan(16384, 32, 2, 2).has_split           # N2 below 64
     assert not paco.Plan(16384, 64, 4, 4, paco.PACO_C64_MFMA_FP16X3).has_split
     assert not paco.Plan(4096, 256, 16, 16, paco.PACO_C64_MFMA_BF16X3).has_split  # FP32 only
