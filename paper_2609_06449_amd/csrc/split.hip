@@ -1,23 +1,25 @@
-// The split form of the fused pipeline for N1 = 2^12 (FP32).
+// The split form (FP32) for N1 = 16 M, M = 2^8, 2^9, 2^10 (N1 = 2^12 .. 2^14).
 //
-// Phase I transforms every column c of X (N1 x N2, row-major) over its
-// N1 = 4096 rows.  Split once more by Cooley-Tukey (Lemma 1 with a first
-// child of length 16): with row j1 = j + 256 r and frequency k1 = k0 + 16 k,
+// Phase I transforms every column c of X (N1 x N2, row-major) over its N1
+// rows.  Split once more by Cooley-Tukey (Lemma 1 with a first child of
+// length 16): with row j1 = j + M r and frequency k1 = k0 + 16 k,
 //
-//   A[k1, c] = sum_j w_256^{-j k} T[c][j][k0],
-//   T[c][j][k0] = w_4096^{-j k0} sum_r X[j + 256 r, c] w_16^{-r k0}.
+//   A[k1, c] = sum_j w_M^{-j k} T[c][j][k0],
+//   T[c][j][k0] = w_N1^{-j k0} sum_r X[j + M r, c] w_16^{-r k0}.
 //
 // The bracket needs only 16 rows of a column at a time, so pass 1 can read
 // x in whole 128-byte row runs (16 columns per workgroup), where a tile that
 // holds entire 4096-point columns on chip reads 32-byte runs; its HBM
 // pattern measured ~30% faster.  The rest of the column transform (16
-// transforms of length 256 per column) needs each column's T contiguous,
+// transforms of length M per column) needs each column's T contiguous,
 // which is exactly what the redistribution of Phase II reads, so pass 2
-// finishes them there: it reads column c's 32 KiB block once, runs two
-// radix-16 stages with one LDS exchange, multiplies by the top-level twiddle
-// w_N^{-k1 c} (Phase II, Sec. 4) and writes row pi_{m2}(c) of out in natural
-// k1 order, as the packed Phase II does.  The pipeline stays at three HBM
-// passes; Phase III is unchanged.
+// finishes them there: it reads column c's block once (N1 items), runs the
+// M-point transforms (two radix-16 stages for M = 256, three stages for 512
+// and 1024), multiplies by the top-level twiddle w_N^{-k1 c} (Phase II,
+// Sec. 4) and writes row pi_{m2}(c) of out in natural k1 order, as the
+// packed Phase II does.  Phase III is unchanged.  For N1 = 2^12 the pipeline
+// stays at three HBM passes; for 2^13 and 2^14, whose Phase I otherwise
+// takes two on-chip passes, the split form saves one.
 
 #include "stages.h"
 
@@ -29,12 +31,12 @@ constexpr int kFirstPad = 257;  // LDS row of pass 1: 256 items + 1
 
 // Pass 1.  Workgroup (cg, jg) owns columns c = 16 cg + cl and indices
 // j = 16 jg + jl (cl, jl < 16), i.e. rows j + M r (M = N1 / 16) of 16
-// adjacent columns:
-// every load instruction reads four full 128-byte row runs.  Its 16 x 256
-// results are ws[c*N1 + 256 jg + (16 jl + k0)]: 2 KiB contiguous per column,
-// stored through LDS so that every store instruction writes 512 bytes, with
-// streaming stores.  Pass 2 reads ws once, in whole 32 KiB blocks that HBM
-// serves at copy speed; left out of the 256 MiB MALL, ws no longer pushes x
+// adjacent columns: every load instruction reads four full 128-byte row
+// runs.  Its 16 x 256 results are ws[c*N1 + 256 jg + (16 jl + k0)]: 2 KiB
+// contiguous per column, stored through LDS so that every store instruction
+// writes 512 bytes, with streaming stores.  Pass 2 reads ws once, in whole
+// column blocks that HBM serves at copy speed; left out of the 256 MiB
+// MALL, ws no longer pushes x
 // (read again by the next transform) and out (Phase III's input) out of
 // it: 2^24 back to back, pass 1 59 -> 47 us, pass 2 56 -> 53 us, Phase III
 // 67 -> 65 us, the transform 175 -> 157 us.
