@@ -8,7 +8,7 @@ sharing Phase I's butterflies.  Inputs are resident in HBM before the timed
 region.  Prints one JSON line: GFLOP/s = 5 N log2 N / t, plus the dominant
 kernel's roofline (HIP events on the stream the kernels run on; phase_us
 times pass 1, pass 2 and Phase III one launch each) and the CPU oracle
-baseline.
+baseline (one thread and all host cores, with the core count and CPU model).
 
 Further fields of the same line (each leg can be skipped by a flag):
   two_pass   the two-HBM-pass form of the same transform (an ablation,
@@ -16,7 +16,8 @@ Further fields of the same line (each leg can be skipped by a flag):
   batched    4096 transforms, N_i = 2^k, k ~ U{8..20}, in one persistent
              launch replayed from a graph, against a loop of single calls
   large      N = 2^28 in two shapes, with their literal (mixed-radix) bases
-             and with the largest bases of which both sizes are powers
+             and with the largest bases of which both sizes are powers; each
+             complete output's rel-L2 against the FP64 oracle
   precision  FP32 and the split MFMA forms at 2^24 and 2^26 on log-uniform
              inputs, with their rel-L2 and worst-output errors vs FP64
 --calibrate-copy adds the device copy that scales rocprofv3's FETCH_SIZE /
@@ -112,26 +113,39 @@ def traffic_from(fetch_csv: str, write_csv: str):
 
 
 def cpu_baseline(x, N: int, budget_s: float):
-    """The FP64 oracle (recursive radix-2, single thread) on whole N-point
-    transforms of the same input, repeated until ~budget_s of CPU work."""
+    """The FP64 oracle (recursive radix-2) on whole N-point transforms of the
+    same input, on one host thread and on all of the host's cores (the same
+    recursion with its top levels spread over threads: bit-identical output),
+    each repeated (at least 3 times) until about budget_s / 2 of wall time;
+    medians reported.  `value` is the all-cores figure."""
     import numpy as np
     import oracle
 
     xs = x.astype(np.complex128)
-    times = []
-    ref = None
-    t_all = time.perf_counter()
-    while True:
-        t0 = time.perf_counter()
-        ref = oracle.fft_radix2(xs)
-        times.append(time.perf_counter() - t0)
-        if time.perf_counter() - t_all > budget_s or len(times) >= 20:
-            break
-    t = sorted(times)[len(times) // 2]
-    return ref, dict(value=round(5.0 * N * math.log2(N) / t / 1e9, 3), unit="GFLOP/s", cores=1,
-                     kind="oracle",
-                     sample=f"{len(times)} full N=2^{int(math.log2(N))} transforms of the bench input "
-                            f"(median {t:.3f} s each, {sum(times):.1f} s total); FP64 recursive radix-2, one thread")
+    gflop = 5.0 * N * math.log2(N) / 1e9
+    threads = oracle.cpu_threads()
+
+    def timed(nthreads):
+        times, ref = [], None
+        t_all = time.perf_counter()
+        while True:
+            t0 = time.perf_counter()
+            ref = oracle.fft_radix2(xs, threads=nthreads)
+            times.append(time.perf_counter() - t0)
+            if len(times) >= 3 and (time.perf_counter() - t_all > budget_s / 2 or len(times) >= 20):
+                break
+        t = sorted(times)[len(times) // 2]
+        return ref, dict(value=round(gflop / t, 3), unit="GFLOP/s", threads=nthreads, median_s=round(t, 4),
+                         runs=len(times))
+
+    ref, one = timed(1)
+    ref_all, many = timed(threads)
+    assert np.array_equal(ref.view(np.uint64), ref_all.view(np.uint64)), "threaded oracle differs"
+    return ref, dict(value=many["value"], unit="GFLOP/s", cores=threads, kind="oracle",
+                     sample=f"full N=2^{int(math.log2(N))} transforms of the bench input, FP64 recursive radix-2: "
+                            f"{one['runs']} on one thread (median {one['median_s']:.3f} s), {many['runs']} on "
+                            f"{threads} threads (median {many['median_s']:.3f} s); value = all cores",
+                     threads_1=one, threads_all=many, nproc=os.cpu_count(), cpu_model=oracle.cpu_model())
 
 
 def bench_batched(steps: int, warmup: int):
@@ -214,6 +228,9 @@ def bench_batched(steps: int, warmup: int):
                loop_single_calls_ms=round(loop_ms, 3), loop_single_calls_graph_ms=round(loop_graph_ms, 3),
                speedup_vs_loop=round(loop_ms / ms, 2), speedup_vs_loop_graph=round(loop_graph_ms / ms, 2),
                plan_create_s=round(tune_s, 2), wait_timeouts=errors, plan=plan.description)
+    if errors:  # a wait gave up: the launch completed with unspecified results
+        rec.update(valid=False, gflops=None, hbm_frac_3pass=None,
+                   note=f"{errors} completion waits hit their poll limit: results unspecified, not a measurement")
     del g, g2, x, out, ws
     for pl in singles.values():
         pl.close()
@@ -279,21 +296,26 @@ LARGE_WORKLOADS = [  # the full-HBM-scale shapes: N = 2^28 (2 GiB per buffer), N
 ]
 
 
-def bench_large(steps: int, warmup: int):
-    """The N = 2^28 shapes (two on-chip passes per local phase: 5 HBM passes):
-    milliseconds per transform and the fraction of the 5-pass roofline.  Inputs
-    are drawn on the device from a seeded generator (timing only; their
-    values are checked against the oracle in the tests)."""
+def bench_large(steps: int, warmup: int, keep_outputs: bool = True):
+    """The N = 2^28 shapes: milliseconds per transform and the fraction of the
+    roofline of the HBM passes the plan makes (`launches`: pass 1, pass 2 and
+    Phase III's two on-chip passes, 4 per transform) and of the 3-pass one.
+    Inputs are the seeded N(0,1) recipes of the tests (seed 3 for the square
+    shapes, 4 for the non-square ones).  With keep_outputs, each shape's
+    complete output is copied to the host after its timed launches (the
+    CPU-baseline leg compares them with the FP64 oracle)."""
     import torch
 
-    from paper_2609_06449_amd import paco
+    from paper_2609_06449_amd import inputs, paco
 
-    rec = {}
+    rec, outs = {}, {}
     sh = torch.cuda.current_stream().cuda_stream
+    xs = {}
     for w in LARGE_WORKLOADS:
         N = w["N1"] * w["N2"]
-        gen = torch.Generator(device="cuda").manual_seed(w["seed"])
-        xd = torch.randn(N, dtype=torch.complex64, device="cuda", generator=gen)
+        if w["seed"] not in xs:
+            xs[w["seed"]] = inputs.normal(N, w["seed"])
+        xd = torch.from_numpy(xs[w["seed"]]).to("cuda")
         out = torch.empty_like(xd)
         ws = torch.empty_like(xd)
         plan = paco.Plan(w["N1"], w["N2"], w["p"], w["b"], mixed=w.get("mixed", False))
@@ -311,10 +333,27 @@ def bench_large(steps: int, warmup: int):
                               hbm_frac_passes=round(16.0 * N * plan.launches / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                               hbm_frac_3pass=round(48.0 * N / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                               launches=plan.launches)
+        if keep_outputs:
+            outs[w["name"]] = out.cpu().numpy()
         plan.close()
         del xd, out, ws
         torch.cuda.empty_cache()
-    return rec
+    return rec, outs, xs
+
+
+def large_errors(outs, xs):
+    """rel-L2 of every 2^28 output against the FP64 oracle (all host cores,
+    one oracle run per input)."""
+    import oracle
+
+    errs = {}
+    for seed, x in xs.items():
+        ref = oracle.fft_radix2(x, threads=oracle.cpu_threads())
+        for w in LARGE_WORKLOADS:
+            if w["seed"] == seed and w["name"] in outs:
+                errs[w["name"]] = float(f"{oracle.rel_l2(outs[w['name']], ref):.4e}")
+        del ref
+    return errs
 
 
 def precision_errors(outs):
@@ -478,7 +517,7 @@ def main():
     if plan.has_split:  # the kernels of the default plan for this workload
         names = ["pass1 split_first_kernel", "pass2 split_middle_kernel<false>",
                  "phase3 local_fft_fast_kernel<12,1,4,2,32,0>"]
-    elif fl:  # the packed form (PACO_SPLIT=0)
+    elif fl:  # the packed form (plan option PACO_PLAN_NO_SPLIT)
         names = ["phase1 local_fft_fast_kernel<12,2,1,2,16,0>", "phase2 middle_packed2_kernel<false,true>",
                  "phase3 local_fft_fast_kernel<12,1,4,2,32,0>"]
     else:
@@ -522,9 +561,12 @@ def main():
         if "xd" in locals():
             del xd, out, ws
         torch.cuda.empty_cache()
-        rec["large"] = bench_large(max(5, args.steps // 20), 2)
+        rec["large"], large_outs, large_xs = bench_large(max(5, args.steps // 20), 2,
+                                                         keep_outputs=not args.skip_cpu_baseline)
 
     prec_outs = None
+    if args.skip_large:
+        large_outs, large_xs = {}, {}
     if not args.skip_precision:
         if "xd" in locals():
             del xd, out, ws
@@ -546,6 +588,8 @@ def main():
             for name, by_w in precision_errors(prec_outs).items():
                 for wname, e in by_w.items():
                     rec["precision"][name][wname].update(e)
+        for name, e in large_errors(large_outs, large_xs).items():
+            rec["large"][name]["rel_l2_vs_oracle"] = e
     else:
         rec["cpu_baseline"] = None
     print(json.dumps(rec), flush=True)

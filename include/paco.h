@@ -115,6 +115,35 @@ paco_status paco_plan_validate_mixed(int64_t N1, int64_t N2, int64_t p, int32_t 
 paco_status paco_plan_create_mixed(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int32_t b,
                                    paco_dtype dt);
 
+/* Plan-creation options.  Every field at zero selects the default, which is
+ * what paco_plan_create builds; a plan never depends on the process
+ * environment (the one exception, PACO_LOG=1, only prints each plan's pass
+ * summary on stderr).  The alternatives exist for stage-wise checks of the
+ * paper's own layouts and for measurement. */
+typedef struct {
+    uint32_t flags;        /* PACO_PLAN_* bits below                                  */
+    int32_t groups1;       /* 0: default; 1, 2 or 3 LDS column groups of Phase I's
+                              single-pass tile (3: two groups of a tile twice as wide) */
+    int32_t groups3;       /* 0: default; the same for Phase III                     */
+    int32_t cols_long;     /* 0: default; else the columns per workgroup (a power of
+                              two) of a single-group pass of 2^10 or more points      */
+} paco_plan_options;
+
+#define PACO_PLAN_MIXED 1u         /* mixed-radix sizes (as paco_plan_create_mixed)        */
+#define PACO_PLAN_PAPER_LAYOUT 2u  /* the paper's Phase-I layout Atilde and a Phase II that
+                                      applies the whole pi_m (no packed buffer, no split
+                                      form, no two-pass form)                              */
+#define PACO_PLAN_NO_SPLIT 4u      /* no split form (the packed form, or the two on-chip
+                                      passes of Phase I plus Phase II)                     */
+#define PACO_PLAN_GENERIC 8u       /* descriptor-driven kernels only (no fast tiles, no
+                                      split form); same arithmetic order as the fast tiles */
+
+/* paco_plan_create / paco_plan_create_mixed with options (NULL: defaults).
+ * Errors as paco_plan_create; PACO_ERR_INVALID_ARG for an unknown flag or a
+ * field out of range. */
+paco_status paco_plan_create_ex(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int32_t b, paco_dtype dt,
+                                const paco_plan_options *options);
+
 /* Bytes of device workspace paco_execute needs (N1*N2*8 for PACO_C64). */
 paco_status paco_plan_workspace_size(const paco_plan *plan, size_t *bytes);
 
@@ -133,8 +162,8 @@ paco_status paco_plan_workspace_size(const paco_plan *plan, size_t *bytes);
  *     workspace[c*N1 + k1] = A[k1, c]   (the "packed" buffer),
  * with contiguous runs on both sides of every HBM pass but Phase I's reads and
  * Phase III's writes.  Phase II is then the unpack (rows c -> pi_{m2}(c)) with
- * the top-level twiddle.  paco_plan_describe names the mode; the environment
- * variable PACO_LAYOUT=paper at plan creation selects the paper's layouts.
+ * the top-level twiddle.  paco_plan_describe names the mode; the plan option
+ * PACO_PLAN_PAPER_LAYOUT selects the paper's layouts.
  *
  * Split form.  A fused PACO_C64 plan with N1 = 2^12 and 16 | N2 <= 2^14, and
  * a PACO_C64 plan with N1 = 2^13 or 2^14 and 64 <= N2, 16 | N2, splits each
@@ -149,8 +178,8 @@ paco_status paco_plan_workspace_size(const paco_plan *plan, size_t *bytes);
  * the HBM passes stay three and only how Phase I's arithmetic is divided
  * between the first two differs; with N1 = 2^13 or 2^14, where Phase I takes
  * two on-chip passes otherwise, the split form saves one HBM pass.
- * paco_plan_has_split tells; PACO_SPLIT=0 in the environment at plan
- * creation keeps the other plan. */
+ * paco_plan_has_split tells; the plan option PACO_PLAN_NO_SPLIT keeps the
+ * other plan. */
 paco_status paco_execute(const paco_plan *plan, const void *in, void *out, void *workspace,
                          size_t workspace_bytes, void *stream);
 
@@ -250,8 +279,8 @@ typedef struct paco_batch_plan_s paco_batch_plan;
  * dividing both exponents, tile widths) come from, in order: the tuning
  * cache file tune_cache_path (text, one line per size, written by an earlier
  * call), else timing every candidate on the current device (allocates about
- * 400 MB of device memory for a moment; the environment variable
- * PACO_BATCH_TUNE=0 skips the timing and takes the defaults), after which
+ * 400 MB of device memory for a moment; the option PACO_BATCH_NO_TUNE of
+ * paco_batch_plan_create_ex skips the timing and takes the defaults), after which
  * the cache file, if named, is (re)written.  NULL: tune now, no file.
  * dt must be PACO_C64 (the split MFMA forms are single-transform only).
  * Errors: NOT_POWER_OF_B (a size not a power of two), UNSUPPORTED (a size
@@ -259,6 +288,28 @@ typedef struct paco_batch_plan_s paco_batch_plan;
  * unknown dt, unwritable cache). */
 paco_status paco_batch_plan_create(paco_batch_plan **bp, int32_t count, const int64_t *N, paco_dtype dt,
                                    const char *tune_cache_path);
+
+/* Batch-plan options (every field zero: the defaults of
+ * paco_batch_plan_create). */
+typedef struct {
+    uint32_t flags;        /* PACO_BATCH_* bits below                              */
+    uint32_t spin_limit;   /* 0: default (2^22); polls before a completion wait
+                              gives up and is counted by paco_batch_errors          */
+    int64_t gap;           /* with PACO_BATCH_SET_GAP: tiles between a job and its
+                              successor in a queue (default: 4 x the resident
+                              workgroups per queue)                                  */
+} paco_batch_options;
+
+#define PACO_BATCH_NO_TUNE 1u      /* default per-size plans, no timing (a cache file is
+                                      still read if named, never written)               */
+#define PACO_BATCH_ONE_QUEUE 2u    /* one shared work queue with device-coherent stores
+                                      instead of one queue per XCD                      */
+#define PACO_BATCH_SET_GAP 4u      /* use options->gap                                  */
+
+/* paco_batch_plan_create with options (NULL: defaults); INVALID_ARG for an
+ * unknown flag or a negative gap. */
+paco_status paco_batch_plan_create_ex(paco_batch_plan **bp, int32_t count, const int64_t *N, paco_dtype dt,
+                                      const char *tune_cache_path, const paco_batch_options *options);
 
 /* Bytes of device workspace paco_execute_batched needs: 8 * sum N[i]. */
 paco_status paco_batch_workspace_size(const paco_batch_plan *bp, size_t *bytes);
@@ -272,8 +323,8 @@ paco_status paco_batch_workspace_size(const paco_batch_plan *bp, size_t *bytes);
  * time (they share the plan's work-queue counters): issue them on one
  * stream.  A completion wait that exceeds its poll limit is counted (see
  * paco_batch_errors) instead of hanging; the launch then still completes,
- * with unspecified results.  The limit is 2^22 polls; the environment
- * variable PACO_BATCH_SPIN_LIMIT at plan creation lowers it (testing). */
+ * with unspecified results.  The limit is 2^22 polls; the option spin_limit
+ * of paco_batch_plan_create_ex sets another (testing). */
 paco_status paco_execute_batched(const paco_batch_plan *bp, const void *in, void *out, void *workspace,
                                  size_t workspace_bytes, void *stream);
 

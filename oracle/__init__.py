@@ -51,7 +51,7 @@ def build(force: bool = False) -> str:
     src = os.path.join(_HERE, "oracle.c")
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
         tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-fPIC", "-shared",
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-fPIC", "-shared", "-pthread",
                                "-o", tmp, src, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
@@ -73,6 +73,8 @@ def _load():
     for name in ("oracle_dft_naive", "oracle_fft_radix2", "oracle_dft", "oracle_idft"):
         getattr(lib, name).restype = ctypes.c_int
         getattr(lib, name).argtypes = [P, P, i64]
+    lib.oracle_fft_radix2_mt.restype = ctypes.c_int
+    lib.oracle_fft_radix2_mt.argtypes = [P, P, i64, ctypes.c_int32]
     lib.oracle_dft_at.restype = ctypes.c_int
     lib.oracle_dft_at.argtypes = [P, i64, P, i64, P]
     lib.oracle_phase1.restype = ctypes.c_int
@@ -183,11 +185,38 @@ def dft_naive(x) -> np.ndarray:
     return y
 
 
-def fft_radix2(x) -> np.ndarray:
+def fft_radix2(x, threads: int = 1) -> np.ndarray:
+    """The recursive radix-2 FFT; threads > 1 runs the same recursion with
+    its top levels spread over that many threads (bit-identical output)."""
     x = _c128(x)
     y = np.empty_like(x)
-    _check(_load().oracle_fft_radix2(_ptr(x), _ptr(y), x.size), "fft_radix2")
+    if threads > 1:
+        _check(_load().oracle_fft_radix2_mt(_ptr(x), _ptr(y), x.size, int(threads)), "fft_radix2_mt")
+    else:
+        _check(_load().oracle_fft_radix2(_ptr(x), _ptr(y), x.size), "fft_radix2")
     return y
+
+
+def cpu_threads() -> int:
+    """Host threads the all-cores oracle uses: the CPUs this process may run
+    on, at most 16 (the host share that goes with one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_model() -> str:
+    """The host CPU's model string (from /proc/cpuinfo, as lscpu prints it)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def dft(x) -> np.ndarray:

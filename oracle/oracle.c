@@ -16,6 +16,7 @@
  * negative exponent, no normalisation.
  */
 #include <math.h>
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -186,17 +187,13 @@ int oracle_dft_at(const double *x, int64_t N, const int64_t *ks, int64_t nk, dou
     return 0;
 }
 
-/* Textbook recursive radix-2 decimation-in-time FFT (N a power of two):
- * the even- and odd-indexed halves are transformed, then combined with
- * w_n^{-k} = w_N^{-k*(N/n)}.  x is read with stride `xs` (in complex items),
- * y is written contiguously. */
-static void fft_r2_rec(const double *x, int64_t xs, double *y, int64_t n, int64_t N, const roots_t *t, int pos)
+/* The butterflies of one level of the radix-2 recursion for k in [k0, k1):
+ * y[k] and y[k + h] (h = n/2) hold the transforms of the even and the odd
+ * samples; they become y[k] +- w_n^{-k} y[k + h], w_n^{-k} = w_N^{-k*(N/n)}. */
+static void fft_r2_combine(double *y, int64_t n, int64_t N, const roots_t *t, int pos, int64_t k0, int64_t k1)
 {
-    if (n == 1) { y[0] = x[0]; y[1] = x[1]; return; }
     int64_t h = n / 2;
-    fft_r2_rec(x, 2 * xs, y, h, N, t, pos);             /* even samples -> y[0..h)   */
-    fft_r2_rec(x + 2 * xs, 2 * xs, y + 2 * h, h, N, t, pos); /* odd samples -> y[h..n) */
-    for (int64_t k = 0; k < h; ++k) {
+    for (int64_t k = k0; k < k1; ++k) {
         double wr, wi;
         roots_get(t, k * (N / n), &wr, &wi);
         if (pos) wi = -wi;                           /* w_n^{+k}: the inverse's roots */
@@ -210,12 +207,138 @@ static void fft_r2_rec(const double *x, int64_t xs, double *y, int64_t n, int64_
     }
 }
 
+/* Textbook recursive radix-2 decimation-in-time FFT (N a power of two):
+ * the even- and odd-indexed halves are transformed, then combined with
+ * w_n^{-k} = w_N^{-k*(N/n)}.  x is read with stride `xs` (in complex items),
+ * y is written contiguously. */
+static void fft_r2_rec(const double *x, int64_t xs, double *y, int64_t n, int64_t N, const roots_t *t, int pos)
+{
+    if (n == 1) { y[0] = x[0]; y[1] = x[1]; return; }
+    int64_t h = n / 2;
+    fft_r2_rec(x, 2 * xs, y, h, N, t, pos);             /* even samples -> y[0..h)   */
+    fft_r2_rec(x + 2 * xs, 2 * xs, y + 2 * h, h, N, t, pos); /* odd samples -> y[h..n) */
+    fft_r2_combine(y, n, N, t, pos, 0, h);
+}
+
 int oracle_fft_radix2(const double *x, double *y, int64_t N)
 {
     if (N < 1 || (N & (N - 1))) return -1;
     roots_t t;
     if (roots_init(&t, N)) return -2;
     fft_r2_rec(x, 1, y, N, N, &t, 0);
+    roots_free(&t);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* all-cores form of the same recursion (CPU baseline timing only)      */
+/* ------------------------------------------------------------------ */
+
+/* The recursion above with its top `depth` levels spread over threads: the
+ * two half transforms of such a level run concurrently and its butterfly
+ * loop is cut into 2^depth independent k ranges.  Every output is formed
+ * by exactly the operations of fft_r2_rec, in the same order, so the result
+ * is bit-identical to oracle_fft_radix2; only the wall time differs. */
+typedef struct {
+    const double *x;
+    int64_t xs;
+    double *y;
+    int64_t n, N;
+    const roots_t *t;
+    int pos, depth;
+    int64_t k0, k1;     /* combine jobs: the k range */
+} r2_job;
+
+static void fft_r2_rec_mt(const double *x, int64_t xs, double *y, int64_t n, int64_t N, const roots_t *t, int pos,
+                          int depth);
+
+static void *r2_half_entry(void *a)
+{
+    r2_job *j = (r2_job *)a;
+    fft_r2_rec_mt(j->x, j->xs, j->y, j->n, j->N, j->t, j->pos, j->depth);
+    return NULL;
+}
+
+static void *r2_combine_entry(void *a)
+{
+    r2_job *j = (r2_job *)a;
+    fft_r2_combine(j->y, j->n, j->N, j->t, j->pos, j->k0, j->k1);
+    return NULL;
+}
+
+static void fft_r2_rec_mt(const double *x, int64_t xs, double *y, int64_t n, int64_t N, const roots_t *t, int pos,
+                          int depth)
+{
+    if (depth <= 0 || n < 2048) { fft_r2_rec(x, xs, y, n, N, t, pos); return; }
+    int64_t h = n / 2;
+    r2_job even = {x, 2 * xs, y, h, N, t, pos, depth - 1, 0, 0};
+    pthread_t th;
+    int spawned = pthread_create(&th, NULL, r2_half_entry, &even) == 0;
+    if (!spawned) r2_half_entry(&even);
+    fft_r2_rec_mt(x + 2 * xs, 2 * xs, y + 2 * h, h, N, t, pos, depth - 1);
+    if (spawned) pthread_join(th, NULL);
+    /* the butterfly loop of this level in 2^depth k ranges */
+    enum { kMaxParts = 64 };
+    int parts = 1 << (depth < 6 ? depth : 6);
+    r2_job cj[kMaxParts];
+    pthread_t ct[kMaxParts];
+    int ok[kMaxParts];
+    for (int i = 0; i < parts; ++i) {
+        r2_job j = {x, xs, y, n, N, t, pos, 0, h * i / parts, h * (i + 1) / parts};
+        cj[i] = j;
+        ok[i] = i > 0 && pthread_create(&ct[i], NULL, r2_combine_entry, &cj[i]) == 0;
+    }
+    r2_combine_entry(&cj[0]);
+    for (int i = 1; i < parts; ++i) {
+        if (ok[i]) pthread_join(ct[i], NULL);
+        else r2_combine_entry(&cj[i]);
+    }
+}
+
+typedef struct {
+    roots_t *t;
+    int64_t r0, r1;
+} roots_job;
+
+static void *roots_fill_entry(void *a)
+{
+    roots_job *j = (roots_job *)a;
+    for (int64_t r = j->r0; r < j->r1; ++r) root_neg(r, j->t->N, &j->t->hi[2 * r], &j->t->hi[2 * r + 1]);
+    return NULL;
+}
+
+/* oracle_fft_radix2 on up to `threads` threads (rounded down to a power of
+ * two, at most 64): the same root table (direct entries filled in
+ * independent ranges) and the recursion above.  Bit-identical output. */
+int oracle_fft_radix2_mt(const double *x, double *y, int64_t N, int32_t threads)
+{
+    if (N < 1 || (N & (N - 1)) || threads < 1) return -1;
+    int depth = 0;
+    while (depth < 6 && (2 << depth) <= threads) ++depth;
+    roots_t t;
+    if (N <= ((int64_t)1 << 22) && depth > 0) {
+        memset(&t, 0, sizeof(t));
+        t.N = N;
+        t.hi = (double *)malloc(sizeof(double) * 2 * (size_t)N);
+        if (!t.hi) return -2;
+        int parts = 1 << depth;
+        roots_job rj[64];
+        pthread_t rt[64];
+        int ok[64];
+        for (int i = 0; i < parts; ++i) {
+            roots_job j = {&t, N * i / parts, N * (i + 1) / parts};
+            rj[i] = j;
+            ok[i] = i > 0 && pthread_create(&rt[i], NULL, roots_fill_entry, &rj[i]) == 0;
+        }
+        roots_fill_entry(&rj[0]);
+        for (int i = 1; i < parts; ++i) {
+            if (ok[i]) pthread_join(rt[i], NULL);
+            else roots_fill_entry(&rj[i]);
+        }
+    } else if (roots_init(&t, N)) {
+        return -2;
+    }
+    fft_r2_rec_mt(x, 1, y, N, N, &t, 0, depth);
     roots_free(&t);
     return 0;
 }

@@ -55,20 +55,7 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     tmp = LIB + ".tmp"
     _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs], verbose)
     os.replace(tmp, LIB)
-    build_probe(hipcc, verbose)
     return LIB
-
-
-def build_probe(hipcc: str, verbose: bool) -> str:
-    """The stand-alone access-pattern tool (probe/access_pattern.hip): times
-    the no-arithmetic load/store pass of each column-tile width; not part of
-    the library."""
-    src = os.path.join(PKG, "probe", "access_pattern.hip")
-    exe = src[:-4]
-    flags = [f for f in HIPCC_FLAGS if f not in ("-shared", "-fPIC")]
-    _run([hipcc, *flags, src, "-o", exe + ".tmp"], verbose)
-    os.replace(exe + ".tmp", exe)
-    return exe
 
 
 if __name__ == "__main__":

@@ -381,6 +381,15 @@ __global__ __launch_bounds__(kBT) void batch_kernel(BatchArgs A)
     }
     __syncthreads();
     if (s_last) {  // everyone else has left: rearm the counters for the next launch
+        // a queue whose ticket never reached its length had tasks no
+        // workgroup ran (no workgroup landed on its XCD): count them
+        for (uint32_t j = tid; j < A.nq; j += kBT) {
+            const uint32_t got = __hip_atomic_load(A.tickets + j * kTicketStride, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t len = A.qbeg[j + 1] - A.qbeg[j];
+            if (got < len) atomicAdd(A.errors, len - got);
+        }
+        __syncthreads();  // every queue checked before its ticket is rearmed
         for (uint32_t j = tid; j < A.njobs; j += kBT) A.done[j] = 0;
         for (uint32_t j = tid; j < A.nq; j += kBT) A.tickets[j * kTicketStride] = 0;
         if (tid == 0) *A.exits = 0;
@@ -490,6 +499,7 @@ struct paco_batch_plan_s {
     int64_t gap = 0;
     int nq = 1;        // work queues
     bool coh = false;  // one queue served by several XCDs: coherent stores
+    paco_batch_options opt{};
     std::string desc;
 };
 
@@ -524,13 +534,12 @@ int resident_workgroups(bool coh, size_t lds)
     return cus * std::max(per, 1);
 }
 
-// Work queues: one per XCD of the device (PACO_BATCH_QUEUES=1 forces one
-// shared queue with device-coherent stores).
-int queue_count()
+// Work queues: one per XCD of the device (the option PACO_BATCH_ONE_QUEUE
+// forces one shared queue with device-coherent stores).
+int queue_count(const paco_batch_options &opt)
 {
     int dev = 0, nx = 0;
-    if (const char *e = std::getenv("PACO_BATCH_QUEUES"))
-        if (e[0] == '1' && e[1] == 0) return 1;
+    if (opt.flags & PACO_BATCH_ONE_QUEUE) return 1;
     if (hipGetDevice(&dev) != hipSuccess) return 1;
     if (hipDeviceGetAttribute(&nx, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess) return 1;
     return (nx >= 1 && nx <= paco::kMaxQueues) ? nx : 1;
@@ -560,7 +569,7 @@ paco_status build_batch(paco_batch_plan_s *P)
     if (!stage_tables(stw, stw_off)) return bfail(PACO_ERR_INVALID_ARG, "internal: stage twiddle layout mismatch");
 
     // ---- queues: transforms to XCDs, largest first onto the least loaded ------
-    int nx = queue_count();
+    int nx = queue_count(P->opt);
     int dev = 0, nxcd = 1;
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&nxcd, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess)
@@ -634,7 +643,7 @@ paco_status build_batch(paco_batch_plan_s *P)
     // per queue: a job's successor is emitted about `gap` tiles after it, a
     // few times the workgroups that serve the queue
     P->gap = 4 * int64_t(resident) / nx;
-    if (const char *g = std::getenv("PACO_BATCH_GAP")) P->gap = std::max<int64_t>(0, std::atoll(g));
+    if (P->opt.flags & PACO_BATCH_SET_GAP) P->gap = P->opt.gap;
 
     // ---- task order, queue by queue ------------------------------------------
     std::vector<BatchTask> tasks;
@@ -732,15 +741,14 @@ paco_status build_batch(paco_batch_plan_s *P)
     A.tickets = reinterpret_cast<uint32_t *>(at(i_tick));
     A.exits = reinterpret_cast<uint32_t *>(at(i_cnt));
     A.errors = reinterpret_cast<uint32_t *>(at(i_cnt) + 256);
-    // testing knob: a tiny poll limit forces the give-up path from the host
+    // option: a tiny poll limit forces the give-up path from the host
     // (every wave still exits; results are then unspecified)
-    A.spin_limit = kSpinLimit;
-    if (const char *e = std::getenv("PACO_BATCH_SPIN_LIMIT")) {
-        const long long v = std::atoll(e);
-        if (v >= 1 && v < (1ll << 31)) A.spin_limit = uint32_t(v);
-    }
+    A.spin_limit = P->opt.spin_limit ? P->opt.spin_limit : kSpinLimit;
     A.done = reinterpret_cast<uint32_t *>(at(i_done));
-    P->grid = int(std::min<int64_t>(int64_t(resident), int64_t(tasks.size())));
+    // at least one workgroup per queue: workgroups are dealt to the XCDs in
+    // turn, so every XCD's queue has a server (the exit check of the kernel
+    // counts any queue left unserved anyway)
+    P->grid = int(std::max<int64_t>(std::min<int64_t>(int64_t(resident), int64_t(tasks.size())), int64_t(nx)));
 
     char buf[256];
     std::snprintf(buf, sizeof buf,
@@ -900,8 +908,19 @@ extern "C" {
 paco_status paco_batch_plan_create(paco_batch_plan **bp, int32_t count, const int64_t *N, paco_dtype dt,
                                    const char *tune_cache_path)
 {
+    return paco_batch_plan_create_ex(bp, count, N, dt, tune_cache_path, nullptr);
+}
+
+paco_status paco_batch_plan_create_ex(paco_batch_plan **bp, int32_t count, const int64_t *N, paco_dtype dt,
+                                      const char *tune_cache_path, const paco_batch_options *options)
+{
     if (!bp) return bfail(PACO_ERR_INVALID_ARG, "plan out-pointer is NULL");
     *bp = nullptr;
+    const paco_batch_options opt = options ? *options : paco_batch_options{};
+    if (opt.flags & ~(PACO_BATCH_NO_TUNE | PACO_BATCH_ONE_QUEUE | PACO_BATCH_SET_GAP))
+        return bfail(PACO_ERR_INVALID_ARG, "unknown batch option flag");
+    if ((opt.flags & PACO_BATCH_SET_GAP) && opt.gap < 0) return bfail(PACO_ERR_INVALID_ARG, "gap must be >= 0");
+    if (opt.spin_limit >= (1u << 31)) return bfail(PACO_ERR_INVALID_ARG, "spin_limit must be below 2^31");
     if (dt == PACO_C64_MFMA_FP16X3 || dt == PACO_C64_MFMA_BF16X3 || dt == PACO_C64_MFMA_BF16X6)
         return bfail(PACO_ERR_UNSUPPORTED, "the batched form runs the FP32 arithmetic only");
     if (dt != PACO_C64) return bfail(PACO_ERR_INVALID_ARG, "unknown dtype");
@@ -909,6 +928,7 @@ paco_status paco_batch_plan_create(paco_batch_plan **bp, int32_t count, const in
     paco_batch_plan_s *P = new (std::nothrow) paco_batch_plan_s();
     if (!P) return bfail(PACO_ERR_ALLOC, "host allocation failed");
     P->count = count;
+    P->opt = opt;
     std::vector<int> ks;
     for (int32_t i = 0; i < count; ++i) {
         const int k = paco::ilog2_pow2(N[i]);
@@ -936,15 +956,14 @@ paco_status paco_batch_plan_create(paco_batch_plan **bp, int32_t count, const in
         free_plan(P);
         return bhip(e, "hipFuncSetAttribute");
     }
-    // per-size plans: cache file, then tuning (unless PACO_BATCH_TUNE=0), else defaults
+    // per-size plans: cache file, then tuning (unless PACO_BATCH_NO_TUNE), else defaults
     std::map<int, SizePlan> plans;
     const std::string key = cache_key();
     if (tune_cache_path) read_cache(tune_cache_path, key, plans);
     std::vector<int> missing;
     for (int k : ks)
         if (!plans.count(k)) missing.push_back(k);
-    const char *te = std::getenv("PACO_BATCH_TUNE");
-    const bool tuning = !(te && te[0] == '0');
+    const bool tuning = !(opt.flags & PACO_BATCH_NO_TUNE);
     if (!missing.empty() && tuning) {
         paco_status st = tune(plans, missing);
         if (st != PACO_OK) {

@@ -167,10 +167,15 @@ namespace {
 
 // Builds the passes and tables of one factorisation N1 x N2 (the forward
 // transform's; paco_plan_create builds a second, N2 x N1, for the inverse).
-paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int32_t b, paco_dtype dt, bool mixed)
+paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int32_t b, paco_dtype dt,
+                        const paco_plan_options &opt)
 {
     if (!plan) return fail(PACO_ERR_INVALID_ARG, "plan out-pointer is NULL");
     *plan = nullptr;
+    const bool mixed = (opt.flags & PACO_PLAN_MIXED) != 0;
+    const bool paper_layout = (opt.flags & PACO_PLAN_PAPER_LAYOUT) != 0;
+    const bool generic = (opt.flags & PACO_PLAN_GENERIC) != 0;
+    const bool no_split = (opt.flags & PACO_PLAN_NO_SPLIT) != 0;
     paco_status st = validate_impl(N1, N2, p, b, dt, mixed);
     if (st != PACO_OK) return st;
 
@@ -256,13 +261,10 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
         q.ncols = ncols;
         q.log2n = log2n;
         q.log2T = paco::choose_log2T(log2n, ncols);
-        if (const char *nf = std::getenv("PACO_NO_FAST")) q.no_fast = nf[0] == '1';
+        q.no_fast = generic ? 1 : 0;
         q.groups = 1;
-        // tuning knob: columns per workgroup for long single-group transforms
-        if (const char *ev = std::getenv("PACO_LOG2T_LONG")) {
-            const int want = std::atoi(ev);
-            if (log2n >= 10 && want >= 0 && (int64_t(1) << want) <= ncols) q.log2T = want;
-        }
+        // option: columns per workgroup for long single-group transforms
+        if (opt.cols_long > 0 && log2n >= 10 && opt.cols_long <= ncols) q.log2T = ilog2_exact(opt.cols_long);
         q.prec = int32_t(dt);  // paco_dtype values are the butterfly arithmetic codes
         q.stw = d_stw + stw_off[log2n];
         q.tw = d_tw;
@@ -346,13 +348,12 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
         P->phase3.push_back(A);
         P->phase3.push_back(B);
     }
-    // Column groups for n >= 2^10 (tuning knobs PACO_GROUPS1 / PACO_GROUPS3):
+    // Column groups for n >= 2^10 (options groups1 / groups3):
     // 1 = one LDS group of T columns; 2 = two groups of T/2 (half the LDS, two
     // workgroups per CU); 3 = two groups of T, a tile twice as wide (512
     // threads with 64 items each).
-    auto pick = [](LocalPass &q, const char *env, int dflt) {
-        int g = dflt;
-        if (const char *e = std::getenv(env)) g = e[0] - '0';
+    auto pick = [](LocalPass &q, int32_t want, int dflt) {
+        int g = want > 0 ? want : dflt;
         if (g < 1 || g > 3 || q.log2n < 10 || q.log2T < 1 || q.no_fast) g = 1;
         // split MFMA forms: no wide tile; 16^s-point passes use the one-group
         // kernel that keeps the MFMA operand layout throughout
@@ -368,9 +369,9 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
         }
     };
     const LocalPass phase1_base = P->phase1[0];
-    for (auto &q : P->phase1) pick(q, "PACO_GROUPS1", q.log2n >= 12 ? 2 : 1);
+    for (auto &q : P->phase1) pick(q, opt.groups1, q.log2n >= 12 ? 2 : 1);
     const LocalPass phase3_base = P->phase3[0];
-    for (auto &q : P->phase3) pick(q, "PACO_GROUPS3", q.log2n >= 12 ? 3 : 1);
+    for (auto &q : P->phase3) pick(q, opt.groups3, q.log2n >= 12 ? 3 : 1);
     // generic passes of the split MFMA forms: at most 512 threads per tile
     for (auto *ph : {&P->phase1, &P->phase3})
         for (auto &q : *ph)
@@ -379,14 +380,13 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
                 --q.log2T;
     // ---- fused pipeline: Phase I writes the packed slab transposed --------
     {
-        const char *lay = std::getenv("PACO_LAYOUT");
-        const bool want = !(lay && std::strcmp(lay, "paper") == 0);
+        const bool want = !paper_layout;
         LocalPass q = phase1_base;
         q.out_tr = 1;
         q.out_t = 0;
         q.out_ell = 0;
         q.out_s = 0;
-        pick(q, "PACO_GROUPS1", q.log2n >= 12 ? 2 : 1);
+        pick(q, opt.groups1, q.log2n >= 12 ? 2 : 1);
         if (q.prec != 0 && q.log2n >= 4 && q.log2n % 4 == 0)  // the operand-layout tile's own width
             q.log2T = paco::mf_log2T(q.log2n, 2);
         if (want && b1 == 0 && N1 >= paco::kMidTile && N2 >= paco::kMidTile && !q.no_fast &&
@@ -408,7 +408,7 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
         q.top_hi = d_thi;
         q.top_lo = d_tlo;
         q.top_cw = d_tcw;
-        pick(q, "PACO_GROUPS3", q.log2n >= 12 ? 3 : 1);
+        pick(q, opt.groups3, q.log2n >= 12 ? 3 : 1);
         if (!q.no_fast && paco::local_fft_fast_mode(q) == 3) {
             P->two_pass = true;
             P->phase3_two = q;
@@ -440,7 +440,7 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
     P->mid.log2Lo = P->lLo;
     P->mid.twiddle = 1;
 
-    // ---- split form (FP32, N1 = 2^12; knob PACO_SPLIT=0 turns it off) ------
+    // ---- split form (FP32, N1 = 2^12 .. 2^14; option PACO_PLAN_NO_SPLIT) ----
     // Measured per transform (MI355X): with plain stores in both forms,
     // N2 = 2^10 49 against 60 us for the packed form, 2^12 183 against
     // 197 us, 2^13 421 against 438 us, 2^14 944 against 926 us; with the
@@ -448,8 +448,7 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
     // 914 against 922 us (b = 4) and 947 against 953 us (b = 2).  Larger N2
     // (up to 2^16) was not measured: N2 <= 2^14.
     {
-        const char *sp = std::getenv("PACO_SPLIT");
-        const bool want = !(sp && sp[0] == '0');
+        const bool want = !no_split && !paper_layout && !generic;
         // N1 = 2^13, 2^14: Phase I takes two on-chip passes there, so the split
         // form also saves one HBM pass (pass 2 runs its M-point transforms in
         // three stages; see split.hip)
@@ -524,13 +523,20 @@ extern "C" {
 namespace {
 
 paco_status create_with_inverse(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int32_t b, paco_dtype dt,
-                                bool mixed)
+                                const paco_plan_options &opt)
 {
-    paco_status st = create_impl(plan, N1, N2, p, b, dt, mixed);
+    if (plan) *plan = nullptr;
+    if (opt.flags & ~(PACO_PLAN_MIXED | PACO_PLAN_PAPER_LAYOUT | PACO_PLAN_NO_SPLIT | PACO_PLAN_GENERIC))
+        return fail(PACO_ERR_INVALID_ARG, "unknown plan option flag");
+    if (opt.groups1 < 0 || opt.groups1 > 3 || opt.groups3 < 0 || opt.groups3 > 3)
+        return fail(PACO_ERR_INVALID_ARG, "groups1 / groups3 must be 0 (default), 1, 2 or 3");
+    if (opt.cols_long < 0 || (opt.cols_long > 0 && ilog2_exact(opt.cols_long) < 0))
+        return fail(PACO_ERR_INVALID_ARG, "cols_long must be 0 (default) or a power of two");
+    paco_status st = create_impl(plan, N1, N2, p, b, dt, opt);
     if (st != PACO_OK || N1 == N2) return st;  // square: the inverse reuses the forward passes
     const std::string note = g_last_error;
     paco_plan *inv = nullptr;
-    st = create_impl(&inv, N2, N1, p, b, dt, mixed);
+    st = create_impl(&inv, N2, N1, p, b, dt, opt);
     if (st != PACO_OK) {
         // the forward plan stands; paco_execute_inverse reports the reason
         (*plan)->inv_error = "inverse (N2 x N1 passes) unavailable: " + g_last_error;
@@ -549,13 +555,21 @@ extern "C" {
 paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int32_t b,
                              paco_dtype dt)
 {
-    return create_with_inverse(plan, N1, N2, p, b, dt, false);
+    return create_with_inverse(plan, N1, N2, p, b, dt, paco_plan_options{});
 }
 
 paco_status paco_plan_create_mixed(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int32_t b,
                                    paco_dtype dt)
 {
-    return create_with_inverse(plan, N1, N2, p, b, dt, true);
+    paco_plan_options o{};
+    o.flags = PACO_PLAN_MIXED;
+    return create_with_inverse(plan, N1, N2, p, b, dt, o);
+}
+
+paco_status paco_plan_create_ex(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int32_t b, paco_dtype dt,
+                                const paco_plan_options *options)
+{
+    return create_with_inverse(plan, N1, N2, p, b, dt, options ? *options : paco_plan_options{});
 }
 
 paco_status paco_plan_workspace_size(const paco_plan *plan, size_t *bytes)

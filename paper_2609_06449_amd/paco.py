@@ -31,13 +31,35 @@ PACO_PACKED = 2
 PACO_TWO_PASS = 4
 PACO_SPLIT = 8
 
+# paco_plan_options.flags
+PACO_PLAN_MIXED = 1
+PACO_PLAN_PAPER_LAYOUT = 2
+PACO_PLAN_NO_SPLIT = 4
+PACO_PLAN_GENERIC = 8
+
+# paco_batch_options.flags
+PACO_BATCH_NO_TUNE = 1
+PACO_BATCH_ONE_QUEUE = 2
+PACO_BATCH_SET_GAP = 4
+
+class PlanOptions(ctypes.Structure):
+    """paco_plan_options (include/paco.h): every field 0 = the default."""
+    _fields_ = [("flags", ctypes.c_uint32), ("groups1", ctypes.c_int32), ("groups3", ctypes.c_int32),
+                ("cols_long", ctypes.c_int32)]
+
+
+class BatchOptions(ctypes.Structure):
+    """paco_batch_options (include/paco.h): every field 0 = the default."""
+    _fields_ = [("flags", ctypes.c_uint32), ("spin_limit", ctypes.c_uint32), ("gap", ctypes.c_int64)]
+
 # every symbol include/paco.h declares
 EXPORTED = (
     "paco_plan_validate", "paco_plan_create", "paco_plan_validate_mixed", "paco_plan_create_mixed",
-    "paco_plan_workspace_size", "paco_execute",
+    "paco_plan_create_ex", "paco_plan_workspace_size", "paco_execute",
     "paco_execute_stage", "paco_execute_inverse", "paco_execute_two_pass", "paco_plan_has_two_pass", "paco_plan_has_split", "paco_plan_describe",
     "paco_plan_destroy", "paco_status_string",
-    "paco_last_error", "paco_batch_plan_create", "paco_batch_workspace_size", "paco_execute_batched",
+    "paco_last_error", "paco_batch_plan_create", "paco_batch_plan_create_ex", "paco_batch_workspace_size",
+    "paco_execute_batched",
     "paco_batch_plan_describe", "paco_batch_errors", "paco_batch_plan_destroy",
 )
 
@@ -67,6 +89,7 @@ def _load() -> ctypes.CDLL:
         "paco_plan_create": (st, [ctypes.POINTER(P), i64, i64, i64, i32, st]),
         "paco_plan_validate_mixed": (st, [i64, i64, i64, i32, st]),
         "paco_plan_create_mixed": (st, [ctypes.POINTER(P), i64, i64, i64, i32, st]),
+        "paco_plan_create_ex": (st, [ctypes.POINTER(P), i64, i64, i64, i32, st, ctypes.POINTER(PlanOptions)]),
         "paco_plan_workspace_size": (st, [P, ctypes.POINTER(sz)]),
         "paco_execute": (st, [P, P, P, P, sz, P]),
         "paco_execute_stage": (st, [P, st, st, P, P, P]),
@@ -79,6 +102,8 @@ def _load() -> ctypes.CDLL:
         "paco_status_string": (ctypes.c_char_p, [st]),
         "paco_last_error": (ctypes.c_char_p, []),
         "paco_batch_plan_create": (st, [ctypes.POINTER(P), i32, ctypes.POINTER(i64), st, ctypes.c_char_p]),
+        "paco_batch_plan_create_ex": (st, [ctypes.POINTER(P), i32, ctypes.POINTER(i64), st, ctypes.c_char_p,
+                                           ctypes.POINTER(BatchOptions)]),
         "paco_batch_workspace_size": (st, [P, ctypes.POINTER(sz)]),
         "paco_execute_batched": (st, [P, P, P, P, sz, P]),
         "paco_batch_plan_describe": (st, [P, i32, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
@@ -134,6 +159,24 @@ def paco_plan_create_mixed(N1: int, N2: int, p: int, b: int, dt: int = PACO_C64)
     return h.value
 
 
+def paco_plan_create_ex(N1: int, N2: int, p: int, b: int, dt: int = PACO_C64, flags: int = 0, groups1: int = 0,
+                        groups3: int = 0, cols_long: int = 0) -> int:
+    opt = PlanOptions(flags, groups1, groups3, cols_long)
+    h = ctypes.c_void_p()
+    _check(_lib.paco_plan_create_ex(ctypes.byref(h), N1, N2, p, b, dt, ctypes.byref(opt)), "paco_plan_create_ex")
+    return h.value
+
+
+def paco_plan_create_ex_status(N1: int, N2: int, p: int, b: int, dt: int = PACO_C64, **fields) -> int:
+    """Status code only (no exception); destroys the plan when one was made."""
+    opt = PlanOptions(**fields)
+    h = ctypes.c_void_p()
+    st = int(_lib.paco_plan_create_ex(ctypes.byref(h), N1, N2, p, b, dt, ctypes.byref(opt)))
+    if h.value:
+        _lib.paco_plan_destroy(h)
+    return st
+
+
 def paco_plan_workspace_size(plan: int) -> int:
     n = ctypes.c_size_t()
     _check(_lib.paco_plan_workspace_size(plan, ctypes.byref(n)), "paco_plan_workspace_size")
@@ -182,9 +225,16 @@ def paco_plan_destroy(plan: int):
 class Plan:
     """Owns one paco_plan handle (created on the current HIP device)."""
 
-    def __init__(self, N1: int, N2: int, p: int, b: int, dt: int = PACO_C64, mixed: bool = False):
+    def __init__(self, N1: int, N2: int, p: int, b: int, dt: int = PACO_C64, mixed: bool = False, flags: int = 0,
+                 groups1: int = 0, groups3: int = 0, cols_long: int = 0):
+        """flags, groups1, groups3, cols_long: paco_plan_options (mixed adds
+        PACO_PLAN_MIXED); all defaults: paco_plan_create."""
         self.N1, self.N2, self.p, self.b, self.dt = N1, N2, p, b, dt
-        self.handle = (paco_plan_create_mixed if mixed else paco_plan_create)(N1, N2, p, b, dt)
+        flags |= PACO_PLAN_MIXED if mixed else 0
+        if flags or groups1 or groups3 or cols_long:
+            self.handle = paco_plan_create_ex(N1, N2, p, b, dt, flags, groups1, groups3, cols_long)
+        else:
+            self.handle = paco_plan_create(N1, N2, p, b, dt)
         self.workspace_bytes = paco_plan_workspace_size(self.handle)
         self.launches, self.description = paco_plan_describe(self.handle)
         self.has_two_pass = paco_plan_has_two_pass(self.handle)
@@ -222,6 +272,17 @@ def paco_batch_plan_create(sizes, dt: int = PACO_C64, tune_cache_path=None) -> i
     h = ctypes.c_void_p()
     path = tune_cache_path.encode() if tune_cache_path is not None else None
     _check(_lib.paco_batch_plan_create(ctypes.byref(h), len(sizes), arr, dt, path), "paco_batch_plan_create")
+    return h.value
+
+
+def paco_batch_plan_create_ex(sizes, dt: int = PACO_C64, tune_cache_path=None, flags: int = 0,
+                              spin_limit: int = 0, gap: int = 0) -> int:
+    arr = (ctypes.c_int64 * len(sizes))(*[int(n) for n in sizes])
+    h = ctypes.c_void_p()
+    path = tune_cache_path.encode() if tune_cache_path is not None else None
+    opt = BatchOptions(flags, spin_limit, gap)
+    _check(_lib.paco_batch_plan_create_ex(ctypes.byref(h), len(sizes), arr, dt, path, ctypes.byref(opt)),
+           "paco_batch_plan_create_ex")
     return h.value
 
 
@@ -268,13 +329,19 @@ class BatchPlan:
     """Owns one paco_batch_plan handle: transform i has sizes[i] items, packed
     back to back (offsets = running sums)."""
 
-    def __init__(self, sizes, dt: int = PACO_C64, tune_cache_path=None):
+    def __init__(self, sizes, dt: int = PACO_C64, tune_cache_path=None, flags: int = 0, spin_limit: int = 0,
+                 gap: int = 0):
+        """flags, spin_limit, gap: paco_batch_options; all defaults:
+        paco_batch_plan_create."""
         self.sizes = [int(n) for n in sizes]
         self.offsets = [0]
         for n in self.sizes:
             self.offsets.append(self.offsets[-1] + n)
         self.total = self.offsets[-1]
-        self.handle = paco_batch_plan_create(self.sizes, dt, tune_cache_path)
+        if flags or spin_limit or gap:
+            self.handle = paco_batch_plan_create_ex(self.sizes, dt, tune_cache_path, flags, spin_limit, gap)
+        else:
+            self.handle = paco_batch_plan_create(self.sizes, dt, tune_cache_path)
         self.workspace_bytes = paco_batch_workspace_size(self.handle)
         _, self.description = paco_batch_plan_describe(self.handle, -1)
 

@@ -57,3 +57,17 @@ def test_traffic_from_scales_by_the_copy(tmp_path, monkeypatch):
 def test_short_kernel_names():
     n = "void paco::(anonymous namespace)::middle_packed2_kernel<false, true>(paco::MiddlePass)"
     assert bench.short_kernel_name(n) == "middle_packed2_kernel<false,true>"
+
+
+def test_cpu_baseline_record():
+    # one thread and all cores, the same output bits, the host named
+    import numpy as np
+
+    x = (np.random.default_rng(3).standard_normal((1 << 14, 2)) @ [1, 1j]).astype(np.complex64)
+    ref, rec = bench.cpu_baseline(x, 1 << 14, budget_s=0.2)
+    assert rec["kind"] == "oracle" and rec["unit"] == "GFLOP/s"
+    assert rec["cores"] == rec["threads_all"]["threads"] >= 1
+    assert rec["threads_1"]["threads"] == 1 and rec["threads_1"]["runs"] >= 3
+    assert rec["value"] == rec["threads_all"]["value"] > 0
+    assert rec["nproc"] >= 1 and rec["cpu_model"]
+    assert ref.dtype == np.complex128 and ref.shape == (1 << 14,)

@@ -129,3 +129,32 @@ def test_batch_plan_rejects_before_any_hip_call(sizes, status):
 
 def test_batch_plan_rejects_unknown_dtype():
     assert paco.paco_batch_plan_create_status([256], dt=7) == paco.PACO_ERR_INVALID_ARG
+
+
+def test_plan_options_are_checked_before_any_device_call():
+    # option errors come back from the host-side checks (no GPU here)
+    bad = [dict(flags=1 << 7), dict(groups1=4), dict(groups3=-1), dict(cols_long=3), dict(cols_long=-2)]
+    for fields in bad:
+        assert paco.paco_plan_create_ex_status(64, 64, 4, 4, **fields) == paco.PACO_ERR_INVALID_ARG, fields
+    # the contract is still checked first for good options
+    assert paco.paco_plan_create_ex_status(64, 32, 4, 4) == paco.PACO_ERR_NOT_POWER_OF_B
+    assert paco.paco_plan_create_ex_status(64, 32, 3, 4, flags=paco.PACO_PLAN_MIXED) == paco.PACO_ERR_DIVISIBILITY
+
+
+def test_batch_options_are_checked_before_any_device_call():
+    lib = paco.lib()
+    arr = (ctypes.c_int64 * 2)(256, 4096)
+    h = ctypes.c_void_p()
+    for opt in (paco.BatchOptions(1 << 5, 0, 0), paco.BatchOptions(paco.PACO_BATCH_SET_GAP, 0, -1),
+                paco.BatchOptions(0, 1 << 31, 0)):
+        st = lib.paco_batch_plan_create_ex(ctypes.byref(h), 2, arr, paco.PACO_C64, None, ctypes.byref(opt))
+        assert st == paco.PACO_ERR_INVALID_ARG and not h.value
+
+
+def test_no_plan_reads_the_environment():
+    # plans depend on their arguments and options only (PACO_LOG=1 just prints)
+    import glob
+    for path in glob.glob(os.path.join(ROOT, "paper_2609_06449_amd", "csrc", "*")):
+        text = open(path).read()
+        names = re.findall(r'getenv\("(\w+)"\)', text)
+        assert set(names) <= {"PACO_LOG"}, (path, names)

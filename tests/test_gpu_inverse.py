@@ -79,7 +79,6 @@ def test_inverse_full_size_round_trip():
 
 
 def test_inverse_in_place_and_paper_layout():
-    import os
     N1, N2, p, b = 256, 1024, 8, 4
     y = inputs.normal(N1 * N2, seed=32)
     plan = paco.Plan(N1, N2, p, b)
@@ -87,11 +86,7 @@ def test_inverse_in_place_and_paper_layout():
     buf = _dev(y)
     _call(plan.execute_inverse, plan, buf, out=buf)
     assert np.array_equal(buf.cpu().numpy().view(np.uint64), ref.view(np.uint64))
-    os.environ["PACO_LAYOUT"] = "paper"
-    try:
-        paper = paco.Plan(N1, N2, p, b)
-    finally:
-        del os.environ["PACO_LAYOUT"]
+    paper = paco.Plan(N1, N2, p, b, flags=paco.PACO_PLAN_PAPER_LAYOUT)
     got = _call(paper.execute_inverse, paper, _dev(y)).cpu().numpy()
     assert oracle.rel_l2(got, oracle.idft(y)) <= TOL
 

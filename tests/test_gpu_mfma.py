@@ -83,17 +83,10 @@ def test_mfma_forms_precision_configs(form, N1, N2, p, b):
 @pytest.mark.parametrize("N1,N2,p,b", [(4096, 4096, 64, 16), (256, 1024, 4, 4)])
 def test_mfma_fast_and_generic_kernels_agree(form, N1, N2, p, b):
     # the same split arithmetic in the fast and the descriptor-driven kernels
-    import os
     dt, _ = FORMS[form]
     x = torch.from_numpy(inputs.loguniform(N1 * N2, seed=9)).to("cuda")
-    os.environ["PACO_LAYOUT"] = "paper"
-    try:
-        fast = paco.Plan(N1, N2, p, b, dt)
-        os.environ["PACO_NO_FAST"] = "1"
-        generic = paco.Plan(N1, N2, p, b, dt)
-    finally:
-        os.environ.pop("PACO_NO_FAST", None)
-        del os.environ["PACO_LAYOUT"]
+    fast = paco.Plan(N1, N2, p, b, dt, flags=paco.PACO_PLAN_PAPER_LAYOUT)
+    generic = paco.Plan(N1, N2, p, b, dt, flags=paco.PACO_PLAN_PAPER_LAYOUT | paco.PACO_PLAN_GENERIC)
     assert "(fast)" in fast.description and "(fast)" not in generic.description
     a, g = _run(fast, x), _run(generic, x)
     assert np.array_equal(a.view(np.uint64), g.view(np.uint64))

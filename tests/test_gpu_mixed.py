@@ -3,9 +3,9 @@ that are not powers of b, outside the paper's preconditions (section 5,
 Limitations).  The digit reversal reads (b, ..., b, r) and is checked
 against the oracle's, whose mixed-radix reading is pinned in test_perm.py:
 end to end against the FP64 DFT, stage by stage against the oracle's stage
-references (the bare permutation bit for bit), in both layouts, the inverse,
-and the 2^28 shapes with their literal bases b = 16 and b = 8."""
-import os
+references (the bare permutation bit for bit), in both layouts, and the
+inverse.  The 2^28 shapes with their literal bases b = 16 and b = 8 are
+compared output by output in test_gpu_full_size.py."""
 
 import numpy as np
 import pytest
@@ -38,12 +38,8 @@ def _call(fn, plan, xd, out=None):
 
 
 def _plan(N1, N2, p, b, layout=None, dt=paco.PACO_C64):
-    if layout:
-        os.environ["PACO_LAYOUT"] = layout
-    try:
-        return paco.Plan(N1, N2, p, b, dt, mixed=True)
-    finally:
-        os.environ.pop("PACO_LAYOUT", None)
+    flags = paco.PACO_PLAN_PAPER_LAYOUT if layout == "paper" else 0
+    return paco.Plan(N1, N2, p, b, dt, mixed=True, flags=flags)
 
 
 SHAPES = [(32, 64, 4, 16), (64, 32, 4, 16), (128, 512, 8, 8), (8, 8, 2, 4), (2, 16, 2, 4), (4096, 2048, 16, 16),
@@ -116,32 +112,6 @@ def test_mixed_plans_need_the_mixed_entry_point():
     a = _call(strict.execute, strict, x).cpu().numpy()
     c = _call(mixed.execute, mixed, x).cpu().numpy()
     assert np.array_equal(a.view(np.uint64), c.view(np.uint64))
-
-
-@pytest.mark.parametrize("name", ["n2p28_16384x16384_b16", "n2p28_8192x32768_b8"])
-def test_mixed_2p28_literal_bases(name):
-    # N = 2^28 with b = 16 (2^14 x 2^14, p = 256) and b = 8 (2^13 x 2^15,
-    # p = 128): round trip through the inverse, Parseval, sampled outputs
-    cfg = inputs.CONFIGS[name]
-    N1, N2, p, b = cfg["N1"], cfg["N2"], cfg["p"], cfg["b"]
-    N = N1 * N2
-    x = inputs.make(cfg["gen"], N, cfg["seed"])
-    plan = _plan(N1, N2, p, b)
-    print(f"{name}: {plan.description}", flush=True)
-    xd = _dev(x)
-    yd = _call(plan.execute, plan, xd)
-    back = _call(plan.execute_inverse, plan, yd)
-    num = torch.linalg.vector_norm((back - xd).to(torch.complex128))
-    rt = float(num / torch.linalg.vector_norm(xd.to(torch.complex128)))
-    del back
-    print(f"{name} round-trip rel_l2={rt:.3e}", flush=True)
-    assert rt <= 2 * TOL
-    y = yd.cpu().numpy()
-    ex = float(np.sum(np.abs(x.astype(np.complex128)) ** 2))
-    ey = float(np.sum(np.abs(y.astype(np.complex128)) ** 2))
-    assert abs(ey - N * ex) <= 2e-6 * N * ex
-    ks = np.array([0, 1, N1 - 1, N1, N // 2 + 3, N - 1])
-    assert np.max(np.abs(y[ks] - oracle.dft_at(x, ks))) < 1e-5 * np.sqrt(ex)
 
 
 @pytest.mark.parametrize("dt,tol", [(paco.PACO_C64_MFMA_FP16X3, 1e-6), (paco.PACO_C64_MFMA_BF16X3, 3e-5),

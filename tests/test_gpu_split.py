@@ -6,7 +6,6 @@ redistribution and top-level twiddle.  Checked against the FP64 oracle: the
 whole transform, each pass on its own (pass 1 against the oracle's 16-point
 DFTs, pass 2 against the oracle's Phase II output), the stage hooks
 composing to paco_execute bit for bit, and the entry-point checks."""
-import os
 
 import numpy as np
 import pytest
@@ -46,11 +45,7 @@ def _stage(plan, stage, src, flags):
 
 
 def _packed_plan(N1, N2, p, b):
-    os.environ["PACO_SPLIT"] = "0"
-    try:
-        return paco.Plan(N1, N2, p, b)
-    finally:
-        del os.environ["PACO_SPLIT"]
+    return paco.Plan(N1, N2, p, b, flags=paco.PACO_PLAN_NO_SPLIT)
 
 
 def _split_buffer(x, N1, N2):
@@ -239,11 +234,11 @@ def test_which_plans_split():
     assert not paco.Plan(16384, 32, 2, 2).has_split           # N2 below 64
     assert not paco.Plan(16384, 64, 4, 4, paco.PACO_C64_MFMA_FP16X3).has_split
     assert not paco.Plan(4096, 256, 16, 16, paco.PACO_C64_MFMA_BF16X3).has_split  # FP32 only
-    os.environ["PACO_LAYOUT"] = "paper"
-    try:
-        assert not paco.Plan(4096, 256, 16, 16).has_split     # the paper's layouts: no fused pipeline
-    finally:
-        del os.environ["PACO_LAYOUT"]
+    paper = paco.PACO_PLAN_PAPER_LAYOUT
+    assert not paco.Plan(4096, 256, 16, 16, flags=paper).has_split   # the paper's layouts: no fused pipeline
+    assert not paco.Plan(16384, 64, 4, 4, flags=paper).has_split      # nor the long-column split form
+    assert not paco.Plan(8192, 1 << 11, 8, 8, flags=paper).has_split
+    assert not paco.Plan(4096, 4096, 64, 16, flags=paco.PACO_PLAN_GENERIC).has_split
 
 
 def test_split_flag_errors():

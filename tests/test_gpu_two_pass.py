@@ -86,13 +86,7 @@ def test_two_pass_in_place_and_deterministic():
     (16, 16, 2, 4, paco.PACO_C64, None),                   # slabs below one 64-item tile: not fused
 ])
 def test_two_pass_unsupported_plans(N1, N2, p, b, dt, layout):
-    import os
-    if layout:
-        os.environ["PACO_LAYOUT"] = layout
-    try:
-        plan = paco.Plan(N1, N2, p, b, dt)
-    finally:
-        os.environ.pop("PACO_LAYOUT", None)
+    plan = paco.Plan(N1, N2, p, b, dt, flags=paco.PACO_PLAN_PAPER_LAYOUT if layout == "paper" else 0)
     assert not plan.has_two_pass
     buf = torch.empty(N1 * N2, dtype=torch.complex64, device="cuda")
     ws = torch.empty_like(buf)
@@ -152,16 +146,11 @@ def test_two_pass_phase3_stage(N1, N2, p, b):
 
 
 def test_packed_stage3_flag_errors():
-    import os
     lib = paco.lib()
     s = _stream()
     buf = torch.empty(4096, dtype=torch.complex64, device="cuda")
     out = torch.empty_like(buf)
-    os.environ["PACO_LAYOUT"] = "paper"
-    try:
-        paper = paco.Plan(64, 64, 4, 4)
-    finally:
-        del os.environ["PACO_LAYOUT"]
+    paper = paco.Plan(64, 64, 4, 4, flags=paco.PACO_PLAN_PAPER_LAYOUT)
     assert lib.paco_execute_stage(paper.handle, 3, paco.PACO_PACKED, buf.data_ptr(), out.data_ptr(), s) == \
         paco.PACO_ERR_UNSUPPORTED
     fused = paco.Plan(64, 64, 4, 4)

@@ -139,3 +139,19 @@ def test_idft_is_not_the_forward_transform():
     # a sign slip would make idft(y) = dft(y)/N; these differ for N >= 3
     y = _rand(64)
     assert oracle.rel_l2(oracle.idft(y), oracle.dft(y) / 64) > 0.5
+
+
+@pytest.mark.parametrize("N,threads", [(1 << 11, 2), (1 << 16, 4), (1 << 20, 8), (1 << 23, 16), (1 << 12, 3)])
+def test_threaded_radix2_is_bit_identical(N, threads):
+    # the all-cores form (CPU baseline) runs the same recursion over threads:
+    # every output is the same FP64 value as the one-thread oracle's; 2^23
+    # takes the two-level root table
+    x = np.random.default_rng(N).standard_normal((N, 2)).view(np.complex128).ravel()
+    one = oracle.fft_radix2(x)
+    many = oracle.fft_radix2(x, threads=threads)
+    assert np.array_equal(one.view(np.uint64), many.view(np.uint64))
+
+
+def test_cpu_threads_and_model():
+    assert 1 <= oracle.cpu_threads() <= 16
+    assert isinstance(oracle.cpu_model(), str) and oracle.cpu_model()

@@ -1,7 +1,8 @@
 """The C oracle built with the host address and undefined-behaviour
 sanitizers (gcc) and driven through every entry point, including the
-two-level root table above 2^22 points: any out-of-bounds access, leak or
-undefined operation aborts the driver."""
+two-level root table above 2^22 points and the threaded form of the radix-2
+recursion: any out-of-bounds access, leak or undefined operation aborts the
+driver."""
 import os
 import shutil
 import subprocess
@@ -16,11 +17,13 @@ DRIVER = r"""
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
+#include <string.h>
 int64_t oracle_digit_reverse(int64_t i, int64_t b, int32_t ell);
 int64_t oracle_digit_reverse_n(int64_t i, int64_t b, int64_t n);
 int oracle_dft_naive(const double *x, double *y, int64_t N);
 int oracle_dft_at(const double *x, int64_t N, const int64_t *ks, int64_t nk, double *y);
 int oracle_fft_radix2(const double *x, double *y, int64_t N);
+int oracle_fft_radix2_mt(const double *x, double *y, int64_t N, int32_t threads);
 int oracle_dft(const double *x, double *y, int64_t N);
 int oracle_idft(const double *y, double *x, int64_t N);
 int oracle_phase1(const double *x, int64_t N1, int64_t N2, int64_t b, const int64_t *cols, int64_t ncols, double *out);
@@ -49,6 +52,19 @@ int main(void) {
         if ((N & (N - 1)) == 0) rc |= oracle_fft_radix2(x, y, N);
         if (N <= 64) rc |= oracle_dft_naive(x, y, N);
         free(x); free(y); free(z);
+    }
+    {   /* the all-cores form: threads over the top levels, bit-identical */
+        const int64_t ns[] = {2048, 1 << 15};
+        const int32_t th[] = {2, 4, 8, 3};
+        for (int s = 0; s < 2; ++s)
+            for (int k = 0; k < 4; ++k) {
+                double *x = vec(ns[s]), *y = vec(ns[s]), *z = vec(ns[s]);
+                rc |= oracle_fft_radix2(x, y, ns[s]);
+                rc |= oracle_fft_radix2_mt(x, z, ns[s], th[k]);
+                rc |= memcmp(y, z, sizeof(double) * 2 * (size_t)ns[s]) != 0;
+                free(x); free(y); free(z);
+            }
+        rc |= oracle_fft_radix2_mt(NULL, NULL, 12, 4) != -1;  /* not a power of two */
     }
     {   /* the two-level root table: N above 2^22 */
         int64_t N = (int64_t)1 << 23, ks[3] = {0, 1, N - 1};
@@ -82,7 +98,7 @@ def test_oracle_under_address_and_ub_sanitizers(tmp_path):
     drv.write_text(DRIVER)
     exe = tmp_path / "oracle_asan"
     cc = ["gcc", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
-          "-fno-omit-frame-pointer", str(drv), ORACLE_C, "-lm", "-o", str(exe)]
+          "-fno-omit-frame-pointer", "-pthread", str(drv), ORACLE_C, "-lm", "-o", str(exe)]
     r = subprocess.run(cc, capture_output=True, text=True)
     if r.returncode != 0 and "sanitizer" in r.stderr.lower():
         pytest.skip("sanitizer runtime not available: " + r.stderr[-300:])
