@@ -41,7 +41,7 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "FFT GFLOP/s (5N·log2N/t) + % HBM roofline, N=2^24 c64; MFMA-split vs FP32"
 WORKLOAD = dict(name="2^24 as 4096 x 4096", N1=4096, N2=4096, p=64, b=16, gen="normal", seed=2)
 KERNEL_SOURCES = ["paper_2609_06449_amd/csrc/" + f for f in ("local_fft.hip", "middle.hip", "stages.h", "middle_dev.h",
-                                                                  "paco_internal.h", "split.hip")]
+                                                                  "paco_internal.h", "split.hip", "sym.hip")]
 
 
 def kernel_hash() -> str:
@@ -431,9 +431,11 @@ def main():
 
     # ---- per-phase durations with HIP events on the same stream ------------
     # the same launches paco_execute makes, one phase per call (split form:
-    # its pass 1 and pass 2 in place of Phases I and II)
+    # its pass 1 and pass 2 in place of Phases I and II; symmetric split
+    # form: its three passes)
     fused = plan.description.startswith("fused")
     fl = paco.PACO_SPLIT if plan.has_split else (paco.PACO_PACKED if fused else 0)
+    fl3 = paco.PACO_SPLIT if plan.has_split == 2 else 0
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     for i in range(args.steps):
         e = ev[i]
@@ -442,7 +444,7 @@ def main():
         e[1].record(stream)
         plan.execute_stage(2, ws.data_ptr(), out.data_ptr(), sh, fl)
         e[2].record(stream)
-        plan.execute_stage(3, out.data_ptr(), out.data_ptr(), sh)
+        plan.execute_stage(3, out.data_ptr(), out.data_ptr(), sh, fl3)
         e[3].record(stream)
     torch.cuda.synchronize()
     ph = np.array([[ev[i][k].elapsed_time(ev[i][k + 1]) for k in range(3)] for i in range(args.steps)])
@@ -514,7 +516,9 @@ def main():
         del src, dst
 
     # the dominant kernel: the slowest of the three phases (each one launch)
-    if plan.has_split:  # the kernels of the default plan for this workload
+    if plan.has_split == 2:  # the kernels of the default plan for this workload
+        names = ["pass1 sym_first_kernel<true>", "pass2 sym_middle_kernel", "pass3 sym_last_kernel"]
+    elif plan.has_split:
         names = ["pass1 split_first_kernel", "pass2 split_middle_kernel<false>",
                  "phase3 local_fft_fast_kernel<12,1,4,2,32,0>"]
     elif fl:  # the packed form (plan option PACO_PLAN_NO_SPLIT)

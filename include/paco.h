@@ -79,7 +79,7 @@ typedef enum {
 #define PACO_NO_TWIDDLE 1       /* stage 2 only: apply the bare permutation pi_m */
 #define PACO_PACKED 2           /* the fused pipeline's Phase-I buffer (below) */
 #define PACO_TWO_PASS 4         /* with PACO_PACKED, stage 1: the two-pass form's Phase I */
-#define PACO_SPLIT 8            /* alone, stage 1 or 2: the split form's pass 1 or pass 2 */
+#define PACO_SPLIT 8            /* alone: pass 1, 2 (or 3) of the plan's split form */
 
 typedef struct paco_plan_s paco_plan;
 
@@ -137,6 +137,8 @@ typedef struct {
                                       passes of Phase I plus Phase II)                     */
 #define PACO_PLAN_GENERIC 8u       /* descriptor-driven kernels only (no fast tiles, no
                                       split form); same arithmetic order as the fast tiles */
+#define PACO_PLAN_NO_SYM 16u       /* no symmetric split form: the split form of Phase I
+                                      alone (Phase III keeps whole columns on chip)         */
 
 /* paco_plan_create / paco_plan_create_mixed with options (NULL: defaults).
  * Errors as paco_plan_create; PACO_ERR_INVALID_ARG for an unknown flag or a
@@ -179,7 +181,26 @@ paco_status paco_plan_workspace_size(const paco_plan *plan, size_t *bytes);
  * between the first two differs; with N1 = 2^13 or 2^14, where Phase I takes
  * two on-chip passes otherwise, the split form saves one HBM pass.
  * paco_plan_has_split tells; the plan option PACO_PLAN_NO_SPLIT keeps the
- * other plan. */
+ * other plan.
+ *
+ * Symmetric split form.  A PACO_C64 plan with N1 = N2 = 4096 (any valid b
+ * and p) splits Phase III the same way, with its 16-point child moved into
+ * the redistribution pass (Lemma 1 on both local phases; Phase I:
+ * j1 = 16 j + r, k1 = k + 256 s; Phase III: j2 = jc + 256 rr,
+ * k2 = q0 + 16 q):
+ *   pass 1: workspace[((k >> 4)*N2 + c)*256 + 16 r + (k & 15)] = U[c][r][k]
+ *           = w_N1^{-k r} sum_j X[16 j + r, c] w_256^{-k j}
+ *   pass 2: A[k + 256 s, c] = sum_r w_16^{-s r} U[c][r][k],
+ *           Z[v, c] = A[v, c] w_N^{-v c},
+ *           out[(16 jc + q0)*N1 + v] = W[v][jc][q0]
+ *           = w_N2^{-q0 jc} sum_rr Z[v, jc + 256 rr] w_16^{-q0 rr}
+ *   pass 3: out[(q0 + 16 q)*N1 + v] = Y[q0 + 16 q, v]
+ *           = sum_jc w_256^{-q jc} W[v][jc][q0]   (in place)
+ * so that every pass reads and writes whole 128-byte lines; the paper's
+ * digit reversals cancel between the redistribution and Phase III's input
+ * layout, as in the packed form.  Three HBM passes, the same workspace and
+ * out.  paco_plan_has_split reports 2; the option PACO_PLAN_NO_SYM keeps the
+ * split form of Phase I alone. */
 paco_status paco_execute(const paco_plan *plan, const void *in, void *out, void *workspace,
                          size_t workspace_bytes, void *stream);
 
@@ -227,8 +248,9 @@ paco_status paco_execute_two_pass(const paco_plan *plan, const void *in, void *o
 /* *yes = 1 when paco_execute_two_pass runs for this plan, else 0. */
 paco_status paco_plan_has_two_pass(const paco_plan *plan, int32_t *yes);
 
-/* *yes = 1 when paco_execute (and paco_execute_inverse of a square plan)
- * runs the split form for this plan, else 0. */
+/* *yes = 2 when paco_execute (and paco_execute_inverse of a square plan)
+ * runs the symmetric split form for this plan, 1 for the split form of
+ * Phase I alone, else 0. */
 paco_status paco_plan_has_split(const paco_plan *plan, int32_t *yes);
 
 /* Runs one phase alone, for stage-wise checks and per-phase timing, always
@@ -253,7 +275,11 @@ paco_status paco_plan_has_split(const paco_plan *plan, int32_t *yes);
  * the split buffer T) or pass 2 (stage 2: src = T, dst = Zhat, the same
  * result as stage 2 of paco_execute); src and dst must not overlap;
  * PACO_ERR_UNSUPPORTED without a split form, PACO_ERR_INVALID_ARG with
- * other flags or stage 3. */
+ * other flags or stage 3.  On a plan with the symmetric split form
+ * PACO_SPLIT runs its passes instead: stage 1 (src = x, dst = the buffer U),
+ * stage 2 (src = U, dst = the buffer W, see paco_execute) and stage 3
+ * (src = W, dst = out = y; src == dst allowed); stages 1 and 2 out of
+ * place. */
 paco_status paco_execute_stage(const paco_plan *plan, int stage, int flags, const void *src,
                                void *dst, void *stream);
 

@@ -1,0 +1,203 @@
+// Address maps of the kernels: which item of which buffer each thread of each
+// workgroup loads or stores.  The kernels compute their addresses with these
+// functions, and a host audit (tests/audit/addr_audit.cpp) enumerates the
+// same functions over every workgroup, thread and item of a pass to check
+// that every address lies inside its buffer, every output item is written
+// exactly once, in-place passes read and write the same items, and the
+// 32-bit byte offsets never wrap.  Plain C++ (no HIP header): compiled for
+// the device by the library and for the host by the audit.
+#pragma once
+
+#include <cstdint>
+
+#if defined(__HIPCC__)
+#define PACO_HD __host__ __device__ __forceinline__
+#else
+#define PACO_HD inline
+#endif
+
+namespace paco {
+
+// ---- digit reversals (appendix A.1) ---------------------------------------
+
+// pi_ell in base b = 2^t: the ell groups of t bits of x in the opposite
+// order.  ell == 0 is the identity.
+PACO_HD int64_t digit_reverse_bits(int64_t x, int t, int ell)
+{
+    if (ell == 0) return x;
+    int64_t r = 0;
+    const int64_t m = (int64_t(1) << t) - 1;
+    for (int g = 0; g < ell; ++g) {
+        r = (r << t) | (x & m);
+        x >>= t;
+    }
+    return r;
+}
+
+// The same permutation for b = 2^t with t in {1, 2, 4, 8} (t*ell <= 32):
+// reverse all t*ell bits, then restore the bit order inside each t-bit digit
+// with up to three mask swaps.  Branch-free; GEN selects the digit-by-digit
+// loop for other t.
+template <bool GEN = false>
+PACO_HD int64_t digrev(int64_t x, int t, int ell)
+{
+    if constexpr (GEN) {
+        return digit_reverse_bits(x, t, ell);
+    } else {
+        const int nb = t * ell;
+        uint32_t r = __builtin_bitreverse32(uint32_t(x)) >> ((32 - nb) & 31);
+        const uint32_t s1 = ((r & 0x55555555u) << 1) | ((r >> 1) & 0x55555555u);
+        r = t >= 2 ? s1 : r;
+        const uint32_t s2 = ((r & 0x33333333u) << 2) | ((r >> 2) & 0x33333333u);
+        r = t >= 4 ? s2 : r;
+        const uint32_t s3 = ((r & 0x0F0F0F0Fu) << 4) | ((r >> 4) & 0x0F0F0F0Fu);
+        r = t >= 8 ? s3 : r;
+        return nb == 0 ? x : int64_t(r);
+    }
+}
+
+// Mixed-radix digit maps over [0, b^ell 2^s) (0 <= s < t): the digits are
+// (b, ..., b, 2^s), least significant first.  The forward map pi reverses
+// the digit string and reads it with the radices reversed:
+//     pi(x)     = (x >> t ell) + digrev(x mod b^ell) 2^s
+//     pi^-1(u)  = digrev(u >> s) + (u mod 2^s) b^ell      (inv = true)
+// s = 0: both are digrev (pi_ell is an involution).
+template <bool GEN = false>
+PACO_HD int64_t digmap(int64_t x, int t, int ell, int s, bool inv)
+{
+    if (s == 0) return digrev<GEN>(x, t, ell);
+    const int nb = t * ell;
+    if (inv) return digrev<GEN>(x >> s, t, ell) | ((x & ((int64_t(1) << s) - 1)) << nb);
+    return (x >> nb) | (digrev<GEN>(x & ((int64_t(1) << nb) - 1), t, ell) << s);
+}
+
+// True when the branch-free digit reversal covers digit width t.
+PACO_HD constexpr bool digrev_fast(int t) { return t == 1 || t == 2 || t == 4 || t == 8; }
+
+// Digit reversal with compile-time digit width TB and digit count ND.
+template <int TB, int ND>
+PACO_HD uint32_t drev(uint32_t x)
+{
+    uint32_t r = 0;
+#pragma unroll
+    for (int g = 0; g < ND; ++g) r |= ((x >> (TB * g)) & ((1u << TB) - 1)) << (TB * (ND - 1 - g));
+    return r;
+}
+constexpr int crev(int x, int tb, int nd)
+{
+    int r = 0;
+    for (int g = 0; g < nd; ++g) r |= ((x >> (tb * g)) & ((1 << tb) - 1)) << (tb * (nd - 1 - g));
+    return r;
+}
+
+// Tile order: the hardware deals consecutive workgroup ids to the 8 XCDs in
+// turn.  Renumber so that the workgroups one XCD receives back to back own
+// neighbouring column tiles, which share 128-byte lines in that XCD's L2.
+PACO_HD int64_t tile_order(int64_t i, int64_t G)
+{
+    if (G & 7) return i;
+    return (i & 7) * (G >> 3) + (i >> 3);
+}
+
+namespace addr {
+
+// Each map is a per-thread base plus a per-item offset (item indices, not
+// bytes, into the pass's source or destination buffer): the kernels form one
+// pointer from the base and add the offsets, the audit adds the two.
+
+// ---- the symmetric split form (sym.hip), N1 = N2 = 4096 ---------------------
+// Workgroup blk, thread tid (256 threads), item i < 16.
+
+// pass 1: workgroup (r, cb) = (blk / (N2/16), blk mod (N2/16)); thread
+// (cl, jl) = (tid & 15, tid >> 4) loads row 16 (jl + 16 i) + r, column 16 cb + cl
+PACO_HD uint32_t sym1_load_base(uint32_t N2, uint32_t blk, uint32_t tid)
+{
+    const uint32_t ncb = N2 >> 4, cb = blk % ncb, r = blk / ncb;
+    return (16u * (tid >> 4) + r) * N2 + (cb << 4) + (tid & 15u);
+}
+PACO_HD uint32_t sym1_load_off(uint32_t N2, uint32_t i) { return 256u * i * N2; }
+// The workspace between passes 1 and 2 holds U[c][r][k] at
+//     ((k >> 4) N2 + c) 256 + 16 r + (k & 15),
+// so that pass 2 reads 2 KiB runs (all r of 16 consecutive k of one column).
+// Thread (kl, cl) = (tid & 15, tid >> 4) stores U[c][r][kl + 16 i], c = 16 cb + cl.
+PACO_HD uint32_t sym1_store_base(uint32_t N2, uint32_t blk, uint32_t tid)
+{
+    const uint32_t ncb = N2 >> 4, cb = blk % ncb, r = blk / ncb;
+    return ((cb << 4) + (tid >> 4)) * 256u + 16u * r + (tid & 15u);
+}
+PACO_HD uint32_t sym1_store_off(uint32_t N2, uint32_t i) { return i * N2 * 256u; }
+// pass 2: the hardware's workgroup id g maps to (jc, kb) = (g mod 256, g / 256)
+// (jc fastest: neighbouring workgroups read neighbouring 2 KiB runs);
+// blk = 16 jc + kb.  Thread (kk, rr) loads U[jc + 256 rr][i][16 kb + kk].
+PACO_HD uint32_t sym2_block(uint32_t g) { return ((g & 255u) << 4) | (g >> 8); }
+PACO_HD uint32_t sym2_load_base(uint32_t N2, uint32_t blk, uint32_t tid)
+{
+    const uint32_t kb = blk & 15u, jc = blk >> 4;
+    return ((kb * N2 + jc + 256u * (tid >> 4)) << 8) + (tid & 15u);
+}
+PACO_HD uint32_t sym2_load_off(uint32_t i) { return 16u * i; }
+// thread (kk, s) stores W at row 16 jc + i, column 16 kb + kk + 256 s
+PACO_HD uint32_t sym2_store_base(uint32_t N1, uint32_t blk, uint32_t tid)
+{
+    const uint32_t kb = blk & 15u, jc = blk >> 4;
+    return 16u * jc * N1 + 16u * kb + (tid & 15u) + 256u * (tid >> 4);
+}
+PACO_HD uint32_t sym2_store_off(uint32_t N1, uint32_t i) { return i * N1; }
+// pass 3: workgroup (q0, vb) = (blk / (N1/16), blk mod (N1/16)); thread
+// (cl, jl) loads row 16 (jl + 16 i) + q0, column 16 vb + cl
+PACO_HD uint32_t sym3_load_base(uint32_t N1, uint32_t blk, uint32_t tid)
+{
+    const uint32_t nvb = N1 >> 4, vb = blk % nvb, q0 = blk / nvb;
+    return (16u * (tid >> 4) + q0) * N1 + (vb << 4) + (tid & 15u);
+}
+PACO_HD uint32_t sym3_load_off(uint32_t N1, uint32_t i) { return 256u * i * N1; }
+// thread (cl, kl) = (tid & 15, tid >> 4) stores row q0 + 16 (kl + 16 i)
+PACO_HD uint32_t sym3_store_base(uint32_t N1, uint32_t blk, uint32_t tid)
+{
+    const uint32_t nvb = N1 >> 4, vb = blk % nvb, q0 = blk / nvb;
+    return (q0 + 16u * (tid >> 4)) * N1 + (vb << 4) + (tid & 15u);
+}
+PACO_HD uint32_t sym3_store_off(uint32_t N1, uint32_t i) { return 256u * i * N1; }
+// workgroup counts of the three passes
+PACO_HD uint32_t sym1_groups(uint32_t N2) { return 16u * (N2 >> 4); }
+PACO_HD uint32_t sym2_groups(uint32_t N1, uint32_t N2) { return (N2 >> 4) * (N1 >> 8); }
+PACO_HD uint32_t sym3_groups(uint32_t N1) { return 16u * (N1 >> 4); }
+
+// ---- the split form of Phase I (split.hip), N1 = 16 M -------------------------
+
+// pass 1: workgroup (cg, jg) = (blk mod (N2/16), blk / (N2/16)), 256
+// threads (cl, jl); thread loads row j + M i (j = 16 jg + jl), column 16 cg + cl
+PACO_HD uint32_t split1_load_base(uint32_t N2, uint32_t blk, uint32_t tid)
+{
+    const uint32_t ncg = N2 >> 4, cg = blk % ncg, jg = blk / ncg;
+    return ((jg << 4) + (tid >> 4)) * N2 + (cg << 4) + (tid & 15u);
+}
+PACO_HD uint32_t split1_load_off(uint32_t N1, uint32_t N2, uint32_t i) { return (N1 >> 4) * i * N2; }
+// store q < 16 of thread tid: column 16 cg + q, items 256 jg + tid of its T
+PACO_HD uint32_t split1_store_base(uint32_t N1, uint32_t N2, uint32_t blk, uint32_t tid)
+{
+    const uint32_t ncg = N2 >> 4, cg = blk % ncg, jg = blk / ncg;
+    return (cg << 4) * N1 + (jg << 8) + tid;
+}
+PACO_HD uint32_t split1_store_off(uint32_t N1, uint32_t q) { return q * N1; }
+PACO_HD uint32_t split1_groups(uint32_t N1, uint32_t N2) { return (N2 >> 4) * (N1 >> 8); }
+
+// pass 2, N1 = 4096: workgroup c, 256 threads (lo, hi) = (tid & 15, tid >> 4):
+// loads T[c][hi + 16 i][lo]; stores row u (the caller's pi_{m2}(c)),
+// frequency lo + 16 hi + 256 i
+PACO_HD uint32_t split2_load_base(uint32_t N1, uint32_t c, uint32_t tid) { return c * N1 + tid; }
+PACO_HD uint32_t split2_load_off(uint32_t i) { return 256u * i; }
+PACO_HD uint32_t split2_store_base(uint32_t N1, uint32_t u, uint32_t tid) { return u * N1 + tid; }
+PACO_HD uint32_t split2_store_off(uint32_t i) { return 256u * i; }
+
+// pass 2, N1 = 16 M with M = 256 R: workgroup c, M threads, thread
+// (k0, jl) = (tid & 15, tid >> 4) loads T[c][jl + (M/16) i][k0]; stage C
+// thread (k0, q) stores, for pair i < 16 / R and kc < R, frequency
+// k0 + 16 (q + (M/16) i) + 4096 kc of row u
+PACO_HD uint32_t split3_load_base(uint32_t N1, uint32_t c, uint32_t tid) { return c * N1 + tid; }
+PACO_HD uint32_t split3_load_off(uint32_t N1, uint32_t i) { return (N1 >> 8) * 16u * i; }
+PACO_HD uint32_t split3_store_base(uint32_t N1, uint32_t u, uint32_t tid) { return u * N1 + tid; }
+PACO_HD uint32_t split3_store_off(uint32_t N1, uint32_t pair, uint32_t kc) { return 16u * (N1 >> 8) * pair + 4096u * kc; }
+
+}  // namespace addr
+}  // namespace paco

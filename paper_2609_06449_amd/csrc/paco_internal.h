@@ -7,6 +7,8 @@
 #include <string>
 #include <vector>
 
+#include "addr.h"
+
 namespace paco {
 
 // Complex product with an explicit fused multiply-add in each component:
@@ -60,42 +62,6 @@ __host__ __device__ constexpr int stage_tw_offset(int l, int s)
 }
 __host__ __device__ constexpr int stage_tw_total(int l) { return stage_tw_offset(l, stage_count(l)); }
 
-// pi_ell in base b = 2^t (appendix A.1): the ell groups of t bits of x in
-// the opposite order.  ell == 0 is the identity.
-__host__ __device__ inline int64_t digit_reverse_bits(int64_t x, int t, int ell)
-{
-    if (ell == 0) return x;
-    int64_t r = 0;
-    const int64_t m = (int64_t(1) << t) - 1;
-    for (int g = 0; g < ell; ++g) {
-        r = (r << t) | (x & m);
-        x >>= t;
-    }
-    return r;
-}
-
-// The same permutation on the device for b = 2^t with t in {1, 2, 4, 8}
-// (t*ell <= 32): reverse all t*ell bits, then restore the bit order inside
-// each t-bit digit with up to three mask swaps.  Branch-free; GEN selects the
-// digit-by-digit loop for other t.
-template <bool GEN = false>
-__device__ __forceinline__ int64_t digrev(int64_t x, int t, int ell)
-{
-    if constexpr (GEN) {
-        return digit_reverse_bits(x, t, ell);
-    } else {
-        const int nb = t * ell;
-        uint32_t r = __builtin_bitreverse32(uint32_t(x)) >> ((32 - nb) & 31);
-        const uint32_t s1 = ((r & 0x55555555u) << 1) | ((r >> 1) & 0x55555555u);
-        r = t >= 2 ? s1 : r;
-        const uint32_t s2 = ((r & 0x33333333u) << 2) | ((r >> 2) & 0x33333333u);
-        r = t >= 4 ? s2 : r;
-        const uint32_t s3 = ((r & 0x0F0F0F0Fu) << 4) | ((r >> 4) & 0x0F0F0F0Fu);
-        r = t >= 8 ? s3 : r;
-        return nb == 0 ? x : int64_t(r);
-    }
-}
-
 // Tile width of the fast kernels: 4096 items per workgroup for short
 // transforms, 4 columns (32-byte row runs) for long ones.
 __host__ __device__ constexpr int fast_log2T(int l) { return l >= 10 ? 2 : 12 - l; }
@@ -112,24 +78,6 @@ __host__ __device__ constexpr int mf_log2T(int l, int mode) { return (mode == 2 
 // arithmetic prec (0: FP32 VALU; the split MFMA forms get 512 threads and
 // with them 256 VGPRs per lane).
 __host__ __device__ constexpr int generic_max_threads(int prec) { return prec == 0 ? 1024 : 512; }
-
-// Mixed-radix digit maps over [0, b^ell 2^s) (0 <= s < t): the digits are
-// (b, ..., b, 2^s), least significant first.  The forward map pi reverses
-// the digit string and reads it with the radices reversed:
-//     pi(x)     = (x >> t ell) + digrev(x mod b^ell) 2^s
-//     pi^-1(u)  = digrev(u >> s) + (u mod 2^s) b^ell      (inv = true)
-// s = 0: both are digrev (pi_ell is an involution).
-template <bool GEN = false>
-__device__ __forceinline__ int64_t digmap(int64_t x, int t, int ell, int s, bool inv)
-{
-    if (s == 0) return digrev<GEN>(x, t, ell);
-    const int nb = t * ell;
-    if (inv) return digrev<GEN>(x >> s, t, ell) | ((x & ((int64_t(1) << s) - 1)) << nb);
-    return (x >> nb) | (digrev<GEN>(x & ((int64_t(1) << nb) - 1), t, ell) << s);
-}
-
-// True when the branch-free device digit reversal covers digit width t.
-__host__ __device__ constexpr bool digrev_fast(int t) { return t == 1 || t == 2 || t == 4 || t == 8; }
 
 // One HBM pass of a batched local FFT: the GPU form of a digit-field view
 // (paper, appendix A.3-A.4).  The pass has n_outer * (ncols / T) independent
@@ -224,6 +172,33 @@ struct SplitPass {
 };
 constexpr int kTwTile = 128;  // tile-twiddle table side: [i*128 + j] = w_N^{-(i*j mod N)}
 
+// The symmetric split form (sym.hip), FP32, N1 = N2 = 4096: Lemma 1 once more
+// on both local phases, with the 16-point children next to the
+// redistribution.  Phase I:   j1 = 16 j + r,  k1 = k + 256 s;
+//                  Phase III: j2 = jc + 256 rr, k2 = q0 + 16 q.
+//   pass 1: U[c][r][k] = w_N1^{-k r} sum_j X[16 j + r, c] w_256^{-k j}
+//           -> ws[((k >> 4) N2 + c) 256 + 16 r + (k & 15)]
+//   pass 2: A[k + 256 s, c] = sum_r w_16^{-s r} U[c][r][k];
+//           Z[v, c] = A[v, c] w_N^{-v c};
+//           W[v][jc][q0] = w_N2^{-q0 jc} sum_rr Z[v, jc + 256 rr] w_16^{-q0 rr}
+//           -> out[(16 jc + q0) N1 + v]
+//   pass 3: Y[q0 + 16 q, v] = sum_jc w_256^{-q jc} W[v][jc][q0]
+//           -> out[(q0 + 16 q) N1 + v], in place (a tile reads and writes the
+//           same rows {q0 + 16 t})
+constexpr int kSymLog2N = 12;
+struct SymPass {
+    const float2 *src;
+    float2 *dst;
+    int64_t N1, N2;
+    const float2 *tw;             // w_L^{-r}, r < L = 2^log2L (L >= N1, N2)
+    int32_t log2L;
+    const float2 *tw_hi, *tw_lo;  // w_N^{-e} = tw_hi[e >> log2Lo] * tw_lo[e mod 2^log2Lo]
+    int32_t log2N, log2Lo;
+    const float2 *tw_sj;          // [s * 256 + jc] = w_{16 N2}^{-s jc}, s < 16, jc < 256
+    int32_t conj_in;              // pass 1: conjugate x on load (the inverse's input map)
+    float out_scale;              // pass 3: nonzero stores conj(y) * out_scale (the inverse's output map)
+};
+
 // Workgroup geometry a local pass is launched with.
 struct LocalLaunch {
     int threads;       // per workgroup
@@ -264,6 +239,11 @@ hipError_t launch_middle(const MiddlePass &p, hipStream_t s);
 hipError_t launch_split_first(const SplitPass &p, hipStream_t s);
 hipError_t launch_split_middle(const SplitPass &p, hipStream_t s);
 hipError_t split_prepare();  // raises the dynamic-LDS limit of the three-stage pass 2 once
+// The three passes of the symmetric split form; hipErrorInvalidValue unless
+// N1 = N2 = 4096.
+hipError_t launch_sym_first(const SymPass &p, hipStream_t s);
+hipError_t launch_sym_middle(const SymPass &p, hipStream_t s);
+hipError_t launch_sym_last(const SymPass &p, hipStream_t s);
 
 // Columns per workgroup for an on-chip pass of length 2^log2n over ncols.
 int32_t choose_log2T(int32_t log2n, int64_t ncols);

@@ -63,6 +63,8 @@ struct paco_plan_s {
     LocalPass phase1_two{}, phase3_two{};   // the two-pass form's passes
     bool split = false;                     // N1 = 2^12: Phase I split 16 x 256 across passes 1 and 2
     paco::SplitPass split_pass{};           // src/dst filled per execution
+    bool sym = false;                       // N1 = N2 = 4096: the symmetric split form (three passes)
+    paco::SymPass sym_pass{};               // src/dst filled per execution
     paco_plan_s *inv = nullptr;             // N2 x N1 passes of the inverse (NULL: square, this plan's)
     std::string inv_error;                  // non-empty: the inverse passes could not be built
     std::string desc;
@@ -176,6 +178,7 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
     const bool paper_layout = (opt.flags & PACO_PLAN_PAPER_LAYOUT) != 0;
     const bool generic = (opt.flags & PACO_PLAN_GENERIC) != 0;
     const bool no_split = (opt.flags & PACO_PLAN_NO_SPLIT) != 0;
+    const bool no_sym = (opt.flags & PACO_PLAN_NO_SYM) != 0;
     paco_status st = validate_impl(N1, N2, p, b, dt, mixed);
     if (st != PACO_OK) return st;
 
@@ -209,7 +212,7 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
 
     // ---- host tables (FP64-generated, rounded once to FP32) ----------------
     const int64_t L = int64_t(1) << P->lL;
-    std::vector<float2> tw(L), thi, tlo, ttile, stw, tcw;
+    std::vector<float2> tw(L), thi, tlo, ttile, stw, tcw, tsj;
     for (int64_t r = 0; r < L; ++r) tw[r] = paco::root_neg(r, L);
     // the two-pass form's column factor w_{16 N1}^{-k} (single-pass Phase III
     // over at most 2^12 columns: a table of at most 512 KiB)
@@ -219,6 +222,14 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
         for (int64_t k = 0; k < 16 * N1; ++k) tcw[k] = paco::root_neg(k, 16 * N1);
     }
     paco::middle_tables(P->lN, thi, tlo, ttile);
+    // the symmetric split form (FP32, N1 = N2 = 4096; option PACO_PLAN_NO_SYM)
+    const bool sym_form = !no_split && !no_sym && !paper_layout && !generic && dt == PACO_C64 &&
+                          P->l1 == paco::kSymLog2N && P->l2 == paco::kSymLog2N;
+    if (sym_form) {  // its pass-2 factor w_{16 N2}^{-s jc}, s < 16, jc < 256
+        tsj.resize(16 * 256);
+        for (int64_t sv = 0; sv < 16; ++sv)
+            for (int64_t jc = 0; jc < 256; ++jc) tsj[sv * 256 + jc] = paco::root_neg((sv * jc) % (16 * N2), 16 * N2);
+    }
     int64_t stw_off[paco::kMaxOnChipLog2 + 1];
     if (!paco::stage_tables(stw, stw_off)) {
         delete P;
@@ -229,7 +240,8 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
     struct Piece { const void *src; size_t bytes; size_t off; };
     std::vector<Piece> pieces = {{tw.data(), tw.size() * 8, 0},       {thi.data(), thi.size() * 8, 0},
                                  {tlo.data(), tlo.size() * 8, 0},     {ttile.data(), ttile.size() * 8, 0},
-                                 {stw.data(), stw.size() * 8, 0},     {tcw.data(), tcw.size() * 8, 0}};
+                                 {stw.data(), stw.size() * 8, 0},     {tcw.data(), tcw.size() * 8, 0},
+                                 {tsj.data(), tsj.size() * 8, 0}};
     size_t total = 0;
     for (auto &pc : pieces) {
         pc.off = total;
@@ -254,6 +266,7 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
     const float2 *d_ttile = reinterpret_cast<const float2 *>(at(3));
     const float2 *d_stw = reinterpret_cast<const float2 *>(at(4));
     const float2 *d_tcw = reinterpret_cast<const float2 *>(at(5));
+    const float2 *d_tsj = reinterpret_cast<const float2 *>(at(6));
 
     auto base_pass = [&](int64_t ld, int64_t ncols, int log2n) {
         LocalPass q{};
@@ -471,6 +484,23 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
         }
     }
 
+    // ---- symmetric split form (FP32, N1 = N2 = 4096; option PACO_PLAN_NO_SYM)
+    // Phase III split like Phase I, its 16-point child moved into the
+    // redistribution pass: every pass moves whole 128-byte lines
+    if (sym_form) {
+        paco::SymPass &q = P->sym_pass;
+        q.N1 = N1;
+        q.N2 = N2;
+        q.tw = d_tw;
+        q.log2L = P->lL;
+        q.tw_hi = d_thi;
+        q.tw_lo = d_tlo;
+        q.log2N = P->lN;
+        q.log2Lo = P->lLo;
+        q.tw_sj = d_tsj;
+        P->sym = true;
+    }
+
     char buf[512];
     std::string desc;
     for (auto *ph : {&P->phase1, &P->phase3}) {
@@ -492,6 +522,9 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
         desc = buf + desc;
     }
     if (P->fused) desc = "fused[phase1 -> packed transposed slab, phase2 row unpack+twiddle] " + desc;
+    if (P->sym)
+        desc = "sym[pass1: phase1 256-point children over rows 16j+r -> ws; pass2: phase1 radix-16 + twiddle + "
+               "phase3 radix-16; pass3: phase3 256-point children, in place] " + desc;
     if (P->two_pass) {
         const paco::LocalLaunch g = paco::local_fft_geometry(P->phase3_two);
         std::snprintf(buf, sizeof buf, " two_pass[phase3 twiddle-on-load n=2^%d T=%d wg=%lld thr=%d lds=%zu]",
@@ -526,7 +559,7 @@ paco_status create_with_inverse(paco_plan **plan, int64_t N1, int64_t N2, int64_
                                 const paco_plan_options &opt)
 {
     if (plan) *plan = nullptr;
-    if (opt.flags & ~(PACO_PLAN_MIXED | PACO_PLAN_PAPER_LAYOUT | PACO_PLAN_NO_SPLIT | PACO_PLAN_GENERIC))
+    if (opt.flags & ~(PACO_PLAN_MIXED | PACO_PLAN_PAPER_LAYOUT | PACO_PLAN_NO_SPLIT | PACO_PLAN_GENERIC | PACO_PLAN_NO_SYM))
         return fail(PACO_ERR_INVALID_ARG, "unknown plan option flag");
     if (opt.groups1 < 0 || opt.groups1 > 3 || opt.groups3 < 0 || opt.groups3 > 3)
         return fail(PACO_ERR_INVALID_ARG, "groups1 / groups3 must be 0 (default), 1, 2 or 3");
@@ -585,7 +618,7 @@ paco_status paco_plan_describe(const paco_plan *plan, int32_t *launches, char *b
 {
     if (!plan) return fail(PACO_ERR_INVALID_ARG, "plan is NULL");
     if (launches)  // the split form runs its two passes in place of Phase I's passes and Phase II
-        *launches = int32_t((plan->split ? 2 : plan->phase1.size() + 1) + plan->phase3.size());
+        *launches = plan->sym ? 3 : int32_t((plan->split ? 2 : plan->phase1.size() + 1) + plan->phase3.size());
     if (buf && buflen) {
         std::strncpy(buf, plan->desc.c_str(), buflen - 1);
         buf[buflen - 1] = 0;
@@ -658,10 +691,30 @@ paco_status run_split(const paco_plan *plan, int pass, const void *src, void *ds
     return PACO_OK;
 }
 
+// Pass 1, 2 or 3 of the symmetric split form.
+paco_status run_sym(const paco_plan *plan, int pass, const void *src, void *dst, bool inverse, hipStream_t s)
+{
+    paco::SymPass q = plan->sym_pass;
+    q.src = static_cast<const float2 *>(src);
+    q.dst = static_cast<float2 *>(dst);
+    q.conj_in = inverse && pass == 1 ? 1 : 0;
+    q.out_scale = inverse && pass == 3 ? 1.0f / float(plan->N1 * plan->N2) : 0.f;  // 2^-log2 N: exact
+    hipError_t e = pass == 1 ? paco::launch_sym_first(q, s)
+                             : (pass == 2 ? paco::launch_sym_middle(q, s) : paco::launch_sym_last(q, s));
+    if (e != hipSuccess) return hip_fail(e, "symmetric split pass launch");
+    return PACO_OK;
+}
+
 // The three phases of one plan.  inverse: conj on Phase I's loads, conj and
 // 1/N on Phase III's stores, i.e. conj(Omega conj(in)) / N.
 paco_status run_three(const paco_plan *plan, const void *in, void *out, void *workspace, hipStream_t s, bool inverse)
 {
+    if (plan->sym) {
+        paco_status st = run_sym(plan, 1, in, workspace, inverse, s);
+        if (st == PACO_OK) st = run_sym(plan, 2, workspace, out, inverse, s);
+        if (st == PACO_OK) st = run_sym(plan, 3, out, out, inverse, s);
+        return st;
+    }
     std::vector<LocalPass> p1 = plan->fused ? std::vector<LocalPass>{plan->phase1_packed} : plan->phase1;
     std::vector<LocalPass> p3 = plan->phase3;
     if (inverse) {
@@ -731,7 +784,7 @@ paco_status paco_plan_has_split(const paco_plan *plan, int32_t *yes)
     if (!yes) return fail(PACO_ERR_INVALID_ARG, "yes out-pointer is NULL");
     *yes = 0;
     if (!plan) return fail(PACO_ERR_INVALID_ARG, "plan is NULL");
-    *yes = plan->split ? 1 : 0;
+    *yes = plan->sym ? 2 : (plan->split ? 1 : 0);
     return PACO_OK;
 }
 
@@ -743,12 +796,14 @@ paco_status paco_execute_stage(const paco_plan *plan, int stage, int flags, cons
     if (flags & ~(PACO_NO_TWIDDLE | PACO_PACKED | PACO_TWO_PASS | PACO_SPLIT))
         return fail(PACO_ERR_INVALID_ARG, "unknown flags");
     if (flags & PACO_SPLIT) {
-        if (flags != PACO_SPLIT || (stage != 1 && stage != 2))
-            return fail(PACO_ERR_INVALID_ARG, "PACO_SPLIT applies alone to stage 1 or 2");
-        if (!plan->split) return fail(PACO_ERR_UNSUPPORTED, "this plan has no split form");
+        if (flags != PACO_SPLIT || stage < 1 || stage > (plan->sym ? 3 : 2))
+            return fail(PACO_ERR_INVALID_ARG, "PACO_SPLIT applies alone to stage 1 or 2 (3 in the symmetric form)");
+        if (!plan->split && !plan->sym) return fail(PACO_ERR_UNSUPPORTED, "this plan has no split form");
         const size_t need = size_t(plan->N1) * size_t(plan->N2) * 8;
         const uintptr_t a = reinterpret_cast<uintptr_t>(src), b = reinterpret_cast<uintptr_t>(dst);
-        if (a < b + need && b < a + need) return fail(PACO_ERR_INVALID_ARG, "split stages are out of place");
+        if (a < b + need && b < a + need && !(stage == 3 && a == b))
+            return fail(PACO_ERR_INVALID_ARG, "split stages 1 and 2 are out of place (stage 3: in place or disjoint)");
+        if (plan->sym) return run_sym(plan, stage, src, dst, false, static_cast<hipStream_t>(stream));
         return run_split(plan, stage, src, dst, false, static_cast<hipStream_t>(stream));
     }
     if ((flags & PACO_TWO_PASS) && !(stage == 1 && (flags & PACO_PACKED)))

@@ -44,15 +44,14 @@ __global__ __launch_bounds__(kSplitThreads) void split_first_kernel(SplitPass P)
 {
     __shared__ float2 lds[16 * kFirstPad];
     const int tid = threadIdx.x;
-    const int64_t ncg = P.N2 >> 4;
-    const int64_t cg = int64_t(blockIdx.x) % ncg, jg = int64_t(blockIdx.x) / ncg;
+    const int64_t jg = int64_t(blockIdx.x) / (P.N2 >> 4);
     const int cl = tid & 15, jl = tid >> 4;
-    const int64_t c = (cg << 4) + cl;
     const int j = int(jg << 4) + jl;
-    const int64_t M = P.N1 >> 4;  // rows j + M r of the first radix-16 stage
+    const uint32_t N1 = uint32_t(P.N1), N2 = uint32_t(P.N2);
+    const float2 *src = P.src + addr::split1_load_base(N2, blockIdx.x, tid);
     float2 v[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = P.src[(int64_t(j) + r * M) * P.N2 + c];
+    for (int r = 0; r < 16; ++r) v[r] = src[addr::split1_load_off(N1, N2, r)];  // rows j + (N1/16) r
     if (P.conj_in) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) v[r].y = -v[r].y;
@@ -63,9 +62,9 @@ __global__ __launch_bounds__(kSplitThreads) void split_first_kernel(SplitPass P)
 #pragma unroll
     for (int k0 = 0; k0 < 16; ++k0) lds[cl * kFirstPad + jl * 16 + k0] = v[k0];
     __syncthreads();
-    float2 *dst = P.dst + (cg << 4) * P.N1 + (jg << 8) + tid;
+    float2 *dst = P.dst + addr::split1_store_base(N1, N2, blockIdx.x, tid);
 #pragma unroll
-    for (int q = 0; q < 16; ++q) st2_stream(dst + q * P.N1, lds[q * kFirstPad + tid]);
+    for (int q = 0; q < 16; ++q) st2_stream(dst + addr::split1_store_off(N1, q), lds[q * kFirstPad + tid]);
 }
 
 // Pass 2.  Workgroup c: y_k0[j] = T[c][j][k0] (j = jl + 16 jh) is
@@ -92,10 +91,11 @@ __global__ __launch_bounds__(kSplitThreads) __attribute__((amdgpu_waves_per_eu(5
     const int tid = threadIdx.x;
     const int64_t c = blockIdx.x;
     const int lo = tid & 15, hi = tid >> 4;  // k0, and jl (inner sums) or kl (outer sums)
-    const float2 *src = P.src + c * P.N1;
+    const uint32_t N1 = uint32_t(P.N1);
     float2 v[16];
+    const float2 *src = P.src + addr::split2_load_base(N1, uint32_t(c), tid);
 #pragma unroll
-    for (int jh = 0; jh < 16; ++jh) v[jh] = ld2_last(src + (hi + 16 * jh) * 16 + lo);  // nothing reads ws again
+    for (int jh = 0; jh < 16; ++jh) v[jh] = ld2_last(src + addr::split2_load_off(jh));  // last use
     float2 t256[16];
 #pragma unroll
     for (int k = 1; k < 16; ++k) t256[k] = P.tw[(16 * hi * k) << P.tw_shift];  // w_256^{-jl kl}
@@ -123,10 +123,9 @@ __global__ __launch_bounds__(kSplitThreads) __attribute__((amdgpu_waves_per_eu(5
     dft_regs<4>(v);
 
     const float2 a = cmul(cmul(a0, a1), cmul(a2, a3));  // w_N^{-(k0 + 16 kl) c}
-    char *dst = reinterpret_cast<char *>(P.dst + u * P.N1 + lo + 16 * hi);
+    float2 *dst = P.dst + addr::split2_store_base(N1, uint32_t(u), tid);
 #pragma unroll
-    for (int kh = 0; kh < 16; ++kh)
-        st2<false>(dst + size_t(256 * kh) * 8u, cmul(v[kh], cmul(a, cmul(bh[kh], bl[kh]))));
+    for (int kh = 0; kh < 16; ++kh) dst[addr::split2_store_off(kh)] = cmul(v[kh], cmul(a, cmul(bh[kh], bl[kh])));
 }
 
 // Pass 2 for N1 = 16 M with M = 256 R (R = 2^LR = 2 or 4: N1 = 2^13, 2^14).
@@ -154,14 +153,15 @@ __global__ __launch_bounds__(256 << LR) __attribute__((amdgpu_waves_per_eu(4))) 
     const int tid = threadIdx.x;
     const int64_t c = blockIdx.x;
     const int k0 = tid & 15;
-    const float2 *src = P.src + c * P.N1;
+    const uint32_t N1 = uint32_t(P.N1);
+    const float2 *src = P.src + addr::split3_load_base(N1, uint32_t(c), tid);
     const uint32_t nmask = uint32_t((uint64_t(1) << P.log2N) - 1), lomask = (1u << P.log2Lo) - 1;
 
     // stage A operands, then every twiddle, issued before the first butterfly
     const int jl = tid >> 4;
     float2 v[16];
 #pragma unroll
-    for (int jh = 0; jh < 16; ++jh) v[jh] = ld2_last(src + (jl + JL * jh) * 16 + k0);  // nothing reads ws again
+    for (int jh = 0; jh < 16; ++jh) v[jh] = ld2_last(src + addr::split3_load_off(N1, jh));  // last use
     // stage B: (k0, ka, jlo); jlo is the same for a whole wave (its twiddles
     // are scalar loads)
     const int kab = (tid >> 4) & 15, jlo = __builtin_amdgcn_readfirstlane(tid >> 8);
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(256 << LR) __attribute__((amdgpu_waves_per_eu(4))) 
     __syncthreads();
     // C: NPAIR radix-R butterflies per thread, stored straight to row pi_{m2}(c)
     const float2 a0 = cmul(h0, l0);
-    char *dst = reinterpret_cast<char *>(P.dst + u * P.N1 + k0);
+    float2 *dst = P.dst + addr::split3_store_base(N1, uint32_t(u), tid);
 #pragma unroll
     for (int i = 0; i < NPAIR; ++i) {
         const int pr = q + JL * i, ka = pr & 15;
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(256 << LR) __attribute__((amdgpu_waves_per_eu(4))) 
         const float2 a = cmul(a0, cmul(hp[i], lp[i]));
 #pragma unroll
         for (int kc = 0; kc < R; ++kc)
-            st2<false>(dst + (size_t(16 * pr) + size_t(4096 * kc)) * 8u, cmul(z[kc], cmul(a, cmul(hc[kc], lc[kc]))));
+            dst[addr::split3_store_off(N1, i, kc)] = cmul(z[kc], cmul(a, cmul(hc[kc], lc[kc])));
     }
 }
 
@@ -250,8 +250,8 @@ hipError_t split_prepare()
 hipError_t launch_split_first(const SplitPass &p, hipStream_t s)
 {
     if (!split_shape_ok(p)) return hipErrorInvalidValue;
-    const int64_t groups = (p.N2 / 16) * (p.N1 / 256);
-    hipLaunchKernelGGL(split_first_kernel, dim3(unsigned(groups)), dim3(kSplitThreads), 0, s, p);
+    hipLaunchKernelGGL(split_first_kernel, dim3(addr::split1_groups(uint32_t(p.N1), uint32_t(p.N2))),
+                       dim3(kSplitThreads), 0, s, p);
     return hipGetLastError();
 }
 

@@ -137,23 +137,6 @@ __device__ __forceinline__ void st4(char *p, float4 v)
 // stride 16*T items) land on distinct banks.
 __device__ __forceinline__ int lpad(int e) { return e + ((e >> 6) << 2); }
 
-// Digit reversal with compile-time digit width TB and digit count ND.
-template <int TB, int ND>
-__device__ __forceinline__ uint32_t drev(uint32_t x)
-{
-    uint32_t r = 0;
-#pragma unroll
-    for (int g = 0; g < ND; ++g) r |= ((x >> (TB * g)) & ((1u << TB) - 1)) << (TB * (ND - 1 - g));
-    return r;
-}
-constexpr int crev(int x, int tb, int nd)
-{
-    int r = 0;
-    for (int g = 0; g < nd; ++g) r |= ((x >> (tb * g)) & ((1 << tb) - 1)) << (tb * (nd - 1 - g));
-    return r;
-}
-
-
 struct Ctx {
     float2 *lds;
     const float2 *twl;
@@ -500,15 +483,6 @@ __device__ __forceinline__ void run_stage(float2 (&v)[H * EG], const Ctx &c)
             }
         }
     }
-}
-
-// Tile order: the hardware deals consecutive workgroup ids to the 8 XCDs in
-// turn.  Renumber so that the workgroups one XCD receives back to back own
-// neighbouring column tiles, which share 128-byte lines in that XCD's L2.
-__device__ __forceinline__ int64_t tile_order(int64_t i, int64_t G)
-{
-    if (G & 7) return i;
-    return (i & 7) * (G >> 3) + (i >> 3);
 }
 
 __device__ __forceinline__ void copy_twiddles(float2 *twl, const float2 *stw, int n, int tid, int nt)

@@ -36,6 +36,7 @@ PACO_PLAN_MIXED = 1
 PACO_PLAN_PAPER_LAYOUT = 2
 PACO_PLAN_NO_SPLIT = 4
 PACO_PLAN_GENERIC = 8
+PACO_PLAN_NO_SYM = 16
 
 # paco_batch_options.flags
 PACO_BATCH_NO_TUNE = 1
@@ -205,10 +206,11 @@ def paco_plan_has_two_pass(plan: int) -> bool:
     return bool(yes.value)
 
 
-def paco_plan_has_split(plan: int) -> bool:
+def paco_plan_has_split(plan: int) -> int:
+    """0: no split form, 1: the split form of Phase I, 2: the symmetric split form."""
     yes = ctypes.c_int32()
     _check(_lib.paco_plan_has_split(plan, ctypes.byref(yes)), "paco_plan_has_split")
-    return bool(yes.value)
+    return int(yes.value)
 
 
 def paco_plan_describe(plan: int):

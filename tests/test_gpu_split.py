@@ -130,13 +130,13 @@ def test_split_mixed_radix_matches_oracle():
 
 
 def test_split_full_size_sampled():
-    # N = 2^24 as 4096 x 4096, p = 64, b = 16, N(0,1) inputs, seed 2: the
-    # launch configuration the bench times; outputs sampled one by one
+    # N = 2^24 as 4096 x 4096, p = 64, b = 16, N(0,1) inputs, seed 2, in the
+    # split form of Phase I alone; outputs sampled one by one
     N1, N2, p, b = 4096, 4096, 64, 16
     N = N1 * N2
     x = inputs.normal(N, seed=2)
-    plan = paco.Plan(N1, N2, p, b)
-    assert plan.has_split
+    plan = paco.Plan(N1, N2, p, b, flags=paco.PACO_PLAN_NO_SYM)  # the symmetric form has its own tests
+    assert plan.has_split == 1
     y = _execute(plan, _dev(x))
     ks = np.array([0, 1, 15, 16, 255, 256, 4095, 4096, 65537, N // 2, N - 1, 12345678, 9876543])
     ref = oracle.dft_at(x, ks)
@@ -205,8 +205,8 @@ def test_square_inverse_through_the_split_passes():
     # a square plan's inverse runs on its own passes: pass 1 conjugates on load
     N1 = N2 = 4096
     x = inputs.normal(N1 * N2, seed=77)
-    plan = paco.Plan(N1, N2, 64, 16)
-    assert plan.has_split
+    plan = paco.Plan(N1, N2, 64, 16, flags=paco.PACO_PLAN_NO_SYM)
+    assert plan.has_split == 1
     yd = _dev(x)
     out = torch.empty_like(yd)
     ws = torch.empty_like(yd)
@@ -220,7 +220,9 @@ def test_square_inverse_through_the_split_passes():
 
 
 def test_which_plans_split():
-    assert paco.Plan(4096, 64, 4, 4).has_split
+    assert paco.Plan(4096, 64, 4, 4).has_split == 1
+    assert paco.Plan(4096, 4096, 64, 16).has_split == 2                       # the symmetric split form
+    assert paco.Plan(4096, 4096, 64, 16, flags=paco.PACO_PLAN_NO_SYM).has_split == 1
     assert not paco.Plan(256, 4096, 4, 16).has_split          # N1 != 4096
     assert not paco.Plan(1024, 4096, 4, 4).has_split
     assert paco.Plan(4096, 8192, 64, 2).has_split
@@ -237,7 +239,7 @@ def test_which_plans_split():
     paper = paco.PACO_PLAN_PAPER_LAYOUT
     assert not paco.Plan(4096, 256, 16, 16, flags=paper).has_split   # the paper's layouts: no fused pipeline
     assert not paco.Plan(16384, 64, 4, 4, flags=paper).has_split      # nor the long-column split form
-    assert not paco.Plan(8192, 1 << 11, 8, 8, flags=paper).has_split
+    assert not paco.Plan(8192, 1 << 11, 8, 2, flags=paper).has_split
     assert not paco.Plan(4096, 4096, 64, 16, flags=paco.PACO_PLAN_GENERIC).has_split
 
 
