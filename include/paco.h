@@ -204,6 +204,23 @@ paco_status paco_plan_workspace_size(const paco_plan *plan, size_t *bytes);
 paco_status paco_execute(const paco_plan *plan, const void *in, void *out, void *workspace,
                          size_t workspace_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * transform of paco_execute, with the workspace held in the library's own
+ * file-scope device array of PACO_NOALLOC_MAX_ITEMS complex64 items (32 MiB).
+ * Each GPU the library runs on holds one such array from the first plan
+ * created on it until the process ends; the plan records its address at
+ * creation.  The call allocates nothing (no hipMalloc, hipFree or allocating
+ * library routine); in and out are as for paco_execute (in == out allowed).
+ * Plans with N1*N2 above PACO_NOALLOC_MAX_ITEMS get PACO_ERR_WORKSPACE before
+ * anything is enqueued.  Every call on one GPU shares that GPU's array, which
+ * keeps the last call's contents (nothing in it needs clearing: every item is
+ * written before it is read): calls that can overlap in time on one GPU
+ * (streams without an order between them) race and their results are
+ * undefined; calls issued on one stream are ordered. */
+#define PACO_NOALLOC_MAX_ITEMS (1 << 22)
+paco_status paco_execute_noalloc(const paco_plan *plan, const void *in, void *out, void *stream);
+
 /* The inverse transform x = Omega_N^{-1} y, x[j] = (1/N) sum_k y[k] w_N^{+jk}
  * (the paper names the inverse in sections 1 and 5 without specifying it;
  * this is the textbook inverse of section 2's convention).  in = y in natural

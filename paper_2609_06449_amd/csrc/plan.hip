@@ -3,6 +3,7 @@
 // middle.hip.
 #include <cmath>
 #include <cstdio>
+#include <mutex>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -14,6 +15,12 @@
 
 using paco::LocalPass;
 using paco::MiddlePass;
+
+// The workspace of paco_execute_noalloc: one array per GPU, in device memory
+// for as long as the process runs.  In host code `scratch` is only a
+// stand-in for the symbol: its device address comes from
+// hipGetSymbolAddress, once per device, with that device current.
+static __device__ __align__(256) float2 scratch[PACO_NOALLOC_MAX_ITEMS];
 
 namespace {
 
@@ -42,6 +49,31 @@ int ilog2_exact(int64_t n)
 constexpr int kMaxLocalLog2 = 16;  // N1, N2 <= 2^16 (at most two on-chip passes)
 constexpr int kMaxTotalLog2 = 28;  // N1*N2 <= 2^28: every buffer < 4 GiB (32-bit byte offsets)
 
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Address of the current device's scratch array (looked up on the first call
+// for that device); nullptr with the reason in `err` on failure.
+void *scratch_for_device(int dev, std::string &err)
+{
+    if (dev < 0 || dev >= kMaxDevices) {
+        err = "device ordinal beyond the library's table";
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
 }  // namespace
 
 void paco::set_last_error(const std::string &msg) { g_last_error = msg; }
@@ -66,6 +98,8 @@ struct paco_plan_s {
     bool sym = false;                       // N1 = N2 = 4096: the symmetric split form (three passes)
     paco::SymPass sym_pass{};               // src/dst filled per execution
     paco_plan_s *inv = nullptr;             // N2 x N1 passes of the inverse (NULL: square, this plan's)
+    void *scratch = nullptr;                // this device's scratch array (paco_execute_noalloc)
+    std::string scratch_error;              // why scratch is NULL
     std::string inv_error;                  // non-empty: the inverse passes could not be built
     std::string desc;
 };
@@ -252,6 +286,9 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
     e = paco::local_fft_prepare();
     if (e == hipSuccess) e = paco::split_prepare();
     if (e != hipSuccess) { delete P; return hip_fail(e, "hipFuncSetAttribute"); }
+    // set-up of paco_execute_noalloc: this device's scratch array (a plan that
+    // cannot have it still works through the other entry points)
+    P->scratch = scratch_for_device(P->device, P->scratch_error);
     e = hipMalloc(&P->dev_tables, total);
     if (e != hipSuccess) { P->dev_tables = nullptr; delete P; return fail(PACO_ERR_ALLOC, std::string("hipMalloc: ") + hipGetErrorString(e)); }
     std::vector<unsigned char> staging(total, 0);
@@ -745,6 +782,17 @@ paco_status paco_execute(const paco_plan *plan, const void *in, void *out, void 
     paco_status st = check_buffers(plan, in, out, workspace, workspace_bytes);
     if (st != PACO_OK) return st;
     return run_three(plan, in, out, workspace, static_cast<hipStream_t>(stream), false);
+}
+
+paco_status paco_execute_noalloc(const paco_plan *plan, const void *in, void *out, void *stream)
+{
+    if (!plan) return fail(PACO_ERR_INVALID_ARG, "plan is NULL");
+    if (plan->N1 * plan->N2 > int64_t(PACO_NOALLOC_MAX_ITEMS))
+        return fail(PACO_ERR_WORKSPACE, "paco_execute_noalloc: N1*N2 above PACO_NOALLOC_MAX_ITEMS (2^22 items)");
+    if (!plan->scratch) return fail(PACO_ERR_HIP, "paco_execute_noalloc: no scratch array: " + plan->scratch_error);
+    paco_status st = check_buffers(plan, in, out, plan->scratch, size_t(PACO_NOALLOC_MAX_ITEMS) * 8);
+    if (st != PACO_OK) return st;
+    return run_three(plan, in, out, plan->scratch, static_cast<hipStream_t>(stream), false);
 }
 
 paco_status paco_execute_inverse(const paco_plan *plan, const void *in, void *out, void *workspace,

@@ -43,6 +43,9 @@ PACO_BATCH_NO_TUNE = 1
 PACO_BATCH_ONE_QUEUE = 2
 PACO_BATCH_SET_GAP = 4
 
+PACO_NOALLOC_MAX_ITEMS = 1 << 22
+
+
 class PlanOptions(ctypes.Structure):
     """paco_plan_options (include/paco.h): every field 0 = the default."""
     _fields_ = [("flags", ctypes.c_uint32), ("groups1", ctypes.c_int32), ("groups3", ctypes.c_int32),
@@ -56,7 +59,7 @@ class BatchOptions(ctypes.Structure):
 # every symbol include/paco.h declares
 EXPORTED = (
     "paco_plan_validate", "paco_plan_create", "paco_plan_validate_mixed", "paco_plan_create_mixed",
-    "paco_plan_create_ex", "paco_plan_workspace_size", "paco_execute",
+    "paco_plan_create_ex", "paco_plan_workspace_size", "paco_execute", "paco_execute_noalloc",
     "paco_execute_stage", "paco_execute_inverse", "paco_execute_two_pass", "paco_plan_has_two_pass", "paco_plan_has_split", "paco_plan_describe",
     "paco_plan_destroy", "paco_status_string",
     "paco_last_error", "paco_batch_plan_create", "paco_batch_plan_create_ex", "paco_batch_workspace_size",
@@ -91,6 +94,7 @@ def _load() -> ctypes.CDLL:
         "paco_plan_validate_mixed": (st, [i64, i64, i64, i32, st]),
         "paco_plan_create_mixed": (st, [ctypes.POINTER(P), i64, i64, i64, i32, st]),
         "paco_plan_create_ex": (st, [ctypes.POINTER(P), i64, i64, i64, i32, st, ctypes.POINTER(PlanOptions)]),
+        "paco_execute_noalloc": (st, [P, P, P, P]),
         "paco_plan_workspace_size": (st, [P, ctypes.POINTER(sz)]),
         "paco_execute": (st, [P, P, P, P, sz, P]),
         "paco_execute_stage": (st, [P, st, st, P, P, P]),
@@ -188,6 +192,10 @@ def paco_execute(plan: int, src: int, dst: int, workspace: int, workspace_bytes:
     _check(_lib.paco_execute(plan, src, dst, workspace, workspace_bytes, stream), "paco_execute")
 
 
+def paco_execute_noalloc(plan: int, src: int, dst: int, stream: int = 0):
+    _check(_lib.paco_execute_noalloc(plan, src, dst, stream), "paco_execute_noalloc")
+
+
 def paco_execute_stage(plan: int, stage: int, flags: int, src: int, dst: int, stream: int = 0):
     _check(_lib.paco_execute_stage(plan, stage, flags, src, dst, stream), "paco_execute_stage")
 
@@ -244,6 +252,9 @@ class Plan:
 
     def execute(self, src: int, dst: int, workspace: int, stream: int = 0):
         paco_execute(self.handle, src, dst, workspace, self.workspace_bytes, stream)
+
+    def execute_noalloc(self, src: int, dst: int, stream: int = 0):
+        paco_execute_noalloc(self.handle, src, dst, stream)
 
     def execute_inverse(self, src: int, dst: int, workspace: int, stream: int = 0):
         paco_execute_inverse(self.handle, src, dst, workspace, self.workspace_bytes, stream)

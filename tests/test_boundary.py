@@ -151,6 +151,12 @@ def test_batch_options_are_checked_before_any_device_call():
         assert st == paco.PACO_ERR_INVALID_ARG and not h.value
 
 
+def test_noalloc_entry_point_argument_checks():
+    lib = paco.lib()
+    assert lib.paco_execute_noalloc(None, None, None, None) == paco.PACO_ERR_INVALID_ARG
+    assert paco.PACO_NOALLOC_MAX_ITEMS == 1 << 22
+
+
 def test_no_plan_reads_the_environment():
     # plans depend on their arguments and options only (PACO_LOG=1 just prints)
     import glob
