@@ -41,7 +41,60 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "FFT GFLOP/s (5N·log2N/t) + % HBM roofline, N=2^24 c64; MFMA-split vs FP32"
 WORKLOAD = dict(name="2^24 as 4096 x 4096", N1=4096, N2=4096, p=64, b=16, gen="normal", seed=2)
 KERNEL_SOURCES = ["paper_2609_06449_amd/csrc/" + f for f in ("local_fft.hip", "middle.hip", "stages.h", "middle_dev.h",
-                                                                  "paco_internal.h", "split.hip", "sym.hip")]
+                                                                  "paco_internal.h", "split.hip", "sym.hip", "addr.h")]
+
+
+class HipEvents:
+    """Timing events of the HIP runtime the library runs on, recorded on the
+    stream the kernels are launched on.  Created with hipEventDisableSystemFence:
+    a default event's system-scope release writes back and invalidates the
+    caches at every record, which lengthened each phase that followed one
+    by several microseconds against the kernel trace (HIP accepts one
+    release-scope flag per event)."""
+
+    FLAGS = 0x20000000  # hipEventDisableSystemFence
+
+    def __init__(self):
+        import ctypes
+
+        path = None
+        with open("/proc/self/maps") as f:  # the copy torch loaded (one HIP runtime per process)
+            for line in f:
+                if "libamdhip64" in line:
+                    path = line.split()[-1]
+                    break
+        self.ct = ctypes
+        self.hip = ctypes.CDLL(path or "libamdhip64.so")
+        self.hip.hipEventCreateWithFlags.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint]
+        self.hip.hipEventRecord.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        self.hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+        self.hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        self.events = []
+
+    def new(self):
+        e = self.ct.c_void_p()
+        rc = self.hip.hipEventCreateWithFlags(self.ct.byref(e), self.FLAGS)
+        if rc != 0:
+            raise RuntimeError(f"hipEventCreateWithFlags failed ({rc})")
+        self.events.append(e)
+        return e
+
+    def record(self, e, stream: int):
+        rc = self.hip.hipEventRecord(e, self.ct.c_void_p(stream))
+        if rc != 0:
+            raise RuntimeError(f"hipEventRecord failed ({rc})")
+
+    def ms(self, a, b) -> float:
+        t = self.ct.c_float()
+        rc = self.hip.hipEventElapsedTime(self.ct.byref(t), a, b)
+        if rc != 0:
+            raise RuntimeError(f"hipEventElapsedTime failed ({rc})")
+        return t.value
+
+    def close(self):
+        for e in self.events:
+            self.hip.hipEventDestroy(e)
+        self.events = []
 
 
 def kernel_hash() -> str:
@@ -381,6 +434,9 @@ def main():
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-precision", action="store_true")
     ap.add_argument("--skip-large", action="store_true")
+    ap.add_argument("--skip-cold", action="store_true",
+                    help="no MALL-flushed launches (profiling runs: every traced launch is then a warm one)")
+    ap.add_argument("--skip-two-pass", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run plain 256 MiB device copies (traffic-counter calibration)")
@@ -436,24 +492,25 @@ def main():
     fused = plan.description.startswith("fused")
     fl = paco.PACO_SPLIT if plan.has_split else (paco.PACO_PACKED if fused else 0)
     fl3 = paco.PACO_SPLIT if plan.has_split == 2 else 0
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    hev = HipEvents()
+    ev = [[hev.new() for _ in range(4)] for _ in range(args.steps)]
     for i in range(args.steps):
         e = ev[i]
-        e[0].record(stream)
+        hev.record(e[0], sh)
         plan.execute_stage(1, xd.data_ptr(), ws.data_ptr(), sh, fl)
-        e[1].record(stream)
+        hev.record(e[1], sh)
         plan.execute_stage(2, ws.data_ptr(), out.data_ptr(), sh, fl)
-        e[2].record(stream)
+        hev.record(e[2], sh)
         plan.execute_stage(3, out.data_ptr(), out.data_ptr(), sh, fl3)
-        e[3].record(stream)
+        hev.record(e[3], sh)
     torch.cuda.synchronize()
-    ph = np.array([[ev[i][k].elapsed_time(ev[i][k + 1]) for k in range(3)] for i in range(args.steps)])
+    ph = np.array([[hev.ms(ev[i][k], ev[i][k + 1]) for k in range(3)] for i in range(args.steps)])
     ph_us = ph.mean(axis=0) * 1e3
 
     # ---- cold: a 1 GiB scratch write between transforms flushes the 256 MB MALL
     flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)
     cold = []
-    for i in range(min(args.steps, 50)):
+    for i in range(0 if args.skip_cold else min(args.steps, 50)):
         flush.fill_(float(i))
         a = torch.cuda.Event(enable_timing=True)
         z = torch.cuda.Event(enable_timing=True)
@@ -463,13 +520,13 @@ def main():
         torch.cuda.synchronize()
         cold.append(a.elapsed_time(z))
     del flush
-    cold_ms = float(np.median(cold))
+    cold_ms = float(np.median(cold)) if cold else None
 
     y = out.cpu().numpy()  # the three-pass output (out is reused below)
 
     # ---- two-pass form (Phase III reads the packed buffer, twiddle on load)
     two, y2 = None, None
-    if plan.has_two_pass:
+    if plan.has_two_pass and not args.skip_two_pass:
         def step2():
             plan.execute_two_pass(xd.data_ptr(), out.data_ptr(), ws.data_ptr(), sh)
 
@@ -550,8 +607,8 @@ def main():
                hbm_frac_3pass=round(48.0 * N / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                phase_us=[round(float(v), 2) for v in ph_us],
                phase_roofline=phase_roofline,
-               cold_ms_per_step=round(cold_ms, 5),
-               cold_hbm_frac_3pass=round(48.0 * N / (cold_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+               cold_ms_per_step=round(cold_ms, 5) if cold_ms else None,
+               cold_hbm_frac_3pass=round(48.0 * N / (cold_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if cold_ms else None,
                plan=plan.description)
     if two is not None:
         rec["two_pass"] = two
