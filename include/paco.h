@@ -183,8 +183,9 @@ paco_status paco_plan_workspace_size(const paco_plan *plan, size_t *bytes);
  * paco_plan_has_split tells; the plan option PACO_PLAN_NO_SPLIT keeps the
  * other plan.
  *
- * Symmetric split form.  A PACO_C64 plan with N1 = N2 = 4096 (any valid b
- * and p) splits Phase III the same way, with its 16-point child moved into
+ * Symmetric split form.  A plan with N1 = N2 = 4096 (any valid b and p,
+ * every dtype: the split MFMA forms run each 16-point transform on MFMA in
+ * the operand layout) splits Phase III the same way, with its 16-point child moved into
  * the redistribution pass (Lemma 1 on both local phases; Phase I:
  * j1 = 16 j + r, k1 = k + 256 s; Phase III: j2 = jc + 256 rr,
  * k2 = q0 + 16 q):

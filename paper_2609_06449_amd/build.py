@@ -18,6 +18,9 @@ HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall",
     # packed-FP32 instructions are left to no one: the compiler may not emit them
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA results in ordinary VGPRs: with accumulation registers every result
+    # took a v_accvgpr_read (128 per wave in a symmetric-split pass)
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
 ]
 
 

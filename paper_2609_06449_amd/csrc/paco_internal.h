@@ -195,6 +195,7 @@ struct SymPass {
     const float2 *tw_hi, *tw_lo;  // w_N^{-e} = tw_hi[e >> log2Lo] * tw_lo[e mod 2^log2Lo]
     int32_t log2N, log2Lo;
     const float2 *tw_sj;          // [s * 256 + jc] = w_{16 N2}^{-s jc}, s < 16, jc < 256
+    const float *w16;             // split MFMA forms: 64 lanes x 16 DFT-matrix operands (w16_operands)
     int32_t conj_in;              // pass 1: conjugate x on load (the inverse's input map)
     float out_scale;              // pass 3: nonzero stores conj(y) * out_scale (the inverse's output map)
 };
@@ -244,6 +245,11 @@ hipError_t split_prepare();  // raises the dynamic-LDS limit of the three-stage 
 hipError_t launch_sym_first(const SymPass &p, hipStream_t s);
 hipError_t launch_sym_middle(const SymPass &p, hipStream_t s);
 hipError_t launch_sym_last(const SymPass &p, hipStream_t s);
+// Pass 1, 2 or 3 of the symmetric split form with the radix-16 butterflies
+// on MFMA in split form prec (kPrecFP16x3, kPrecBF16x3, kPrecBF16x6; sym_mf.hip).
+hipError_t launch_sym_mf(int prec, int pass, const SymPass &p, hipStream_t s);
+// The radix-16 DFT-matrix operands of every MFMA lane (64 x 16 floats).
+void w16_operands(float *table);
 
 // Columns per workgroup for an on-chip pass of length 2^log2n over ncols.
 int32_t choose_log2T(int32_t log2n, int64_t ncols);

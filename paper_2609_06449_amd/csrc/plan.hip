@@ -247,6 +247,7 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
     // ---- host tables (FP64-generated, rounded once to FP32) ----------------
     const int64_t L = int64_t(1) << P->lL;
     std::vector<float2> tw(L), thi, tlo, ttile, stw, tcw, tsj;
+    std::vector<float> tw16;
     for (int64_t r = 0; r < L; ++r) tw[r] = paco::root_neg(r, L);
     // the two-pass form's column factor w_{16 N1}^{-k} (single-pass Phase III
     // over at most 2^12 columns: a table of at most 512 KiB)
@@ -256,13 +257,17 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
         for (int64_t k = 0; k < 16 * N1; ++k) tcw[k] = paco::root_neg(k, 16 * N1);
     }
     paco::middle_tables(P->lN, thi, tlo, ttile);
-    // the symmetric split form (FP32, N1 = N2 = 4096; option PACO_PLAN_NO_SYM)
-    const bool sym_form = !no_split && !no_sym && !paper_layout && !generic && dt == PACO_C64 &&
-                          P->l1 == paco::kSymLog2N && P->l2 == paco::kSymLog2N;
+    // the symmetric split form (N1 = N2 = 4096, every dtype; option PACO_PLAN_NO_SYM)
+    const bool sym_form = !no_split && !no_sym && !paper_layout && !generic && P->l1 == paco::kSymLog2N &&
+                          P->l2 == paco::kSymLog2N;
     if (sym_form) {  // its pass-2 factor w_{16 N2}^{-s jc}, s < 16, jc < 256
         tsj.resize(16 * 256);
         for (int64_t sv = 0; sv < 16; ++sv)
             for (int64_t jc = 0; jc < 256; ++jc) tsj[sv * 256 + jc] = paco::root_neg((sv * jc) % (16 * N2), 16 * N2);
+        if (dt != PACO_C64) {  // the MFMA lanes' DFT-matrix operands
+            tw16.resize(64 * 16);
+            paco::w16_operands(tw16.data());
+        }
     }
     int64_t stw_off[paco::kMaxOnChipLog2 + 1];
     if (!paco::stage_tables(stw, stw_off)) {
@@ -275,7 +280,7 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
     std::vector<Piece> pieces = {{tw.data(), tw.size() * 8, 0},       {thi.data(), thi.size() * 8, 0},
                                  {tlo.data(), tlo.size() * 8, 0},     {ttile.data(), ttile.size() * 8, 0},
                                  {stw.data(), stw.size() * 8, 0},     {tcw.data(), tcw.size() * 8, 0},
-                                 {tsj.data(), tsj.size() * 8, 0}};
+                                 {tsj.data(), tsj.size() * 8, 0},     {tw16.data(), tw16.size() * 4, 0}};
     size_t total = 0;
     for (auto &pc : pieces) {
         pc.off = total;
@@ -304,6 +309,7 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
     const float2 *d_stw = reinterpret_cast<const float2 *>(at(4));
     const float2 *d_tcw = reinterpret_cast<const float2 *>(at(5));
     const float2 *d_tsj = reinterpret_cast<const float2 *>(at(6));
+    const float *d_tw16 = reinterpret_cast<const float *>(at(7));
 
     auto base_pass = [&](int64_t ld, int64_t ncols, int log2n) {
         LocalPass q{};
@@ -535,6 +541,7 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
         q.log2N = P->lN;
         q.log2Lo = P->lLo;
         q.tw_sj = d_tsj;
+        q.w16 = d_tw16;
         P->sym = true;
     }
 
@@ -736,8 +743,10 @@ paco_status run_sym(const paco_plan *plan, int pass, const void *src, void *dst,
     q.dst = static_cast<float2 *>(dst);
     q.conj_in = inverse && pass == 1 ? 1 : 0;
     q.out_scale = inverse && pass == 3 ? 1.0f / float(plan->N1 * plan->N2) : 0.f;  // 2^-log2 N: exact
-    hipError_t e = pass == 1 ? paco::launch_sym_first(q, s)
-                             : (pass == 2 ? paco::launch_sym_middle(q, s) : paco::launch_sym_last(q, s));
+    hipError_t e = plan->dt != PACO_C64 ? paco::launch_sym_mf(int(plan->dt), pass, q, s)
+                   : pass == 1          ? paco::launch_sym_first(q, s)
+                   : pass == 2          ? paco::launch_sym_middle(q, s)
+                                        : paco::launch_sym_last(q, s);
     if (e != hipSuccess) return hip_fail(e, "symmetric split pass launch");
     return PACO_OK;
 }

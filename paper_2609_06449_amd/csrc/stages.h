@@ -175,7 +175,7 @@ typedef _Float16 mf_f16x8 __attribute__((ext_vector_type(8)));
 typedef float mf_f32x4 __attribute__((ext_vector_type(4)));
 
 // cos(2 pi r / 16) for any integer r: FP64 values rounded once to FP32.
-__device__ __forceinline__ float cos16(int r)
+__host__ __device__ __forceinline__ float cos16(int r)
 {
     const int a = r & 7;
     const float v = a == 0   ? 1.0f

@@ -39,14 +39,16 @@ namespace paco {
 namespace {
 
 constexpr int kSymThreads = 256;
-// LDS exchange buffers: 16 planes of 16 x 16 items.  Plane strides give
-// the minimum of two LDS cycles per wave access: 260 (= 4 mod 32 slots of
-// 8 bytes) where 16 lanes run across planes and 4 along a row, 272 (= 16 mod
-// 32) where 16 lanes run along a row and 4 across planes.  Pass 2 keeps
-// 256-item planes (32 KiB, five workgroups per CU) and swaps the row pairs
-// of odd planes instead (row a of plane m at a ^ (m & 1)), which gives the
-// same two cycles.
-constexpr int kPlaneK = 260;
+// LDS exchange buffers: 16 planes of 16 x 16 items.  The LDS serves a wave's
+// 8-byte accesses in two halves of 32 lanes, one 8-byte slot of 32 per lane
+// and cycle; the plane strides make every half-wave hit 32 distinct slots:
+// 258 (= 2 mod 32 slots) where a half-wave's 16 lanes run across planes and
+// 2 along a row (pass 1's stage-2 reads; 260 had measured 3.1M bank-conflict
+// cycles per launch), 272 (= 16 mod 32) where 16 lanes run along a row and
+// 2 across planes.  Pass 2 keeps 256-item planes (32 KiB, five workgroups
+// per CU) and swaps the row pairs of odd planes instead (row a of plane m at
+// a ^ (m & 1)), which gives the same.
+constexpr int kPlaneK = 258;
 constexpr int kPlaneR = 272;
 
 // w_M^{-m} for M = 2^log2M <= L from the table w_L^{-r}

@@ -48,6 +48,14 @@ def _stage(plan, stage, src, dst=None):
     return dst
 
 
+# the split MFMA forms and their bounds (see test_gpu_mfma.py)
+MFMA_FORMS = {
+    "fp16x3": (paco.PACO_C64_MFMA_FP16X3, 1e-6),
+    "bf16x3": (paco.PACO_C64_MFMA_BF16X3, 3e-5),
+    "bf16x6": (paco.PACO_C64_MFMA_BF16X6, 1e-6),
+}
+
+
 def _w(n, e):
     """w_n^{-e} in FP64 from the exact integer exponent."""
     return np.exp(-2j * np.pi * (np.asarray(e, dtype=np.int64) % n) / n)
@@ -67,8 +75,9 @@ def test_plan_takes_the_symmetric_form():
     plan = paco.Plan(N1, N2, 64, 16)
     assert plan.has_split == 2 and plan.description.startswith("sym["), plan.description
     assert plan.launches == 3
-    for dt in (paco.PACO_C64_MFMA_FP16X3, paco.PACO_C64_MFMA_BF16X6):
-        assert paco.Plan(N1, N2, 64, 16, dt).has_split != 2      # FP32 only
+    for dt in MFMA_FORMS.values():                                 # every dtype
+        mp = paco.Plan(N1, N2, 64, 16, dt[0])
+        assert mp.has_split == 2 and mp.launches == 3, mp.description
     assert paco.Plan(N1, 2048, 64, 16, mixed=True).has_split != 2  # N1 = N2 = 4096 only
     for fl in (paco.PACO_PLAN_NO_SYM, paco.PACO_PLAN_NO_SPLIT, paco.PACO_PLAN_PAPER_LAYOUT, paco.PACO_PLAN_GENERIC):
         assert paco.Plan(N1, N2, 64, 16, flags=fl).has_split != 2
@@ -203,3 +212,42 @@ def test_stage_flag_errors():
     out = torch.empty_like(buf)
     assert lib.paco_execute_stage(old.handle, 3, paco.PACO_SPLIT, buf.data_ptr(), out.data_ptr(), s) == \
         paco.PACO_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("form", sorted(MFMA_FORMS))
+def test_mfma_passes_against_the_fp32_passes(form):
+    # each pass of an MFMA form on the same seeded input as the FP32 pass
+    # (whose passes are checked against the oracle above), within the
+    # form's bound; log-uniform magnitudes stress the split
+    dt, tol = MFMA_FORMS[form]
+    fp32 = paco.Plan(N1, N2, 64, 16)
+    mf = paco.Plan(N1, N2, 64, 16, dt)
+    for stage, seed in ((1, 85), (2, 86), (3, 87)):
+        src = _dev(inputs.loguniform(N, seed=seed))
+        a = _stage(fp32, stage, src).cpu().numpy()
+        b = _stage(mf, stage, src).cpu().numpy()
+        err = oracle.rel_l2(b, a)
+        print(f"{form} pass {stage}: rel-L2 against the FP32 pass {err:.3e}", flush=True)
+        assert err <= tol, (stage, err)
+
+
+@pytest.mark.parametrize("form", sorted(MFMA_FORMS))
+def test_mfma_stage_hooks_compose_in_place_and_inverse(form):
+    dt, tol = MFMA_FORMS[form]
+    x = inputs.loguniform(N, seed=88)
+    xd = _dev(x)
+    plan = paco.Plan(N1, N2, 64, 16, dt)
+    u = _stage(plan, 1, xd)
+    w = _stage(plan, 2, u)
+    _stage(plan, 3, w, dst=w)
+    y = _execute(plan, xd).cpu().numpy()
+    assert np.array_equal(w.cpu().numpy().view(np.uint64), y.view(np.uint64))
+    buf = xd.clone()
+    _execute(plan, buf, out=buf)
+    assert np.array_equal(buf.cpu().numpy().view(np.uint64), y.view(np.uint64))
+    ref = oracle.fft_radix2(x, threads=oracle.cpu_threads())
+    assert oracle.rel_l2(y, ref) <= tol
+    back = _execute(plan, _dev(ref), fn=plan.execute_inverse).cpu().numpy()
+    err = oracle.rel_l2(back, x)
+    print(f"{form} inverse of the oracle's output: rel-L2 vs x {err:.3e}", flush=True)
+    assert err <= 2 * tol
