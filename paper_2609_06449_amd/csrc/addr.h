@@ -163,6 +163,44 @@ PACO_HD uint32_t sym1_groups(uint32_t N2) { return 16u * (N2 >> 4); }
 PACO_HD uint32_t sym2_groups(uint32_t N1, uint32_t N2) { return (N2 >> 4) * (N1 >> 8); }
 PACO_HD uint32_t sym3_groups(uint32_t N1) { return 16u * (N1 >> 4); }
 
+// Exchange buffers of the MFMA passes (sym_mf.hip): 16 rows of 256 items.
+// Stage-1 results: lane (n, kb) stores output i of group j, logical row
+// 4 kb + i, column 16 j + n (8-byte stores; a half-wave covers two rows).
+// Stage-2 operands, one component per 4-byte load: pass 1 lane (n, half)
+// loads operand i of group c (row n, column 16 (8 half + i) + c); passes 2
+// and 3 lane (n, half) of group row g load row g, column 16 (8 half + i) + n.
+// Pass 1 (loads across rows): item (row, col) at row * 260 + col + (col >>
+// 7) + 2 (row >> 3 & 1); pass 3: row * 260 + (col ^ 16 (col >> 7)); both
+// 4160 items (at most four workgroups per CU, which measured faster for
+// these two passes than five).  Pass 2: row * 256 + (col ^ 16 b), b = bit 2
+// of row xor bit 7 of col, 4096 items (32 KiB: five workgroups per CU).
+// Every store half-wave hits 32 distinct 8-byte slots, every load wave 64
+// distinct banks; each lane's addresses are one or two bases plus
+// compile-time offsets (i and j are unrolled constants).
+constexpr int kMf1Items = 16 * 260;  // passes 1 and 3
+PACO_HD int mf1_store(int kb, int i, int j, int n)
+{
+    return (4 * kb + i) * 260 + 2 * (kb >> 1) + 16 * j + (j >> 3) + n;
+}
+PACO_HD int mf1_load(int n, int half, int i, int c) { return n * 260 + 2 * (n >> 3) + 129 * half + 16 * i + c; }
+PACO_HD int mf3_store(int kb, int i, int j, int n) { return (4 * kb + i) * 260 + ((16 * j) ^ (16 * (j >> 3))) + n; }
+PACO_HD int mf3_load(int g, int half, int i, int n)
+{
+    const int b0 = g * 260 + 144 * half + n;
+    return ((i & 1) ? b0 - 32 * half : b0) + 16 * i;
+}
+PACO_HD int mf2_store(int kb, int i, int j, int n)
+{
+    const int f = (kb ^ (j >> 3)) & 1;
+    return (4 * kb + i) * 256 + 16 * j + ((j & 1) ? -16 * f : 16 * f) + n;
+}
+PACO_HD int mf2_load(int g, int half, int i, int n)
+{
+    const int f = ((g >> 2) ^ half) & 1;
+    const int b0 = g * 256 + 128 * half + n + 16 * f;
+    return ((i & 1) ? b0 - 32 * f : b0) + 16 * i;
+}
+
 // ---- the split form of Phase I (split.hip), N1 = 16 M -------------------------
 
 // pass 1: workgroup (cg, jg) = (blk mod (N2/16), blk / (N2/16)), 256

@@ -201,30 +201,117 @@ struct MfSplit<kPrecFP16x3> {
     T h, m, l;
 };
 
+typedef __bf16 mf_bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 mf_f16x2 __attribute__((ext_vector_type(2)));
+typedef float mf_f32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t mf_u32x4 __attribute__((ext_vector_type(4)));
+
+// Two FP32 values rounded (to nearest even) into one packed BF16 pair; the
+// rounded values back in FP32 are the pair's halves moved into the upper 16
+// bits, so one conversion, one shift and one mask per pair.
+__device__ __forceinline__ uint32_t bf16_pair(float a, float b, float &ra, float &rb)
+{
+    const mf_f32x2 v = {a, b};
+    const uint32_t p = __builtin_bit_cast(uint32_t, __builtin_convertvector(v, mf_bf16x2));
+    ra = __uint_as_float(p << 16);
+    rb = __uint_as_float(p & 0xffff0000u);
+    return p;
+}
+__device__ __forceinline__ uint32_t bf16_pair(float a, float b)
+{
+    const mf_f32x2 v = {a, b};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, mf_bf16x2));
+}
+
+// 16-bit parts of 8 values (see above).  FP16x3 takes x 2^-e (e: the
+// butterfly's power-of-two scale, applied here): hi = f16(x 2^-e) and
+// lo = f16(x 2^(11-e) - 2^11 hi), the subtraction one mixed-precision FMA on
+// the packed hi part.  BF16: hi = bf16(x), the remainders split again.
 template <int PREC>
-__device__ __forceinline__ MfSplit<PREC> mf_split(const float (&x)[8])
+__device__ __forceinline__ MfSplit<PREC> mf_split(const float (&x)[8], int e = 0)
 {
     MfSplit<PREC> s;
+    if constexpr (PREC == kPrecFP16x3) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        if constexpr (PREC == kPrecFP16x3) {
-            const _Float16 h = (_Float16)x[i];
-            s.h[i] = h;
-            s.l[i] = (_Float16)((x[i] - (float)h) * 2048.0f);
-        } else {
-            const __bf16 h = (__bf16)x[i];
-            const float r = x[i] - (float)h;
-            s.h[i] = h;
-            if constexpr (PREC == kPrecBF16x6) {
-                const __bf16 m = (__bf16)r;
-                s.m[i] = m;
-                s.l[i] = (__bf16)(r - (float)m);
-            } else {
-                s.l[i] = (__bf16)r;
-            }
+        for (int i = 0; i < 4; ++i) {
+            const mf_f32x2 y = {ldexpf(x[2 * i], -e), ldexpf(x[2 * i + 1], -e)};
+            const float z0 = ldexpf(x[2 * i], 11 - e), z1 = ldexpf(x[2 * i + 1], 11 - e);
+            const mf_f16x2 h = __builtin_convertvector(y, mf_f16x2);
+            const mf_f32x2 r = {__builtin_fmaf(float(h[0]), -2048.0f, z0), __builtin_fmaf(float(h[1]), -2048.0f, z1)};
+            const mf_f16x2 l = __builtin_convertvector(r, mf_f16x2);
+            s.h[2 * i] = h[0];
+            s.h[2 * i + 1] = h[1];
+            s.l[2 * i] = l[0];
+            s.l[2 * i + 1] = l[1];
         }
+    } else {
+        mf_u32x4 hw, mw, lw;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            float h0, h1;
+            hw[i] = bf16_pair(x[2 * i], x[2 * i + 1], h0, h1);
+            float r0 = x[2 * i] - h0, r1 = x[2 * i + 1] - h1;
+            if constexpr (PREC == kPrecBF16x6) {
+                float m0, m1;
+                mw[i] = bf16_pair(r0, r1, m0, m1);
+                r0 -= m0;
+                r1 -= m1;
+            }
+            lw[i] = bf16_pair(r0, r1);
+        }
+        s.h = __builtin_bit_cast(mf_bf16x8, hw);
+        if constexpr (PREC == kPrecBF16x6) s.m = __builtin_bit_cast(mf_bf16x8, mw);
+        s.l = __builtin_bit_cast(mf_bf16x8, lw);
     }
     return s;
+}
+
+// Cross-lane exchanges of the operand layout, on the vector ALU
+// (v_permlane32_swap / v_permlane16_swap: the upper 32 (16) lanes of the first
+// operand trade places with the lower 32 (16) lanes of the second).
+__device__ __forceinline__ void swap32(float &a, float &b)
+{
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    a = __uint_as_float(r[0]);
+    b = __uint_as_float(r[1]);
+}
+// max over lanes l, l ^ 16, l ^ 32, l ^ 48
+__device__ __forceinline__ float max_over_kb(float v)
+{
+    const auto a = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    v = fmaxf(__uint_as_float(a[0]), __uint_as_float(a[1]));
+    const auto b = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+    return fmaxf(__uint_as_float(b[0]), __uint_as_float(b[1]));
+}
+
+// Stage-0 operands of one group from four whole items per lane: lanes
+// l < 32 loaded items q = 0..3 of their 8, lanes l + 32 items 4..7 (it[k]:
+// item (l < 32 ? k : 4 + k)); afterwards x[k], x[4 + k] are the real parts
+// (l < 32) or the imaginary parts (l >= 32) of items k and 4 + k.
+__device__ __forceinline__ void mf_swap_in(const float2 (&it)[4], float (&x)[8])
+{
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        float a = it[k].x, b = it[k].y;
+        swap32(a, b);
+        x[k] = a;
+        x[4 + k] = b;
+    }
+}
+
+// FP16x3: the exponent e with amax 2^-e in [1/2, 1) for the butterfly's 32
+// reals (lanes n, n + 16, n + 32, n + 48); 0 for an all-zero butterfly.
+// e >= -100 keeps 2^-e and 2^(11-e) finite for butterflies of subnormal
+// values (they then stay below 1/2, which loses nothing).
+__device__ __forceinline__ int mf_scale_exp(const float (&x)[8])
+{
+    float amax = 0.f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) amax = fmaxf(amax, fabsf(x[i]));
+    amax = max_over_kb(amax);
+    int e = 0;
+    if (amax > 0.f) (void)frexpf(amax, &e);
+    return e < -100 ? -100 : e;
 }
 
 __device__ __forceinline__ mf_f32x4 mf_mma(mf_bf16x8 a, mf_bf16x8 b, mf_f32x4 c)
@@ -681,13 +768,7 @@ __device__ __forceinline__ void mf_tile(const float2 *srcm, float2 *dstm, uint32
             }
         }
 #pragma unroll
-        for (int G = 0; G < 4; ++G)
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const float recv = __shfl_xor(comp ? it[G][k].x : it[G][k].y, 32);
-                xin[G][k] = comp ? recv : it[G][k].x;
-                xin[G][4 + k] = comp ? it[G][k].y : recv;
-            }
+        for (int G = 0; G < 4; ++G) mf_swap_in(it[G], xin[G]);
     }
     if (conj_in && comp == 1) {  // the inverse transform's input map: negate the imaginary parts
 #pragma unroll
@@ -719,20 +800,9 @@ __device__ __forceinline__ void mf_tile(const float2 *srcm, float2 *dstm, uint32
                     xin[G][i] = reinterpret_cast<const float *>(lds + lpad((row << LT) + t))[comp];
                 }
             }
-            int e = 0;
-            if constexpr (PREC == kPrecFP16x3) {
-                // per-butterfly power-of-two scale: the column's 32 reals sit in
-                // lanes n, n + 16, n + 32, n + 48
-                float amax = 0.f;
-#pragma unroll
-                for (int i = 0; i < 8; ++i) amax = fmaxf(amax, fabsf(xin[G][i]));
-                amax = fmaxf(amax, __shfl_xor(amax, 16));
-                amax = fmaxf(amax, __shfl_xor(amax, 32));
-                if (amax > 0.f) (void)frexpf(amax, &e);
-#pragma unroll
-                for (int i = 0; i < 8; ++i) xin[G][i] = ldexpf(xin[G][i], -e);
-            }
-            const MfSplit<PREC> B = mf_split<PREC>(xin[G]);
+            // FP16x3: per-butterfly power-of-two scale (the column's 32 reals)
+            const int e = PREC == kPrecFP16x3 ? mf_scale_exp(xin[G]) : 0;
+            const MfSplit<PREC> B = mf_split<PREC>(xin[G], e);
             const mf_f32x4 yr = mf_product<PREC>(Ar, B);
             const mf_f32x4 yi = mf_product<PREC>(Ai, B);
 #pragma unroll

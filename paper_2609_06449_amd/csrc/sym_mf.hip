@@ -23,9 +23,9 @@
 namespace paco {
 namespace {
 
-constexpr int kPlaneK = 260;  // the exchange layouts of sym.hip
-constexpr int kPlaneR = 272;
-
+// Exchange buffers addressed by addr::mf1_*, mf2_* and mf3_* (passes 1, 2
+// and 3): bank-conflict free for the stores of stage-1 results and the
+// component loads of stage 2.
 __device__ __forceinline__ float2 root_of(const float2 *tw, int log2L, int log2M, uint32_t m)
 {
     return tw[(m & ((1u << log2M) - 1u)) << (log2L - log2M)];
@@ -52,20 +52,10 @@ struct MfW16 {
     // outputs m = 4 kb + i.  FP16x3: the butterfly's 32 reals (lanes n,
     // n + 16, n + 32, n + 48) are scaled by one power of two into [1/2, 1)
     // and back (exact).
-    __device__ __forceinline__ void dft(float (&x)[8], float2 (&o)[4]) const
+    __device__ __forceinline__ void dft(const float (&x)[8], float2 (&o)[4]) const
     {
-        int e = 0;
-        if constexpr (PREC == kPrecFP16x3) {
-            float amax = 0.f;
-#pragma unroll
-            for (int i = 0; i < 8; ++i) amax = fmaxf(amax, fabsf(x[i]));
-            amax = fmaxf(amax, __shfl_xor(amax, 16));
-            amax = fmaxf(amax, __shfl_xor(amax, 32));
-            if (amax > 0.f) (void)frexpf(amax, &e);
-#pragma unroll
-            for (int i = 0; i < 8; ++i) x[i] = ldexpf(x[i], -e);
-        }
-        const MfSplit<PREC> B = mf_split<PREC>(x);
+        const int e = PREC == kPrecFP16x3 ? mf_scale_exp(x) : 0;
+        const MfSplit<PREC> B = mf_split<PREC>(x, e);
         const mf_f32x4 yr = mf_product<PREC>(Ar, B), yi = mf_product<PREC>(Ai, B);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -75,18 +65,11 @@ struct MfW16 {
     }
 };
 
-// Stage-0 operands of one group from four whole items per lane: it[k] is
-// item 8 (kb & 1) + (comp ? 4 + k : k) of the lane's butterfly; the pair l,
-// l ^ 32 swaps components.  conj: the inverse's input map (negate the
-// imaginary parts).
-__device__ __forceinline__ void mf_swap_in(const float2 (&it)[4], float (&x)[8], int comp, bool conj)
+// Stage-0 operands of one group (mf_swap_in); conj: the inverse's input map
+// (negate the imaginary parts, held by lanes l >= 32).
+__device__ __forceinline__ void mf_load_ops(const float2 (&it)[4], float (&x)[8], int comp, bool conj)
 {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const float recv = __shfl_xor(comp ? it[k].x : it[k].y, 32);
-        x[k] = comp ? recv : it[k].x;
-        x[4 + k] = comp ? it[k].y : recv;
-    }
+    mf_swap_in(it, x);
     if (conj && comp) {
 #pragma unroll
         for (int i = 0; i < 8; ++i) x[i] = -x[i];
@@ -98,8 +81,8 @@ __device__ __forceinline__ void mf_swap_in(const float2 (&it)[4], float (&x)[8],
 template <int PREC>
 __global__ __launch_bounds__(256) void sym_first_mf_kernel(SymPass P)
 {
-    __shared__ float2 lds[16 * kPlaneK];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    __shared__ float2 lds[addr::kMf1Items];
+    const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n = lane & 15, kb = lane >> 4, comp = kb >> 1, half = kb & 1;
     const uint32_t N2 = uint32_t(P.N2);
     const uint32_t r = blockIdx.x / (N2 >> 4);
@@ -114,35 +97,41 @@ __global__ __launch_bounds__(256) void sym_first_mf_kernel(SymPass P)
             for (int k = 0; k < 4; ++k) it[G][k] = src[addr::sym1_load_off(N2, uint32_t(8 * half + (comp ? 4 + k : k)))];
         }
 #pragma unroll
-        for (int G = 0; G < 4; ++G) mf_swap_in(it[G], x[G], comp, P.conj_in != 0);
+        for (int G = 0; G < 4; ++G) mf_load_ops(it[G], x[G], comp, P.conj_in != 0);
     }
+    // every twiddle loaded right behind the data (LDS caps the kernel at four
+    // waves per SIMD, so the registers are there): stage 1's w_256^{-jl m}
+    // and the outputs' w_N1^{-k r}, k = n + 16 kh, kh = 4 kb + i
+    float2 t1[4][4], t2[4];
+#pragma unroll
+    for (int G = 0; G < 4; ++G)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) t1[G][i] = root_of(P.tw, P.log2L, 8, uint32_t((4 * w + G) * (4 * kb + i)));
+    const float2 a = root_of(P.tw, P.log2L, 12, uint32_t(n) * r);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) t2[i] = root_of(P.tw, P.log2L, 12, 16u * uint32_t(4 * kb + i) * r);
     float2 o[4][4];
 #pragma unroll
     for (int G = 0; G < 4; ++G) {
         W.dft(x[G], o[G]);
         const int jl = 4 * w + G;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int m = 4 * kb + i;
-            lds[m * kPlaneK + jl * 16 + n] = cmul(o[G][i], root_of(P.tw, P.log2L, 8, uint32_t(jl * m)));
-        }
+        for (int i = 0; i < 4; ++i) lds[addr::mf1_store(kb, i, jl, n)] = cmul(o[G][i], t1[G][i]);
     }
     __syncthreads();
+    const float *ldf = reinterpret_cast<const float *>(lds) + comp;
 #pragma unroll
     for (int G = 0; G < 4; ++G) {
         const int cl2 = 4 * w + G;
 #pragma unroll
-        for (int i = 0; i < 8; ++i)
-            x[G][i] = reinterpret_cast<const float *>(&lds[n * kPlaneK + (8 * half + i) * 16 + cl2])[comp];
+        for (int i = 0; i < 8; ++i) x[G][i] = ldf[2 * addr::mf1_load(n, half, i, cl2)];
         W.dft(x[G], o[G]);
     }
-    // outputs kh = 4 kb + i of butterfly (kl = n, c = 16 cb + cl2), times
-    // w_N1^{-k r}, k = n + 16 kh
-    const float2 a = root_of(P.tw, P.log2L, 12, uint32_t(n) * r);
+    // outputs kh = 4 kb + i of butterfly (kl = n, c = 16 cb + cl2)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const uint32_t kh = uint32_t(4 * kb + i);
-        const float2 t = cmul(a, root_of(P.tw, P.log2L, 12, 16u * kh * r));
+        const float2 t = cmul(a, t2[i]);
 #pragma unroll
         for (int G = 0; G < 4; ++G) {
             float2 *d = P.dst + addr::sym1_store_base(N2, blockIdx.x, uint32_t(n + 16 * (4 * w + G)));
@@ -152,61 +141,76 @@ __global__ __launch_bounds__(256) void sym_first_mf_kernel(SymPass P)
 }
 
 // Pass 2: stage 1 butterfly (kk = n, rr = 4 w + G) over r, stage 2 butterfly
-// (kk = n, s = 4 w + G) over rr.
+// (kk = n, s = 4 w + G) over rr.  The twiddle of stage-1 output s of group G
+// is w_N^{-c (k + 256 s)}, c = jc + 256 rr, s = 4 kb + i: the first (i = 0)
+// from the two-level table, each next one times w_65536^{-c}, which is the
+// same for the whole wave (scalar loads).  That keeps the twiddle loads few
+// (one pair per group) and issued right behind the data loads; with one
+// lookup per output the compiler spread 32 loads, each waited for, between
+// the butterflies.
 template <int PREC>
-__global__ __launch_bounds__(256) void sym_middle_mf_kernel(SymPass P)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == kPrecBF16x6 ? 4 : 5))) void sym_middle_mf_kernel(SymPass P)
 {
     __shared__ float2 lds[16 * 256];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n = lane & 15, kb = lane >> 4, comp = kb >> 1, half = kb & 1;
     const uint32_t N1 = uint32_t(P.N1), N2 = uint32_t(P.N2);
     const uint32_t blk = addr::sym2_block(blockIdx.x);
     const uint32_t jc = blk >> 4, k = 16u * (blk & 15) + n;
-    const MfW16<PREC> W(P.w16, lane);
-    float x[4][8];
-    {
-        float2 it[4][4];
+    float2 it[4][4];
 #pragma unroll
-        for (int G = 0; G < 4; ++G) {
-            const float2 *src = P.src + addr::sym2_load_base(N2, blk, uint32_t(n + 16 * (4 * w + G)));
+    for (int G = 0; G < 4; ++G) {
+        const float2 *src = P.src + addr::sym2_load_base(N2, blk, uint32_t(n + 16 * (4 * w + G)));
 #pragma unroll
-            for (int q = 0; q < 4; ++q) it[G][q] = ld2_last(src + addr::sym2_load_off(uint32_t(8 * half + (comp ? 4 + q : q))));
-        }
-#pragma unroll
-        for (int G = 0; G < 4; ++G) mf_swap_in(it[G], x[G], comp, false);
+        for (int q = 0; q < 4; ++q) it[G][q] = ld2_last(src + addr::sym2_load_off(uint32_t(8 * half + (comp ? 4 + q : q))));
     }
     const uint32_t nmask = uint32_t((uint64_t(1) << P.log2N) - 1), lomask = (1u << P.log2Lo) - 1u;
+    float2 th[4], tl[4];  // w_N^{-c (k + 1024 kb)} as its two table factors
+#pragma unroll
+    for (int G = 0; G < 4; ++G) {
+        const uint32_t c = jc + 256u * uint32_t(4 * w + G);
+        const uint32_t e = (c * (k + 1024u * uint32_t(kb))) & nmask;
+        th[G] = P.tw_hi[e >> P.log2Lo];
+        tl[G] = P.tw_lo[e & lomask];
+    }
+    const MfW16<PREC> W(P.w16, lane);
+    float x[4][8];
+#pragma unroll
+    for (int G = 0; G < 4; ++G) mf_swap_in(it[G], x[G]);
+    const float2 sj = P.tw_sj[256 + jc];  // w_65536^{-jc}
     float2 o[4][4];
 #pragma unroll
     for (int G = 0; G < 4; ++G) {
         W.dft(x[G], o[G]);
-        const uint32_t rr = uint32_t(4 * w + G), c = jc + 256u * rr;
-        const uint32_t e1 = (k * c) & nmask;
-        const float2 t1 = cmul(P.tw_hi[e1 >> P.log2Lo], P.tw_lo[e1 & lomask]);  // w_N^{-k c}
+        const int rr = 4 * w + G;
+        const float2 step = cmul(sj, root_of(P.tw, P.log2L, 8, uint32_t(rr)));  // w_65536^{-c}
+        float2 t = cmul(th[G], tl[G]);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int s = 4 * kb + i;
-            const float2 t = cmul(t1, cmul(P.tw_sj[s * 256 + jc], root_of(P.tw, P.log2L, 8, uint32_t(s) * rr)));
-            lds[s * 256 + ((int(rr) ^ (s & 1)) << 4) + n] = cmul(o[G][i], t);
+            lds[addr::mf2_store(kb, i, rr, n)] = cmul(o[G][i], t);
+            if (i < 3) t = cmul(t, step);
         }
     }
     __syncthreads();
+    float2 t4[4];  // w_N2^{-q0 jc}, q0 = 4 kb + i
+#pragma unroll
+    for (int i = 0; i < 4; ++i) t4[i] = root_of(P.tw, P.log2L, 12, uint32_t(4 * kb + i) * jc);
+    const float *ldf = reinterpret_cast<const float *>(lds) + comp;
 #pragma unroll
     for (int G = 0; G < 4; ++G) {
         const int s2 = 4 * w + G;
 #pragma unroll
-        for (int i = 0; i < 8; ++i)
-            x[G][i] = reinterpret_cast<const float *>(&lds[s2 * 256 + (((8 * half + i) ^ (s2 & 1)) << 4) + n])[comp];
+        for (int i = 0; i < 8; ++i) x[G][i] = ldf[2 * addr::mf2_load(s2, half, i, n)];
         W.dft(x[G], o[G]);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const uint32_t q0 = uint32_t(4 * kb + i);
-        const float2 t4 = root_of(P.tw, P.log2L, 12, q0 * jc);  // w_N2^{-q0 jc}
 #pragma unroll
         for (int G = 0; G < 4; ++G) {
             float2 *d = P.dst + addr::sym2_store_base(N1, blk, uint32_t(n + 16 * (4 * w + G)));
-            d[addr::sym2_store_off(N1, q0)] = q0 ? cmul(o[G][i], t4) : o[G][i];
+            d[addr::sym2_store_off(N1, q0)] = q0 ? cmul(o[G][i], t4[i]) : o[G][i];
         }
     }
 }
@@ -216,8 +220,8 @@ __global__ __launch_bounds__(256) void sym_middle_mf_kernel(SymPass P)
 template <int PREC>
 __global__ __launch_bounds__(256) void sym_last_mf_kernel(SymPass P)
 {
-    __shared__ float2 lds[16 * kPlaneR];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    __shared__ float2 lds[addr::kMf1Items];
+    const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n = lane & 15, kb = lane >> 4, comp = kb >> 1, half = kb & 1;
     const uint32_t N1 = uint32_t(P.N1);
     const MfW16<PREC> W(P.w16, lane);
@@ -231,26 +235,28 @@ __global__ __launch_bounds__(256) void sym_last_mf_kernel(SymPass P)
             for (int q = 0; q < 4; ++q) it[G][q] = src[addr::sym3_load_off(N1, uint32_t(8 * half + (comp ? 4 + q : q)))];
         }
 #pragma unroll
-        for (int G = 0; G < 4; ++G) mf_swap_in(it[G], x[G], comp, false);
+        for (int G = 0; G < 4; ++G) mf_swap_in(it[G], x[G]);
     }
+    float2 t1[4][4];  // w_256^{-jl m}, loaded right behind the data (as in pass 1)
+#pragma unroll
+    for (int G = 0; G < 4; ++G)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) t1[G][i] = root_of(P.tw, P.log2L, 8, uint32_t((4 * w + G) * (4 * kb + i)));
     float2 o[4][4];
 #pragma unroll
     for (int G = 0; G < 4; ++G) {
         W.dft(x[G], o[G]);
         const int jl = 4 * w + G;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int m = 4 * kb + i;
-            lds[m * kPlaneR + jl * 16 + n] = cmul(o[G][i], root_of(P.tw, P.log2L, 8, uint32_t(jl * m)));
-        }
+        for (int i = 0; i < 4; ++i) lds[addr::mf3_store(kb, i, jl, n)] = cmul(o[G][i], t1[G][i]);
     }
     __syncthreads();
+    const float *ldf = reinterpret_cast<const float *>(lds) + comp;
 #pragma unroll
     for (int G = 0; G < 4; ++G) {
         const int kl = 4 * w + G;
 #pragma unroll
-        for (int i = 0; i < 8; ++i)
-            x[G][i] = reinterpret_cast<const float *>(&lds[kl * kPlaneR + (8 * half + i) * 16 + n])[comp];
+        for (int i = 0; i < 8; ++i) x[G][i] = ldf[2 * addr::mf3_load(kl, half, i, n)];
         W.dft(x[G], o[G]);
     }
 #pragma unroll

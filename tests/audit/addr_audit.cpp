@@ -209,11 +209,67 @@ void audit_digit_maps()
 
 }  // namespace
 
+// The MFMA passes' LDS exchange buffers (16 rows of 256 logical items): the
+// stage-1 stores of 4 waves x 4 groups x 4 outputs x 64 lanes fill every slot
+// once, inside the buffer; every stage-2 component load reads the slot its
+// logical item was stored to; and (the layouts' purpose) every store
+// half-wave covers 32 distinct 8-byte slots, every load wave 64 distinct
+// 4-byte banks.
+template <class Store, class Load>
+void audit_mf_exchange(const char *name, int items, Store store, Load load, bool load_across_rows)
+{
+    std::vector<int> at(items, -1);  // logical item (row * 256 + col) per slot
+    std::vector<int> slot_of(16 * 256, -1);
+    for (int w = 0; w < 4; ++w)
+        for (int G = 0; G < 4; ++G)
+            for (int i = 0; i < 4; ++i) {
+                const int j = 4 * w + G;
+                int slots[64];
+                for (int l = 0; l < 64; ++l) {
+                    const int n = l & 15, kb = l >> 4;
+                    const int a = store(kb, i, j, n);
+                    CHECK(a >= 0 && a < items, "%s: store %d outside %d items", name, a, items);
+                    CHECK(at[a] < 0, "%s: slot %d stored twice", name, a);
+                    const int logical = (4 * kb + i) * 256 + 16 * j + n;
+                    at[a] = logical;
+                    slot_of[logical] = a;
+                    slots[l] = a & 31;
+                }
+                for (int h = 0; h < 2; ++h) {
+                    uint32_t seen = 0;
+                    for (int l = 32 * h; l < 32 * h + 32; ++l) seen |= 1u << slots[l];
+                    CHECK(seen == 0xffffffffu, "%s: store half-wave %d of (w %d, G %d, i %d) shares a slot", name, h, w,
+                          G, i);
+                }
+            }
+    for (int w = 0; w < 4; ++w)
+        for (int G = 0; G < 4; ++G)
+            for (int i = 0; i < 8; ++i) {
+                const int g = 4 * w + G;
+                uint64_t banks = 0;
+                for (int l = 0; l < 64; ++l) {
+                    const int n = l & 15, kb = l >> 4, half = kb & 1, comp = kb >> 1;
+                    const int a = load(load_across_rows ? n : g, half, i, load_across_rows ? g : n);
+                    const int logical =
+                        load_across_rows ? n * 256 + 16 * (8 * half + i) + g : g * 256 + 16 * (8 * half + i) + n;
+                    CHECK(a >= 0 && a < items && at[a] == logical, "%s: load (w %d, G %d, i %d, lane %d) reads slot %d",
+                          name, w, G, i, l, a);
+                    banks |= uint64_t(1) << ((2 * a + comp) & 63);
+                }
+                CHECK(banks == ~uint64_t(0), "%s: load wave (w %d, G %d, i %d) shares a bank", name, w, G, i);
+            }
+    for (int v : slot_of) CHECK(v >= 0, "%s: a logical item is never stored", name);
+    std::printf("ok   MFMA exchange buffer %s (%d items)\n", name, items);
+}
+
 int main(int argc, char **argv)
 {
     const bool full = argc > 1;  // also the 2^28 shapes (about 2 x 2^28 items per pass)
     audit_digit_maps();
     audit_sym();
+    audit_mf_exchange("pass 1", addr::kMf1Items, addr::mf1_store, addr::mf1_load, true);
+    audit_mf_exchange("pass 2", 16 * 256, addr::mf2_store, addr::mf2_load, false);
+    audit_mf_exchange("pass 3", addr::kMf1Items, addr::mf3_store, addr::mf3_load, false);
     const uint32_t n1s[] = {4096, 8192, 16384};
     const uint32_t n2s[] = {16, 64, 256, 2048, 4096};
     for (uint32_t N1 : n1s)

@@ -4,9 +4,12 @@ kernels take their address functions from (paper_2609_06449_amd/csrc/addr.h)
 and enumerates every load and store of every workgroup, thread and item of
 the symmetric split form, the split form of Phase I (N1 = 2^12, 2^13, 2^14;
 several N2 and bases, mixed radix included; the 2^28 shapes the benchmark
-times in the full run), the digit maps and the XCD tile order: every index
-inside its buffer, every output written once, in-place passes reading and
-writing the same items per workgroup, no 32-bit wrap."""
+times in the full run), the digit maps, the XCD tile order and the LDS
+exchange buffers of the MFMA passes: every index inside its buffer, every
+output written once, in-place passes reading and writing the same items per
+workgroup, no 32-bit wrap; every exchange-buffer load reading the slot its
+item was stored to, with no two lanes of a store half-wave or a load wave
+on one bank."""
 import os
 import shutil
 import subprocess
