@@ -178,6 +178,9 @@ PACO_HD uint32_t sym3_groups(uint32_t N1) { return 16u * (N1 >> 4); }
 // distinct banks; each lane's addresses are one or two bases plus
 // compile-time offsets (i and j are unrolled constants).
 constexpr int kMf1Items = 16 * 260;  // passes 1 and 3
+// items no stage-1 store of pass 1 (pass 3) touches: two from here on hold
+// four floats of workgroup scratch
+constexpr int kMf1Spare = 257, kMf3Spare = 256;
 PACO_HD int mf1_store(int kb, int i, int j, int n)
 {
     return (4 * kb + i) * 260 + 2 * (kb >> 1) + 16 * j + (j >> 3) + n;

@@ -49,21 +49,62 @@ struct MfW16 {
         Ai = mf_split<PREC>(ai);
     }
     // One group's 16 butterflies: x = this lane's 8 operands, o = its 4
-    // outputs m = 4 kb + i.  FP16x3: the butterfly's 32 reals (lanes n,
-    // n + 16, n + 32, n + 48) are scaled by one power of two into [1/2, 1)
-    // and back (exact).
-    __device__ __forceinline__ void dft(const float (&x)[8], float2 (&o)[4]) const
+    // outputs m = 4 kb + i.  FP16x3 splits x 2^-e (e: the power of two of
+    // the butterfly or of the workgroup's tile) and leaves the outputs in
+    // units of 2^e: the caller scales back, mostly inside a twiddle factor
+    // it multiplies by anyway.
+    __device__ __forceinline__ void dft(const float (&x)[8], float2 (&o)[4], int e = 0) const
     {
-        const int e = PREC == kPrecFP16x3 ? mf_scale_exp(x) : 0;
         const MfSplit<PREC> B = mf_split<PREC>(x, e);
         const mf_f32x4 yr = mf_product<PREC>(Ar, B), yi = mf_product<PREC>(Ai, B);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            o[i] = make_float2(yr[i], yi[i]);
-            if constexpr (PREC == kPrecFP16x3) o[i] = make_float2(ldexpf(o[i].x, e), ldexpf(o[i].y, e));
-        }
+        for (int i = 0; i < 4; ++i) o[i] = make_float2(yr[i], yi[i]);
     }
 };
+
+// FP16x3 scales of passes 1 and 3: a power of two per workgroup tile
+// instead of per butterfly: the tile's operands share one exponent range
+// (values far below the tile's largest keep their absolute accuracy, the
+// relative one of the largest), the scale costs one reduction per pass
+// instead of one per group, and stage 1's outputs feed stage 2 without
+// rescaling.  (Pass 2 keeps the scale per butterfly: there the reduction had
+// to wait for all of the wave's loads.)  max |x| over the wave's 64 lanes x
+// 32 operands:
+__device__ __forceinline__ float wave_absmax(const float (&x)[4][8])
+{
+    float m = 0.f;
+#pragma unroll
+    for (int G = 0; G < 4; ++G)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) m = fmaxf(m, fabsf(x[G][i]));
+    m = max_over_kb(m);
+    // the 16 lanes of a row, with DPP moves (no LDS): swaps of neighbours
+    // and of lane pairs (quad_perm [1,0,3,2], [2,3,0,1]), then the mirror of
+    // each half row and of the row
+    m = fmaxf(m, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(m), 0xB1, 0xF, 0xF, false)));
+    m = fmaxf(m, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(m), 0x4E, 0xF, 0xF, false)));
+    m = fmaxf(m, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(m), 0x141, 0xF, 0xF, false)));
+    m = fmaxf(m, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(m), 0x140, 0xF, 0xF, false)));
+    return m;
+}
+// e with m 2^-e in [1/2, 1) (0 for m = 0; at least -100, so that 2^-e and
+// 2^(11-e) stay finite for subnormal tiles), the same in every lane
+__device__ __forceinline__ int scale_of(float m)
+{
+    int e = 0;
+    if (m > 0.f) (void)frexpf(m, &e);
+    return __builtin_amdgcn_readfirstlane(e < -100 ? -100 : e);
+}
+// Workgroup scale of passes 1 and 3: the four wave maxima meet in exchange
+// slots that stage 1 does not store to (spare: a float2 item index).
+__device__ __forceinline__ int tile_scale(const float (&x)[4][8], float2 *lds, int spare, int lane, int w)
+{
+    float *red = reinterpret_cast<float *>(lds + spare);
+    const float m = wave_absmax(x);
+    if (lane == 0) red[w] = m;
+    __syncthreads();
+    return scale_of(fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3])));
+}
 
 // Stage-0 operands of one group (mf_swap_in); conj: the inverse's input map
 // (negate the imaginary parts, held by lanes l >= 32).
@@ -110,10 +151,13 @@ __global__ __launch_bounds__(256) void sym_first_mf_kernel(SymPass P)
     const float2 a = root_of(P.tw, P.log2L, 12, uint32_t(n) * r);
 #pragma unroll
     for (int i = 0; i < 4; ++i) t2[i] = root_of(P.tw, P.log2L, 12, 16u * uint32_t(4 * kb + i) * r);
+    // FP16x3: one scale for the tile; stage 1's outputs (below 16 in its
+    // units) feed stage 2 unscaled, the final twiddle scales back
+    const int e = PREC == kPrecFP16x3 ? tile_scale(x, lds, addr::kMf1Spare, lane, w) : 0;
     float2 o[4][4];
 #pragma unroll
     for (int G = 0; G < 4; ++G) {
-        W.dft(x[G], o[G]);
+        W.dft(x[G], o[G], e);
         const int jl = 4 * w + G;
 #pragma unroll
         for (int i = 0; i < 4; ++i) lds[addr::mf1_store(kb, i, jl, n)] = cmul(o[G][i], t1[G][i]);
@@ -131,7 +175,8 @@ __global__ __launch_bounds__(256) void sym_first_mf_kernel(SymPass P)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const uint32_t kh = uint32_t(4 * kb + i);
-        const float2 t = cmul(a, t2[i]);
+        float2 t = cmul(a, t2[i]);
+        if constexpr (PREC == kPrecFP16x3) t = make_float2(ldexpf(t.x, e), ldexpf(t.y, e));
 #pragma unroll
         for (int G = 0; G < 4; ++G) {
             float2 *d = P.dst + addr::sym1_store_base(N2, blockIdx.x, uint32_t(n + 16 * (4 * w + G)));
@@ -177,14 +222,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == kPr
     float x[4][8];
 #pragma unroll
     for (int G = 0; G < 4; ++G) mf_swap_in(it[G], x[G]);
+    // FP16x3: one scale per butterfly (mf_scale_exp), scaled back inside the
+    // twiddle factor; a scale per wave measured slower here, since no group
+    // could start before the wave's last load had arrived
     const float2 sj = P.tw_sj[256 + jc];  // w_65536^{-jc}
     float2 o[4][4];
 #pragma unroll
     for (int G = 0; G < 4; ++G) {
-        W.dft(x[G], o[G]);
+        const int e1 = PREC == kPrecFP16x3 ? mf_scale_exp(x[G]) : 0;
+        W.dft(x[G], o[G], e1);
         const int rr = 4 * w + G;
         const float2 step = cmul(sj, root_of(P.tw, P.log2L, 8, uint32_t(rr)));  // w_65536^{-c}
         float2 t = cmul(th[G], tl[G]);
+        if constexpr (PREC == kPrecFP16x3) t = make_float2(ldexpf(t.x, e1), ldexpf(t.y, e1));
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int s = 4 * kb + i;
@@ -202,7 +252,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == kPr
         const int s2 = 4 * w + G;
 #pragma unroll
         for (int i = 0; i < 8; ++i) x[G][i] = ldf[2 * addr::mf2_load(s2, half, i, n)];
-        W.dft(x[G], o[G]);
+        const int e2 = PREC == kPrecFP16x3 ? mf_scale_exp(x[G]) : 0;
+        W.dft(x[G], o[G], e2);
+        if constexpr (PREC == kPrecFP16x3) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) o[G][i] = make_float2(ldexpf(o[G][i].x, e2), ldexpf(o[G][i].y, e2));
+        }
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -242,10 +297,12 @@ __global__ __launch_bounds__(256) void sym_last_mf_kernel(SymPass P)
     for (int G = 0; G < 4; ++G)
 #pragma unroll
         for (int i = 0; i < 4; ++i) t1[G][i] = root_of(P.tw, P.log2L, 8, uint32_t((4 * w + G) * (4 * kb + i)));
+    // FP16x3: one scale for the tile (as in pass 1), scaled back at the store
+    const int e = PREC == kPrecFP16x3 ? tile_scale(x, lds, addr::kMf3Spare, lane, w) : 0;
     float2 o[4][4];
 #pragma unroll
     for (int G = 0; G < 4; ++G) {
-        W.dft(x[G], o[G]);
+        W.dft(x[G], o[G], e);
         const int jl = 4 * w + G;
 #pragma unroll
         for (int i = 0; i < 4; ++i) lds[addr::mf3_store(kb, i, jl, n)] = cmul(o[G][i], t1[G][i]);
@@ -259,13 +316,14 @@ __global__ __launch_bounds__(256) void sym_last_mf_kernel(SymPass P)
         for (int i = 0; i < 8; ++i) x[G][i] = ldf[2 * addr::mf3_load(kl, half, i, n)];
         W.dft(x[G], o[G]);
     }
+    const float osc = ldexpf(1.0f, e);  // 1 except in FP16x3
 #pragma unroll
     for (int G = 0; G < 4; ++G) {
         float2 *d = P.dst + addr::sym3_store_base(N1, blockIdx.x, uint32_t(n + 16 * (4 * w + G)));
 #pragma unroll
         for (int i = 0; i < 4; ++i)
             d[addr::sym3_store_off(N1, uint32_t(4 * kb + i))] =
-                P.out_scale != 0.f ? conj_scale(o[G][i], P.out_scale) : o[G][i];
+                P.out_scale != 0.f ? conj_scale(o[G][i], P.out_scale * osc) : make_float2(o[G][i].x * osc, o[G][i].y * osc);
     }
 }
 

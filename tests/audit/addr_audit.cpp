@@ -211,12 +211,13 @@ void audit_digit_maps()
 
 // The MFMA passes' LDS exchange buffers (16 rows of 256 logical items): the
 // stage-1 stores of 4 waves x 4 groups x 4 outputs x 64 lanes fill every slot
-// once, inside the buffer; every stage-2 component load reads the slot its
+// once, inside the buffer, and leave the two spare items (the FP16x3 tile
+// scale's scratch) alone; every stage-2 component load reads the slot its
 // logical item was stored to; and (the layouts' purpose) every store
 // half-wave covers 32 distinct 8-byte slots, every load wave 64 distinct
 // 4-byte banks.
 template <class Store, class Load>
-void audit_mf_exchange(const char *name, int items, Store store, Load load, bool load_across_rows)
+void audit_mf_exchange(const char *name, int items, Store store, Load load, bool load_across_rows, int spare)
 {
     std::vector<int> at(items, -1);  // logical item (row * 256 + col) per slot
     std::vector<int> slot_of(16 * 256, -1);
@@ -230,6 +231,7 @@ void audit_mf_exchange(const char *name, int items, Store store, Load load, bool
                     const int a = store(kb, i, j, n);
                     CHECK(a >= 0 && a < items, "%s: store %d outside %d items", name, a, items);
                     CHECK(at[a] < 0, "%s: slot %d stored twice", name, a);
+                    CHECK(spare < 0 || a < spare || a >= spare + 2, "%s: store to spare slot %d", name, a);
                     const int logical = (4 * kb + i) * 256 + 16 * j + n;
                     at[a] = logical;
                     slot_of[logical] = a;
@@ -267,9 +269,9 @@ int main(int argc, char **argv)
     const bool full = argc > 1;  // also the 2^28 shapes (about 2 x 2^28 items per pass)
     audit_digit_maps();
     audit_sym();
-    audit_mf_exchange("pass 1", addr::kMf1Items, addr::mf1_store, addr::mf1_load, true);
-    audit_mf_exchange("pass 2", 16 * 256, addr::mf2_store, addr::mf2_load, false);
-    audit_mf_exchange("pass 3", addr::kMf1Items, addr::mf3_store, addr::mf3_load, false);
+    audit_mf_exchange("pass 1", addr::kMf1Items, addr::mf1_store, addr::mf1_load, true, addr::kMf1Spare);
+    audit_mf_exchange("pass 2", 16 * 256, addr::mf2_store, addr::mf2_load, false, -1);
+    audit_mf_exchange("pass 3", addr::kMf1Items, addr::mf3_store, addr::mf3_load, false, addr::kMf3Spare);
     const uint32_t n1s[] = {4096, 8192, 16384};
     const uint32_t n2s[] = {16, 64, 256, 2048, 4096};
     for (uint32_t N1 : n1s)

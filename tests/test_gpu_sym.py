@@ -251,3 +251,45 @@ def test_mfma_stage_hooks_compose_in_place_and_inverse(form):
     err = oracle.rel_l2(back, x)
     print(f"{form} inverse of the oracle's output: rel-L2 vs x {err:.3e}", flush=True)
     assert err <= 2 * tol
+
+
+@pytest.mark.parametrize("form", sorted(MFMA_FORMS) + ["fp32"])
+def test_power_of_two_input_scale_passes_through_exactly(form):
+    # The FP16x3 form scales each tile (passes 1, 3) or wave (pass 2) by a
+    # power of two taken from its largest operand; the BF16 forms and FP32
+    # need none.  Scaling the input by 2^s must then scale every output by
+    # exactly 2^s, bit for bit, as long as nothing leaves FP32's normal range:
+    # s = 60 puts |x| near 10^22 (far outside FP16), s = -80 near 10^-28.
+    dt = paco.PACO_C64 if form == "fp32" else MFMA_FORMS[form][0]
+    plan = paco.Plan(N1, N2, 64, 16, dt)
+    x = inputs.loguniform(N, seed=89)
+    y = _execute(plan, _dev(x)).cpu().numpy()
+    for s in (60, -80):
+        xs = np.ldexp(x.view(np.float32), s).view(np.complex64)  # componentwise, exact
+        ys = _execute(plan, _dev(xs)).cpu().numpy()
+        scaled = np.ldexp(y.view(np.float32), s).view(np.complex64)
+        assert np.array_equal(ys.view(np.uint64), scaled.view(np.uint64)), (form, s)
+    zero = _execute(plan, _dev(np.zeros(N, np.complex64))).cpu().numpy()
+    assert not np.any(zero), form
+
+
+def test_fp16x3_scale_sees_every_lane():
+    # Small noise (|x| ~ 1e-3) with 10^6 spikes at 4096 random positions:
+    # a scale that missed the lane of a spike would leave it near 5e8 in
+    # FP16 units (FP16 overflows at 65504) and poison the pass with inf.
+    # Each pass alone on that input, against the FP32 pass.
+    dt, tol = MFMA_FORMS["fp16x3"]
+    fp32 = paco.Plan(N1, N2, 64, 16)
+    mf = paco.Plan(N1, N2, 64, 16, dt)
+    rng = np.random.default_rng(90)
+    x = (1e-3 * inputs.normal(N, seed=90)).astype(np.complex64)
+    pos = rng.choice(N, size=4096, replace=False)
+    x[pos] = (1e6 * np.exp(2j * np.pi * rng.random(4096))).astype(np.complex64)
+    src = _dev(x)
+    for stage in (1, 2, 3):
+        a = _stage(fp32, stage, src).cpu().numpy()
+        b = _stage(mf, stage, src).cpu().numpy()
+        assert np.all(np.isfinite(b.view(np.float32))), stage
+        err = oracle.rel_l2(b, a)
+        print(f"fp16x3 pass {stage} on spikes: rel-L2 against the FP32 pass {err:.3e}", flush=True)
+        assert err <= tol, (stage, err)
