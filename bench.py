@@ -3,12 +3,13 @@
 One step = one complete transform (Phase I LocalFFT -> Phase II fused
 permutation -> Phase III LocalFFT) of the N = 2^24 complex64 workload
 (N1 = N2 = 4096, p = 64 slabs, b = 16, N(0,1) inputs, seed 2) through the C
-ABI, in the plan's default (split) form: three HBM passes, the first two
-sharing Phase I's butterflies.  Inputs are resident in HBM before the timed
-region.  Prints one JSON line: GFLOP/s = 5 N log2 N / t, plus the dominant
-kernel's roofline (HIP events on the stream the kernels run on; phase_us
-times pass 1, pass 2 and Phase III one launch each) and the CPU oracle
-baseline (one thread and all host cores, with the core count and CPU model).
+ABI, in the plan's default (symmetric split) form: three HBM passes, the
+16-point children of both local phases in the middle one.  Inputs are
+resident in HBM before the timed region.  Prints one JSON line: GFLOP/s =
+5 N log2 N / t, plus the dominant kernel's roofline (HIP events on the stream
+the kernels run on; phase_us times passes 1, 2 and 3 one launch each) and the
+CPU oracle baseline (one thread and all host cores, with the core count and
+CPU model).
 
 Further fields of the same line (each leg can be skipped by a flag):
   two_pass   the two-HBM-pass form of the same transform (an ablation,
@@ -19,7 +20,8 @@ Further fields of the same line (each leg can be skipped by a flag):
              and with the largest bases of which both sizes are powers; each
              complete output's rel-L2 against the FP64 oracle
   precision  FP32 and the split MFMA forms at 2^24 and 2^26 on log-uniform
-             inputs, with their rel-L2 and worst-output errors vs FP64
+             inputs, with their rel-L2 and worst-output errors vs FP64; the
+             forms take turns in 5 rounds of timed launches, median round
 --calibrate-copy adds the device copy that scales rocprofv3's FETCH_SIZE /
 WRITE_SIZE counters; --traffic-from turns two such counter files into
 profiles/traffic_2p24_4096x4096.json (the roofline's traffic field).
@@ -299,6 +301,9 @@ PRECISION_WORKLOADS = [  # N = 2^24 and 2^26, |x| = 10^U[-4,4], arg x ~ U[0, 2 p
 FORMS = [(0, "fp32"), (1, "fp16x3"), (2, "bf16x3"), (3, "bf16x6")]
 
 
+PRECISION_REPEATS = 5
+
+
 def bench_precision(steps: int, warmup: int):
     """Every arithmetic form on the precision workloads: milliseconds per
     transform (back-to-back launches on one stream, inputs resident).
@@ -317,20 +322,32 @@ def bench_precision(steps: int, warmup: int):
         xd = torch.from_numpy(x).to("cuda")
         out = torch.empty_like(xd)
         ws = torch.empty_like(xd)
-        for dt, name in FORMS:
-            plan = paco.Plan(w["N1"], w["N2"], w["p"], w["b"], dt)
+        plans = {name: paco.Plan(w["N1"], w["N2"], w["p"], w["b"], dt) for dt, name in FORMS}
+        for plan in plans.values():
             for _ in range(warmup):
                 plan.execute(xd.data_ptr(), out.data_ptr(), ws.data_ptr(), sh)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(steps):
-                plan.execute(xd.data_ptr(), out.data_ptr(), ws.data_ptr(), sh)
-            torch.cuda.synchronize()
-            ms = (time.perf_counter() - t0) * 1e3 / steps
+        torch.cuda.synchronize()
+        # the forms take turns, PRECISION_REPEATS rounds of `steps` launches
+        # each, so that a drift of the clock or of the caches hits every form
+        # alike; the median round is reported
+        runs = {name: [] for name in plans}
+        for _ in range(PRECISION_REPEATS):
+            for name, plan in plans.items():
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(steps):
+                    plan.execute(xd.data_ptr(), out.data_ptr(), ws.data_ptr(), sh)
+                torch.cuda.synchronize()
+                runs[name].append((time.perf_counter() - t0) * 1e3 / steps)
+        for name, plan in plans.items():
+            ms = sorted(runs[name])[len(runs[name]) // 2]
             rec.setdefault(name, {})[w["name"]] = dict(
-                ms=round(ms, 4), gflops=round(5.0 * N * math.log2(N) / (ms * 1e-3) / 1e9, 1),
+                ms=round(ms, 4), ms_min=round(min(runs[name]), 4),
+                gflops=round(5.0 * N * math.log2(N) / (ms * 1e-3) / 1e9, 1),
                 hbm_frac_passes=round(16.0 * N * plan.launches / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                 launches=plan.launches)
+            plan.execute(xd.data_ptr(), out.data_ptr(), ws.data_ptr(), sh)
+            torch.cuda.synchronize()
             outs[(name, w["name"])] = out.cpu().numpy()
             plan.close()
         outs[("x", w["name"])] = x
@@ -632,7 +649,7 @@ def main():
         if "xd" in locals():
             del xd, out, ws
         torch.cuda.empty_cache()
-        rec["precision"], prec_outs = bench_precision(max(10, args.steps // 4), 3)
+        rec["precision"], prec_outs = bench_precision(max(20, args.steps), 3)
         rec["precision"]["workload"] = ("log-uniform |x| = 10^U[-4,4], uniform phase (seed 5); N = 2^24 as 4096 x 4096 "
                                        "(b = 16) and N = 2^26 as 4096 x 16384 (b = 4); split forms run every "
                                        "radix-16 butterfly on MFMA")

@@ -105,57 +105,68 @@ namespace addr {
 // bytes, into the pass's source or destination buffer): the kernels form one
 // pointer from the base and add the offsets, the audit adds the two.
 
-// ---- the symmetric split form (sym.hip), N1 = N2 = 4096 ---------------------
-// Workgroup blk, thread tid (256 threads), item i < 16.
+// ---- the symmetric split form (sym.hip), N1 = N2 = 16 L, L = 2^ll ----------
+// (ll = 8, 9, 10: N = 2^24, 2^26, 2^28).  Workgroup blk, L threads (256 for
+// ll = 8), item i < 16.  With P = L / 256 threads per M-point stage-B
+// transform (M = L / 16): thread tid of passes 1 and 3 is (cl, jl) =
+// (tid & 15, tid >> 4) in stage A and, in stage B, k fastest in pass 1
+// (ka, jp, cl) = (tid & 15, (tid >> 4) & (P - 1), tid >> (4 + ll - 8)) and
+// column fastest in pass 3 (cl, jp, ka) = (tid & 15, (tid >> 4) & (P - 1),
+// tid >> (4 + ll - 8)); jp picks the outputs kB = i + 16 jp of the thread.
 
 // pass 1: workgroup (r, cb) = (blk / (N2/16), blk mod (N2/16)); thread
-// (cl, jl) = (tid & 15, tid >> 4) loads row 16 (jl + 16 i) + r, column 16 cb + cl
+// (cl, jl) loads row 16 (jl + (L/16) i) + r, column 16 cb + cl
 PACO_HD uint32_t sym1_load_base(uint32_t N2, uint32_t blk, uint32_t tid)
 {
     const uint32_t ncb = N2 >> 4, cb = blk % ncb, r = blk / ncb;
     return (16u * (tid >> 4) + r) * N2 + (cb << 4) + (tid & 15u);
 }
-PACO_HD uint32_t sym1_load_off(uint32_t N2, uint32_t i) { return 256u * i * N2; }
+PACO_HD uint32_t sym1_load_off(uint32_t N2, uint32_t i, uint32_t ll = 8) { return (i << ll) * N2; }
 // The workspace between passes 1 and 2 holds U[c][r][k] at
 //     ((k >> 4) N2 + c) 256 + 16 r + (k & 15),
 // so that pass 2 reads 2 KiB runs (all r of 16 consecutive k of one column).
-// Thread (kl, cl) = (tid & 15, tid >> 4) stores U[c][r][kl + 16 i], c = 16 cb + cl.
-PACO_HD uint32_t sym1_store_base(uint32_t N2, uint32_t blk, uint32_t tid)
+// Stage-B thread (ka, jp, cl) stores U[c][r][ka + 16 (i + 16 jp)], c = 16 cb + cl.
+PACO_HD uint32_t sym1_store_base(uint32_t N2, uint32_t blk, uint32_t tid, uint32_t ll = 8)
 {
     const uint32_t ncb = N2 >> 4, cb = blk % ncb, r = blk / ncb;
-    return ((cb << 4) + (tid >> 4)) * 256u + 16u * r + (tid & 15u);
+    const uint32_t jp = (tid >> 4) & ((1u << (ll - 8)) - 1u), cl = tid >> (ll - 4);
+    return ((16u * jp * N2 + (cb << 4) + cl) << 8) + 16u * r + (tid & 15u);
 }
 PACO_HD uint32_t sym1_store_off(uint32_t N2, uint32_t i) { return i * N2 * 256u; }
-// pass 2: the hardware's workgroup id g maps to (jc, kb) = (g mod 256, g / 256)
+// pass 2: the hardware's workgroup id g maps to (jc, kb) = (g mod L, g / L)
 // (jc fastest: neighbouring workgroups read neighbouring 2 KiB runs);
-// blk = 16 jc + kb.  Thread (kk, rr) loads U[jc + 256 rr][i][16 kb + kk].
-PACO_HD uint32_t sym2_block(uint32_t g) { return ((g & 255u) << 4) | (g >> 8); }
-PACO_HD uint32_t sym2_load_base(uint32_t N2, uint32_t blk, uint32_t tid)
+// blk = (L/16) jc + kb.  Thread (kk, rr) loads U[jc + L rr][i][16 kb + kk].
+PACO_HD uint32_t sym2_block(uint32_t g, uint32_t ll = 8)
 {
-    const uint32_t kb = blk & 15u, jc = blk >> 4;
-    return ((kb * N2 + jc + 256u * (tid >> 4)) << 8) + (tid & 15u);
+    return ((g & ((1u << ll) - 1u)) << (ll - 4)) | (g >> ll);
+}
+PACO_HD uint32_t sym2_load_base(uint32_t N2, uint32_t blk, uint32_t tid, uint32_t ll = 8)
+{
+    const uint32_t kb = blk & ((1u << (ll - 4)) - 1u), jc = blk >> (ll - 4);
+    return ((kb * N2 + jc + ((tid >> 4) << ll)) << 8) + (tid & 15u);
 }
 PACO_HD uint32_t sym2_load_off(uint32_t i) { return 16u * i; }
-// thread (kk, s) stores W at row 16 jc + i, column 16 kb + kk + 256 s
-PACO_HD uint32_t sym2_store_base(uint32_t N1, uint32_t blk, uint32_t tid)
+// thread (kk, s) stores W at row 16 jc + i, column 16 kb + kk + L s
+PACO_HD uint32_t sym2_store_base(uint32_t N1, uint32_t blk, uint32_t tid, uint32_t ll = 8)
 {
-    const uint32_t kb = blk & 15u, jc = blk >> 4;
-    return 16u * jc * N1 + 16u * kb + (tid & 15u) + 256u * (tid >> 4);
+    const uint32_t kb = blk & ((1u << (ll - 4)) - 1u), jc = blk >> (ll - 4);
+    return 16u * jc * N1 + 16u * kb + (tid & 15u) + ((tid >> 4) << ll);
 }
 PACO_HD uint32_t sym2_store_off(uint32_t N1, uint32_t i) { return i * N1; }
 // pass 3: workgroup (q0, vb) = (blk / (N1/16), blk mod (N1/16)); thread
-// (cl, jl) loads row 16 (jl + 16 i) + q0, column 16 vb + cl
+// (cl, jl) loads row 16 (jl + (L/16) i) + q0, column 16 vb + cl
 PACO_HD uint32_t sym3_load_base(uint32_t N1, uint32_t blk, uint32_t tid)
 {
     const uint32_t nvb = N1 >> 4, vb = blk % nvb, q0 = blk / nvb;
     return (16u * (tid >> 4) + q0) * N1 + (vb << 4) + (tid & 15u);
 }
-PACO_HD uint32_t sym3_load_off(uint32_t N1, uint32_t i) { return 256u * i * N1; }
-// thread (cl, kl) = (tid & 15, tid >> 4) stores row q0 + 16 (kl + 16 i)
-PACO_HD uint32_t sym3_store_base(uint32_t N1, uint32_t blk, uint32_t tid)
+PACO_HD uint32_t sym3_load_off(uint32_t N1, uint32_t i, uint32_t ll = 8) { return (i << ll) * N1; }
+// stage-B thread (cl, jp, ka) stores row q0 + 16 q, q = ka + 16 (i + 16 jp)
+PACO_HD uint32_t sym3_store_base(uint32_t N1, uint32_t blk, uint32_t tid, uint32_t ll = 8)
 {
     const uint32_t nvb = N1 >> 4, vb = blk % nvb, q0 = blk / nvb;
-    return (q0 + 16u * (tid >> 4)) * N1 + (vb << 4) + (tid & 15u);
+    const uint32_t jp = (tid >> 4) & ((1u << (ll - 8)) - 1u), ka = tid >> (ll - 4);
+    return (q0 + 16u * ka + 4096u * jp) * N1 + (vb << 4) + (tid & 15u);
 }
 PACO_HD uint32_t sym3_store_off(uint32_t N1, uint32_t i) { return 256u * i * N1; }
 // workgroup counts of the three passes

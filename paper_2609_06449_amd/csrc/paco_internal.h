@@ -172,20 +172,21 @@ struct SplitPass {
 };
 constexpr int kTwTile = 128;  // tile-twiddle table side: [i*128 + j] = w_N^{-(i*j mod N)}
 
-// The symmetric split form (sym.hip), FP32, N1 = N2 = 4096: Lemma 1 once more
-// on both local phases, with the 16-point children next to the
-// redistribution.  Phase I:   j1 = 16 j + r,  k1 = k + 256 s;
-//                  Phase III: j2 = jc + 256 rr, k2 = q0 + 16 q.
-//   pass 1: U[c][r][k] = w_N1^{-k r} sum_j X[16 j + r, c] w_256^{-k j}
+// The symmetric split form (sym.hip), N1 = N2 = 16 L, L = 256, 512, 1024
+// (the split MFMA forms: L = 256): Lemma 1 once more on both local phases,
+// with the 16-point children next to the redistribution.
+//   Phase I:   j1 = 16 j + r,  k1 = k + L s;
+//   Phase III: j2 = jc + L rr, k2 = q0 + 16 q.
+//   pass 1: U[c][r][k] = w_N1^{-k r} sum_j X[16 j + r, c] w_L^{-k j}
 //           -> ws[((k >> 4) N2 + c) 256 + 16 r + (k & 15)]
-//   pass 2: A[k + 256 s, c] = sum_r w_16^{-s r} U[c][r][k];
+//   pass 2: A[k + L s, c] = sum_r w_16^{-s r} U[c][r][k];
 //           Z[v, c] = A[v, c] w_N^{-v c};
-//           W[v][jc][q0] = w_N2^{-q0 jc} sum_rr Z[v, jc + 256 rr] w_16^{-q0 rr}
+//           W[v][jc][q0] = w_N2^{-q0 jc} sum_rr Z[v, jc + L rr] w_16^{-q0 rr}
 //           -> out[(16 jc + q0) N1 + v]
-//   pass 3: Y[q0 + 16 q, v] = sum_jc w_256^{-q jc} W[v][jc][q0]
+//   pass 3: Y[q0 + 16 q, v] = sum_jc w_L^{-q jc} W[v][jc][q0]
 //           -> out[(q0 + 16 q) N1 + v], in place (a tile reads and writes the
 //           same rows {q0 + 16 t})
-constexpr int kSymLog2N = 12;
+constexpr int kSymLog2N = 12;  // N1 = N2 = 2^12: every dtype
 struct SymPass {
     const float2 *src;
     float2 *dst;
@@ -194,7 +195,7 @@ struct SymPass {
     int32_t log2L;
     const float2 *tw_hi, *tw_lo;  // w_N^{-e} = tw_hi[e >> log2Lo] * tw_lo[e mod 2^log2Lo]
     int32_t log2N, log2Lo;
-    const float2 *tw_sj;          // [s * 256 + jc] = w_{16 N2}^{-s jc}, s < 16, jc < 256
+    const float2 *tw_sj;          // [s L + jc] = w_{16 N2}^{-s jc}, s < 16, jc < L = N2 / 16
     const float *w16;             // split MFMA forms: 64 lanes x 16 DFT-matrix operands (w16_operands)
     int32_t conj_in;              // pass 1: conjugate x on load (the inverse's input map)
     float out_scale;              // pass 3: nonzero stores conj(y) * out_scale (the inverse's output map)

@@ -95,7 +95,7 @@ struct paco_plan_s {
     LocalPass phase1_two{}, phase3_two{};   // the two-pass form's passes
     bool split = false;                     // N1 = 2^12: Phase I split 16 x 256 across passes 1 and 2
     paco::SplitPass split_pass{};           // src/dst filled per execution
-    bool sym = false;                       // N1 = N2 = 4096: the symmetric split form (three passes)
+    bool sym = false;                       // N1 = N2 = 16 L: the symmetric split form (three passes)
     paco::SymPass sym_pass{};               // src/dst filled per execution
     paco_plan_s *inv = nullptr;             // N2 x N1 passes of the inverse (NULL: square, this plan's)
     void *scratch = nullptr;                // this device's scratch array (paco_execute_noalloc)
@@ -257,13 +257,15 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
         for (int64_t k = 0; k < 16 * N1; ++k) tcw[k] = paco::root_neg(k, 16 * N1);
     }
     paco::middle_tables(P->lN, thi, tlo, ttile);
-    // the symmetric split form (N1 = N2 = 4096, every dtype; option PACO_PLAN_NO_SYM)
-    const bool sym_form = !no_split && !no_sym && !paper_layout && !generic && P->l1 == paco::kSymLog2N &&
-                          P->l2 == paco::kSymLog2N;
-    if (sym_form) {  // its pass-2 factor w_{16 N2}^{-s jc}, s < 16, jc < 256
-        tsj.resize(16 * 256);
+    // the symmetric split form (N1 = N2 = 16 L: L = 256 for every dtype, 512
+    // and 1024 in FP32; option PACO_PLAN_NO_SYM)
+    const bool sym_form = !no_split && !no_sym && !paper_layout && !generic && P->l1 == P->l2 &&
+                          (P->l1 == paco::kSymLog2N || (dt == PACO_C64 && (P->l1 == 13 || P->l1 == 14)));
+    if (sym_form) {  // its pass-2 factor w_{16 N2}^{-s jc}, s < 16, jc < L
+        const int64_t L = N1 / 16;
+        tsj.resize(size_t(16 * L));
         for (int64_t sv = 0; sv < 16; ++sv)
-            for (int64_t jc = 0; jc < 256; ++jc) tsj[sv * 256 + jc] = paco::root_neg((sv * jc) % (16 * N2), 16 * N2);
+            for (int64_t jc = 0; jc < L; ++jc) tsj[sv * L + jc] = paco::root_neg((sv * jc) % (16 * N2), 16 * N2);
         if (dt != PACO_C64) {  // the MFMA lanes' DFT-matrix operands
             tw16.resize(64 * 16);
             paco::w16_operands(tw16.data());
@@ -527,7 +529,7 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
         }
     }
 
-    // ---- symmetric split form (FP32, N1 = N2 = 4096; option PACO_PLAN_NO_SYM)
+    // ---- symmetric split form (N1 = N2 = 16 L; option PACO_PLAN_NO_SYM)
     // Phase III split like Phase I, its 16-point child moved into the
     // redistribution pass: every pass moves whole 128-byte lines
     if (sym_form) {
@@ -566,9 +568,13 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
         desc = buf + desc;
     }
     if (P->fused) desc = "fused[phase1 -> packed transposed slab, phase2 row unpack+twiddle] " + desc;
-    if (P->sym)
-        desc = "sym[pass1: phase1 256-point children over rows 16j+r -> ws; pass2: phase1 radix-16 + twiddle + "
-               "phase3 radix-16; pass3: phase3 256-point children, in place] " + desc;
+    if (P->sym) {
+        std::snprintf(buf, sizeof buf,
+                      "sym[pass1: phase1 %lld-point children over rows 16j+r -> ws; pass2: phase1 radix-16 + twiddle + "
+                      "phase3 radix-16; pass3: phase3 %lld-point children, in place] ",
+                      (long long)(N1 / 16), (long long)(N2 / 16));
+        desc = buf + desc;
+    }
     if (P->two_pass) {
         const paco::LocalLaunch g = paco::local_fft_geometry(P->phase3_two);
         std::snprintf(buf, sizeof buf, " two_pass[phase3 twiddle-on-load n=2^%d T=%d wg=%lld thr=%d lds=%zu]",

@@ -121,17 +121,20 @@ __global__ __launch_bounds__(kSymThreads) void sym_first_kernel(SymPass P)
 // fastest, padded LDS, the factor as a product of two-level table entries):
 // 54 against 63 us, and pass 1, which now stores 128-byte runs, 45 against
 // 50 us.  Five waves per SIMD (96 VGPRs, 32 KiB of LDS).
+// L = 2^LL (N1 = N2 = 16 L): jc < L, kb < L/16, c = jc + L rr, and the
+// pass-2 factor table holds w_{16 N2}^{-s jc} at [s L + jc].
+template <int LL>
 __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(5))) void sym_middle_kernel(SymPass P)
 {
     __shared__ float2 lds[16 * 256];
     const int tid = threadIdx.x;
     const uint32_t N1 = uint32_t(P.N1), N2 = uint32_t(P.N2);
-    const uint32_t blk = addr::sym2_block(blockIdx.x);
-    const uint32_t kb = blk & 15, jc = blk >> 4;
+    const uint32_t blk = addr::sym2_block(blockIdx.x, LL);
+    const uint32_t kb = blk & ((1u << (LL - 4)) - 1u), jc = blk >> (LL - 4);
     const int kk = tid & 15, rr = tid >> 4;
-    const uint32_t c = jc + 256u * rr, k = 16u * kb + kk;
+    const uint32_t c = jc + (uint32_t(rr) << LL), k = 16u * kb + kk;
     float2 v[16];
-    const float2 *src = P.src + addr::sym2_load_base(N2, blk, tid);
+    const float2 *src = P.src + addr::sym2_load_base(N2, blk, tid, LL);
 #pragma unroll
     for (int r = 0; r < 16; ++r) v[r] = ld2_last(src + addr::sym2_load_off(r));  // last use
     const uint32_t nmask = uint32_t((uint64_t(1) << P.log2N) - 1), lomask = (1u << P.log2Lo) - 1u;
@@ -140,9 +143,9 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(5))
     float2 t2[16], t3[16], t4[16];
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
-        t2[s] = P.tw_sj[s * 256 + jc];                           // w_{16 N2}^{-s jc}
-        t3[s] = root_of(P.tw, P.log2L, 8, uint32_t(s * rr));    // w_256^{-s rr}
-        t4[s] = root_of(P.tw, P.log2L, 12, uint32_t(s) * jc);  // w_N2^{-q0 jc}, q0 = s
+        t2[s] = P.tw_sj[(s << LL) + jc];                             // w_{16 N2}^{-s jc}
+        t3[s] = root_of(P.tw, P.log2L, 8, uint32_t(s * rr));        // w_256^{-s rr}
+        t4[s] = root_of(P.tw, P.log2L, LL + 4, uint32_t(s) * jc);  // w_N2^{-q0 jc}, q0 = s
     }
     dft_regs<4>(v);
     const float2 t1 = cmul(h1, l1);
@@ -156,7 +159,7 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(5))
 #pragma unroll
     for (int i = 0; i < 16; ++i) v[i] = lds[s2 * 256 + ((i ^ (s2 & 1)) << 4) + kk];
     dft_regs<4>(v);
-    float2 *dst = P.dst + addr::sym2_store_base(N1, blk, tid);
+    float2 *dst = P.dst + addr::sym2_store_base(N1, blk, tid, LL);
 #pragma unroll
     for (int q0 = 0; q0 < 16; ++q0) dst[addr::sym2_store_off(N1, q0)] = q0 ? cmul(v[q0], t4[q0]) : v[q0];
 }
@@ -194,10 +197,161 @@ __global__ __launch_bounds__(kSymThreads) void sym_last_kernel(SymPass P)
         dst[addr::sym3_store_off(N1, kh)] = P.out_scale != 0.f ? conj_scale(v[kh], P.out_scale) : v[kh];
 }
 
+// ---- passes 1 and 3 for L = 512 and 1024 (N1 = N2 = 8192, 16384) ----------
+// The L-point transform of a 16-column tile: radix 16 over jh (j = jl + M jh,
+// M = L/16) by thread (cl, jl), twiddle w_L^{-jl ka}, exchange; then the
+// M-point transform over jl = jp + P jm (P = M/16 = 2 or 4) of each (column,
+// ka): radix 16 over jm by thread (jp, ...), twiddle w_M^{-jp kb'}, and radix
+// P across the P threads of a transform, which sit 16 lanes apart: a
+// v_permlane16_swap (and for P = 4 two v_permlane32_swaps) of a value with
+// itself leaves every lane with the values of all P threads.  Thread jp keeps
+// the outputs kb' + 16 jp, i.e. k = ka + 16 (kb' + 16 jp) of the L-point
+// transform.  The exchange buffer holds 16 planes (ka) of M x 16 items.
+
+template <int PP>
+__device__ __forceinline__ float2 radix_across_lanes(float2 y, int jp)
+{
+    // X_jp = sum_p w_P^{-jp p} y_p, y_p the value of lane group p
+    const auto sx = __builtin_amdgcn_permlane16_swap(__float_as_uint(y.x), __float_as_uint(y.x), false, false);
+    const auto sy = __builtin_amdgcn_permlane16_swap(__float_as_uint(y.y), __float_as_uint(y.y), false, false);
+    float2 a = make_float2(__uint_as_float(sx[0]), __uint_as_float(sy[0]));  // y of the even lane group
+    float2 b = make_float2(__uint_as_float(sx[1]), __uint_as_float(sy[1]));  // y of the odd lane group
+    if constexpr (PP == 2) {
+        const float sg = (jp & 1) ? -1.f : 1.f;
+        return make_float2(fmaf(sg, b.x, a.x), fmaf(sg, b.y, a.y));
+    } else {
+        // after the 32-lane swaps: a = y_0, a2 = y_2, b = y_1, b2 = y_3
+        const auto ax = __builtin_amdgcn_permlane32_swap(__float_as_uint(a.x), __float_as_uint(a.x), false, false);
+        const auto ay = __builtin_amdgcn_permlane32_swap(__float_as_uint(a.y), __float_as_uint(a.y), false, false);
+        const auto bx = __builtin_amdgcn_permlane32_swap(__float_as_uint(b.x), __float_as_uint(b.x), false, false);
+        const auto by = __builtin_amdgcn_permlane32_swap(__float_as_uint(b.y), __float_as_uint(b.y), false, false);
+        const float2 y0 = make_float2(__uint_as_float(ax[0]), __uint_as_float(ay[0]));
+        const float2 y2 = make_float2(__uint_as_float(ax[1]), __uint_as_float(ay[1]));
+        const float2 y1 = make_float2(__uint_as_float(bx[0]), __uint_as_float(by[0]));
+        const float2 y3 = make_float2(__uint_as_float(bx[1]), __uint_as_float(by[1]));
+        // X_t = (y0 + (-1)^t y2) + w_4^{-t} (y1 + (-1)^t y3), w_4^{-1} = -i
+        const float sg = (jp & 1) ? -1.f : 1.f;
+        const float2 e = make_float2(fmaf(sg, y2.x, y0.x), fmaf(sg, y2.y, y0.y));
+        const float2 o = make_float2(fmaf(sg, y3.x, y1.x), fmaf(sg, y3.y, y1.y));
+        const float2 r = (jp & 1) ? make_float2(o.y, -o.x) : o;
+        const float g = (jp & 2) ? -1.f : 1.f;
+        return make_float2(fmaf(g, r.x, e.x), fmaf(g, r.y, e.y));
+    }
+}
+
+// Stage B on the 16 values v[jm] of item jl = jp + P jm: afterwards v[i] is
+// output kb' = i of the thread's M-point transform times nothing, combined
+// across its P threads (output i + 16 jp).  tb[i] = w_M^{-jp i}.
+template <int PP>
+__device__ __forceinline__ void stage_b(float2 (&v)[16], const float2 (&tb)[16], int jp)
+{
+    dft_regs<4>(v);
+#pragma unroll
+    for (int i = 1; i < 16; ++i) v[i] = cmul(v[i], tb[i]);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = radix_across_lanes<PP>(v[i], jp);
+}
+
+// Pass 1, L = 2^LL.  Stage-B thread (ka, jp, cl2) = (tid & 15, (tid >> 4) &
+// (P-1), tid >> (4 + log2 P)): k fastest, for the 128-byte runs of U.  Plane
+// stride L + 1 (odd): a half-wave of stage-B loads (16 ka x 2 jp) hits 32
+// distinct 8-byte slots.
+template <bool STREAM, int LL>
+__global__ __launch_bounds__(1 << LL) __attribute__((amdgpu_waves_per_eu(4))) void sym_first_long_kernel(SymPass P)
+{
+    constexpr int L = 1 << LL, M = L >> 4, PP = M >> 4, S = L + 1;
+    __shared__ float2 lds[16 * S];
+    const int tid = threadIdx.x;
+    const uint32_t N2 = uint32_t(P.N2);
+    const uint32_t r = blockIdx.x / (N2 >> 4);
+    const int cl = tid & 15, jl = tid >> 4;
+    float2 v[16];
+    const float2 *src = P.src + addr::sym1_load_base(N2, blockIdx.x, tid);
+#pragma unroll
+    for (int jh = 0; jh < 16; ++jh) v[jh] = src[addr::sym1_load_off(N2, jh, LL)];
+    const int ka = tid & 15, jp = (tid >> 4) & (PP - 1), cl2 = tid >> (LL - 4);
+    float2 ta[16], tb[16];
+#pragma unroll
+    for (int k = 1; k < 16; ++k) {
+        ta[k] = root_of(P.tw, P.log2L, LL, uint32_t(jl * k));      // w_L^{-jl ka}
+        tb[k] = root_of(P.tw, P.log2L, LL - 4, uint32_t(jp * k));  // w_M^{-jp kb'}
+    }
+    const float2 a = root_of(P.tw, P.log2L, LL + 4, uint32_t(ka) * r);  // w_N1^{-ka r}
+    if (P.conj_in) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i].y = -v[i].y;
+    }
+    dft_regs<4>(v);
+#pragma unroll
+    for (int k = 1; k < 16; ++k) v[k] = cmul(v[k], ta[k]);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) lds[k * S + jl * 16 + cl] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int jm = 0; jm < 16; ++jm) v[jm] = lds[ka * S + (jp + PP * jm) * 16 + cl2];
+    stage_b<PP>(v, tb, jp);
+    float2 *dst = P.dst + addr::sym1_store_base(N2, blockIdx.x, tid, LL);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        // w_N1^{-k r}, k = ka + 16 (i + 16 jp)
+        const float2 y = cmul(v[i], cmul(a, root_of(P.tw, P.log2L, LL + 4, 16u * uint32_t(i + 16 * jp) * r)));
+        float2 *d = dst + addr::sym1_store_off(N2, i);
+        if constexpr (STREAM)
+            st2_stream(d, y);
+        else
+            *d = y;
+    }
+}
+
+// Pass 3, L = 2^LL, in place.  Stage-B thread (cl, jp, ka) = (tid & 15,
+// (tid >> 4) & (P-1), tid >> (4 + log2 P)): column fastest, for the 128-byte
+// runs of the rows it stores; a half-wave of stage-B loads (16 cl x 2 jp) is
+// 32 consecutive items of one plane, so the planes need no padding.
+template <int LL>
+__global__ __launch_bounds__(1 << LL) __attribute__((amdgpu_waves_per_eu(4))) void sym_last_long_kernel(SymPass P)
+{
+    constexpr int L = 1 << LL, M = L >> 4, PP = M >> 4, S = L;
+    __shared__ float2 lds[16 * S];
+    const int tid = threadIdx.x;
+    const uint32_t N1 = uint32_t(P.N1);
+    const int cl = tid & 15, jl = tid >> 4;
+    const float2 *src = P.src + addr::sym3_load_base(N1, blockIdx.x, tid);
+    float2 v[16];
+#pragma unroll
+    for (int jh = 0; jh < 16; ++jh) v[jh] = src[addr::sym3_load_off(N1, jh, LL)];
+    const int jp = (tid >> 4) & (PP - 1), ka = tid >> (LL - 4);
+    float2 ta[16], tb[16];
+#pragma unroll
+    for (int k = 1; k < 16; ++k) {
+        ta[k] = root_of(P.tw, P.log2L, LL, uint32_t(jl * k));
+        tb[k] = root_of(P.tw, P.log2L, LL - 4, uint32_t(jp * k));
+    }
+    dft_regs<4>(v);
+#pragma unroll
+    for (int k = 1; k < 16; ++k) v[k] = cmul(v[k], ta[k]);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) lds[k * S + jl * 16 + cl] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int jm = 0; jm < 16; ++jm) v[jm] = lds[ka * S + (jp + PP * jm) * 16 + cl];
+    stage_b<PP>(v, tb, jp);
+    float2 *dst = P.dst + addr::sym3_store_base(N1, blockIdx.x, tid, LL);
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+        dst[addr::sym3_store_off(N1, i)] = P.out_scale != 0.f ? conj_scale(v[i], P.out_scale) : v[i];
+}
+
+// log2 L of a supported shape (N1 = N2 = 16 L, L = 256, 512, 1024), else 0
+int sym_ll(const SymPass &p)
+{
+    if (p.N1 != p.N2) return 0;
+    const int ll = p.N1 == 4096 ? 8 : p.N1 == 8192 ? 9 : p.N1 == 16384 ? 10 : 0;
+    return ll && p.log2L >= ll + 4 && p.log2N == 2 * (ll + 4) ? ll : 0;
+}
+
 bool sym_shape_ok(const SymPass &p)
 {
-    return p.N1 == 4096 && p.N2 == 4096 && p.log2L >= 12 && p.log2N == 24 && p.src && p.dst && p.tw && p.tw_hi &&
-           p.tw_lo && p.tw_sj;
+    return sym_ll(p) && p.src && p.dst && p.tw && p.tw_hi && p.tw_lo && p.tw_sj;
 }
 
 }  // namespace
@@ -205,22 +359,36 @@ bool sym_shape_ok(const SymPass &p)
 hipError_t launch_sym_first(const SymPass &p, hipStream_t s)
 {
     if (!sym_shape_ok(p)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(sym_first_kernel<true>, dim3(addr::sym1_groups(uint32_t(p.N2))), dim3(kSymThreads), 0, s, p);
+    const dim3 grid(addr::sym1_groups(uint32_t(p.N2)));
+    switch (sym_ll(p)) {
+    case 8: hipLaunchKernelGGL(sym_first_kernel<true>, grid, dim3(kSymThreads), 0, s, p); break;
+    case 9: hipLaunchKernelGGL((sym_first_long_kernel<true, 9>), grid, dim3(512), 0, s, p); break;
+    default: hipLaunchKernelGGL((sym_first_long_kernel<true, 10>), grid, dim3(1024), 0, s, p); break;
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_sym_middle(const SymPass &p, hipStream_t s)
 {
     if (!sym_shape_ok(p)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(sym_middle_kernel, dim3(addr::sym2_groups(uint32_t(p.N1), uint32_t(p.N2))), dim3(kSymThreads), 0,
-                       s, p);
+    const dim3 grid(addr::sym2_groups(uint32_t(p.N1), uint32_t(p.N2)));
+    switch (sym_ll(p)) {
+    case 8: hipLaunchKernelGGL(sym_middle_kernel<8>, grid, dim3(kSymThreads), 0, s, p); break;
+    case 9: hipLaunchKernelGGL(sym_middle_kernel<9>, grid, dim3(kSymThreads), 0, s, p); break;
+    default: hipLaunchKernelGGL(sym_middle_kernel<10>, grid, dim3(kSymThreads), 0, s, p); break;
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_sym_last(const SymPass &p, hipStream_t s)
 {
     if (!sym_shape_ok(p)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(sym_last_kernel, dim3(addr::sym3_groups(uint32_t(p.N1))), dim3(kSymThreads), 0, s, p);
+    const dim3 grid(addr::sym3_groups(uint32_t(p.N1)));
+    switch (sym_ll(p)) {
+    case 8: hipLaunchKernelGGL(sym_last_kernel, grid, dim3(kSymThreads), 0, s, p); break;
+    case 9: hipLaunchKernelGGL(sym_last_long_kernel<9>, grid, dim3(512), 0, s, p); break;
+    default: hipLaunchKernelGGL(sym_last_long_kernel<10>, grid, dim3(1024), 0, s, p); break;
+    }
     return hipGetLastError();
 }
 

@@ -66,34 +66,37 @@ uint32_t item(uint32_t base, uint32_t off, uint64_t N, const char *what)
     return uint32_t(exact);
 }
 
-void audit_sym()
+// N1 = N2 = 16 L, L = 2^ll: L threads per workgroup in passes 1 and 3, 256 in pass 2
+void audit_sym(uint32_t ll)
 {
-    const uint32_t N1 = 4096, N2 = 4096;
+    const uint32_t N1 = 16u << ll, N2 = N1, T = 1u << ll;
     const uint64_t N = uint64_t(N1) * N2;
     {
         Cover rd(N), wr(N);
         for (uint32_t blk = 0; blk < addr::sym1_groups(N2); ++blk)
-            for (uint32_t tid = 0; tid < 256; ++tid)
+            for (uint32_t tid = 0; tid < T; ++tid)
                 for (uint32_t i = 0; i < 16; ++i) {
-                    rd.hit(item(addr::sym1_load_base(N2, blk, tid), addr::sym1_load_off(N2, i), N, "sym pass 1 load"));
-                    wr.hit(item(addr::sym1_store_base(N2, blk, tid), addr::sym1_store_off(N2, i), N, "sym pass 1 store"));
+                    rd.hit(item(addr::sym1_load_base(N2, blk, tid), addr::sym1_load_off(N2, i, ll), N, "sym pass 1 load"));
+                    wr.hit(item(addr::sym1_store_base(N2, blk, tid, ll), addr::sym1_store_off(N2, i), N,
+                                "sym pass 1 store"));
                 }
-        CHECK(rd.exact() && wr.exact(), "sym pass 1 is not a permutation");
+        CHECK(rd.exact() && wr.exact(), "sym pass 1 is not a permutation (L = 2^%u)", ll);
     }
     {
         Cover rd(N), wr(N), blocks(addr::sym2_groups(N1, N2));
         for (uint32_t g = 0; g < addr::sym2_groups(N1, N2); ++g) {
-            const uint32_t blk = addr::sym2_block(g);
+            const uint32_t blk = addr::sym2_block(g, ll);
             CHECK(blk < addr::sym2_groups(N1, N2), "sym pass 2 block id out of range");
             blocks.hit(blk);
             for (uint32_t tid = 0; tid < 256; ++tid)
                 for (uint32_t i = 0; i < 16; ++i) {
-                    rd.hit(item(addr::sym2_load_base(N2, blk, tid), addr::sym2_load_off(i), N, "sym pass 2 load"));
-                    wr.hit(item(addr::sym2_store_base(N1, blk, tid), addr::sym2_store_off(N1, i), N, "sym pass 2 store"));
+                    rd.hit(item(addr::sym2_load_base(N2, blk, tid, ll), addr::sym2_load_off(i), N, "sym pass 2 load"));
+                    wr.hit(item(addr::sym2_store_base(N1, blk, tid, ll), addr::sym2_store_off(N1, i), N,
+                                "sym pass 2 store"));
                 }
         }
-        CHECK(blocks.exact(), "sym pass 2 block order is not a permutation");
-        CHECK(rd.exact() && wr.exact(), "sym pass 2 is not a permutation");
+        CHECK(blocks.exact(), "sym pass 2 block order is not a permutation (L = 2^%u)", ll);
+        CHECK(rd.exact() && wr.exact(), "sym pass 2 is not a permutation (L = 2^%u)", ll);
     }
     {
         Cover rd(N), wr(N);
@@ -101,10 +104,12 @@ void audit_sym()
         for (uint32_t blk = 0; blk < addr::sym3_groups(N1); ++blk) {
             a.clear();
             b.clear();
-            for (uint32_t tid = 0; tid < 256; ++tid)
+            for (uint32_t tid = 0; tid < T; ++tid)
                 for (uint32_t i = 0; i < 16; ++i) {
-                    a.push_back(item(addr::sym3_load_base(N1, blk, tid), addr::sym3_load_off(N1, i), N, "sym pass 3 load"));
-                    b.push_back(item(addr::sym3_store_base(N1, blk, tid), addr::sym3_store_off(N1, i), N, "sym pass 3 store"));
+                    a.push_back(item(addr::sym3_load_base(N1, blk, tid), addr::sym3_load_off(N1, i, ll), N,
+                                     "sym pass 3 load"));
+                    b.push_back(item(addr::sym3_store_base(N1, blk, tid, ll), addr::sym3_store_off(N1, i), N,
+                                     "sym pass 3 store"));
                 }
             for (uint32_t x : a) rd.hit(x);
             for (uint32_t x : b) wr.hit(x);
@@ -112,9 +117,10 @@ void audit_sym()
             std::sort(b.begin(), b.end());
             CHECK(a == b, "sym pass 3 workgroup %u reads and writes different items (in place)", blk);
         }
-        CHECK(rd.exact() && wr.exact(), "sym pass 3 is not a permutation");
+        CHECK(rd.exact() && wr.exact(), "sym pass 3 is not a permutation (L = 2^%u)", ll);
     }
-    std::printf("ok symmetric split form 4096 x 4096: three passes are permutations, pass 3 in place per workgroup\n");
+    std::printf("ok symmetric split form %u x %u: three passes are permutations, pass 3 in place per workgroup\n", N1,
+                N2);
 }
 
 // the split form of Phase I for N1 = 16 M, every pass over every workgroup;
@@ -268,7 +274,8 @@ int main(int argc, char **argv)
 {
     const bool full = argc > 1;  // also the 2^28 shapes (about 2 x 2^28 items per pass)
     audit_digit_maps();
-    audit_sym();
+    audit_sym(8);
+    audit_sym(9);
     audit_mf_exchange("pass 1", addr::kMf1Items, addr::mf1_store, addr::mf1_load, true, addr::kMf1Spare);
     audit_mf_exchange("pass 2", 16 * 256, addr::mf2_store, addr::mf2_load, false, -1);
     audit_mf_exchange("pass 3", addr::kMf1Items, addr::mf3_store, addr::mf3_load, false, addr::kMf3Spare);
@@ -279,6 +286,7 @@ int main(int argc, char **argv)
             for (int t : {1, 2, 3, 4})
                 audit_split(N1, N2, t, true);
     if (full) {  // the 2^28 shapes the benchmark times, every workgroup
+        audit_sym(10);
         audit_split(16384, 16384, 2, false);
         audit_split(16384, 16384, 4, true);
         audit_split(8192, 32768, 1, false);
