@@ -114,6 +114,26 @@ namespace addr {
 // column fastest in pass 3 (cl, jp, ka) = (tid & 15, (tid >> 4) & (P - 1),
 // tid >> (4 + ll - 8)); jp picks the outputs kB = i + 16 jp of the thread.
 
+// Block orders: the hardware's workgroup id g of a pass maps to its tile blk
+// (a permutation of [0, groups)); the order decides which tiles run at the
+// same time, and so how far apart in HBM their loads and stores fall.
+// Measured per L (pass times in us, transform in ms):
+//   L = 256  (4096^2):  tile order (cb / vb fastest) in passes 1 and 3, jc
+//            fastest in pass 2: 42.0 / 54.3 / 42.4; other orders within 1-2%.
+//   L = 512  (8192^2):  the same in passes 1 and 3, kb fastest in pass 2
+//            (its stores then fill whole rows): 264 / 212 / 244, 0.706 ms,
+//            against 262 / 276 / 243 (0.756) with jc fastest.
+//   L = 1024 (16384^2): r (q0) fastest in passes 1 (3), kb fastest in pass 2:
+//            1215 / 879 / 1328, 3.43 ms, against 1309 / 922 / 1399 (3.67).
+PACO_HD uint32_t sym1_block(uint32_t g, uint32_t N2, uint32_t ll = 8)
+{
+    return ll >= 10 ? (g & 15u) * (N2 >> 4) + (g >> 4) : g;  // r fastest : cb fastest
+}
+PACO_HD uint32_t sym3_block(uint32_t g, uint32_t N1, uint32_t ll = 8)
+{
+    return ll >= 10 ? (g & 15u) * (N1 >> 4) + (g >> 4) : g;  // q0 fastest : vb fastest
+}
+
 // pass 1: workgroup (r, cb) = (blk / (N2/16), blk mod (N2/16)); thread
 // (cl, jl) loads row 16 (jl + (L/16) i) + r, column 16 cb + cl
 PACO_HD uint32_t sym1_load_base(uint32_t N2, uint32_t blk, uint32_t tid)
@@ -133,12 +153,14 @@ PACO_HD uint32_t sym1_store_base(uint32_t N2, uint32_t blk, uint32_t tid, uint32
     return ((16u * jp * N2 + (cb << 4) + cl) << 8) + 16u * r + (tid & 15u);
 }
 PACO_HD uint32_t sym1_store_off(uint32_t N2, uint32_t i) { return i * N2 * 256u; }
-// pass 2: the hardware's workgroup id g maps to (jc, kb) = (g mod L, g / L)
-// (jc fastest: neighbouring workgroups read neighbouring 2 KiB runs);
-// blk = (L/16) jc + kb.  Thread (kk, rr) loads U[jc + L rr][i][16 kb + kk].
+// pass 2: tile blk = (L/16) jc + kb.  L = 256: the hardware's workgroup id g
+// maps to (jc, kb) = (g mod L, g / L) (jc fastest: neighbouring workgroups
+// read neighbouring 2 KiB runs); L >= 512: blk = g (kb fastest: the running
+// workgroups' stores fill whole rows of W).  Thread (kk, rr) loads
+// U[jc + L rr][i][16 kb + kk].
 PACO_HD uint32_t sym2_block(uint32_t g, uint32_t ll = 8)
 {
-    return ((g & ((1u << ll) - 1u)) << (ll - 4)) | (g >> ll);
+    return ll == 8 ? ((g & ((1u << ll) - 1u)) << (ll - 4)) | (g >> ll) : g;
 }
 PACO_HD uint32_t sym2_load_base(uint32_t N2, uint32_t blk, uint32_t tid, uint32_t ll = 8)
 {

@@ -70,10 +70,11 @@ __global__ __launch_bounds__(kSymThreads) void sym_first_kernel(SymPass P)
     __shared__ float2 lds[16 * kPlaneK];
     const int tid = threadIdx.x;
     const uint32_t N2 = uint32_t(P.N2);
-    const uint32_t r = blockIdx.x / (N2 >> 4);
+    const uint32_t blk = addr::sym1_block(blockIdx.x, N2);
+    const uint32_t r = blk / (N2 >> 4);
     const int cl = tid & 15, jl = tid >> 4;
     float2 v[16];
-    const float2 *src = P.src + addr::sym1_load_base(N2, blockIdx.x, tid);
+    const float2 *src = P.src + addr::sym1_load_base(N2, blk, tid);
 #pragma unroll
     for (int jh = 0; jh < 16; ++jh) v[jh] = src[addr::sym1_load_off(N2, jh)];
     // every twiddle factor, issued behind the data loads
@@ -97,7 +98,7 @@ __global__ __launch_bounds__(kSymThreads) void sym_first_kernel(SymPass P)
 #pragma unroll
     for (int j = 0; j < 16; ++j) v[j] = lds[kl * kPlaneK + j * 16 + cl2];
     dft_regs<4>(v);
-    float2 *dst = P.dst + addr::sym1_store_base(N2, blockIdx.x, tid);
+    float2 *dst = P.dst + addr::sym1_store_base(N2, blk, tid);
 #pragma unroll
     for (int kh = 0; kh < 16; ++kh) {
         const float2 y = cmul(v[kh], cmul(a, b[kh]));
@@ -174,7 +175,8 @@ __global__ __launch_bounds__(kSymThreads) void sym_last_kernel(SymPass P)
     const int tid = threadIdx.x;
     const uint32_t N1 = uint32_t(P.N1);
     const int cl = tid & 15, jl = tid >> 4;
-    const float2 *src = P.src + addr::sym3_load_base(N1, blockIdx.x, tid);
+    const uint32_t blk = addr::sym3_block(blockIdx.x, N1);
+    const float2 *src = P.src + addr::sym3_load_base(N1, blk, tid);
     float2 v[16];
 #pragma unroll
     for (int jh = 0; jh < 16; ++jh) v[jh] = src[addr::sym3_load_off(N1, jh)];
@@ -191,7 +193,7 @@ __global__ __launch_bounds__(kSymThreads) void sym_last_kernel(SymPass P)
 #pragma unroll
     for (int j = 0; j < 16; ++j) v[j] = lds[kl * kPlaneR + j * 16 + cl];
     dft_regs<4>(v);
-    float2 *dst = P.dst + addr::sym3_store_base(N1, blockIdx.x, tid);
+    float2 *dst = P.dst + addr::sym3_store_base(N1, blk, tid);
 #pragma unroll
     for (int kh = 0; kh < 16; ++kh)
         dst[addr::sym3_store_off(N1, kh)] = P.out_scale != 0.f ? conj_scale(v[kh], P.out_scale) : v[kh];
@@ -263,10 +265,11 @@ __global__ __launch_bounds__(1 << LL) __attribute__((amdgpu_waves_per_eu(4))) vo
     __shared__ float2 lds[16 * S];
     const int tid = threadIdx.x;
     const uint32_t N2 = uint32_t(P.N2);
-    const uint32_t r = blockIdx.x / (N2 >> 4);
+    const uint32_t blk = addr::sym1_block(blockIdx.x, N2, LL);
+    const uint32_t r = blk / (N2 >> 4);
     const int cl = tid & 15, jl = tid >> 4;
     float2 v[16];
-    const float2 *src = P.src + addr::sym1_load_base(N2, blockIdx.x, tid);
+    const float2 *src = P.src + addr::sym1_load_base(N2, blk, tid);
 #pragma unroll
     for (int jh = 0; jh < 16; ++jh) v[jh] = src[addr::sym1_load_off(N2, jh, LL)];
     const int ka = tid & 15, jp = (tid >> 4) & (PP - 1), cl2 = tid >> (LL - 4);
@@ -290,7 +293,7 @@ __global__ __launch_bounds__(1 << LL) __attribute__((amdgpu_waves_per_eu(4))) vo
 #pragma unroll
     for (int jm = 0; jm < 16; ++jm) v[jm] = lds[ka * S + (jp + PP * jm) * 16 + cl2];
     stage_b<PP>(v, tb, jp);
-    float2 *dst = P.dst + addr::sym1_store_base(N2, blockIdx.x, tid, LL);
+    float2 *dst = P.dst + addr::sym1_store_base(N2, blk, tid, LL);
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         // w_N1^{-k r}, k = ka + 16 (i + 16 jp)
@@ -315,7 +318,8 @@ __global__ __launch_bounds__(1 << LL) __attribute__((amdgpu_waves_per_eu(4))) vo
     const int tid = threadIdx.x;
     const uint32_t N1 = uint32_t(P.N1);
     const int cl = tid & 15, jl = tid >> 4;
-    const float2 *src = P.src + addr::sym3_load_base(N1, blockIdx.x, tid);
+    const uint32_t blk = addr::sym3_block(blockIdx.x, N1, LL);
+    const float2 *src = P.src + addr::sym3_load_base(N1, blk, tid);
     float2 v[16];
 #pragma unroll
     for (int jh = 0; jh < 16; ++jh) v[jh] = src[addr::sym3_load_off(N1, jh, LL)];
@@ -335,7 +339,7 @@ __global__ __launch_bounds__(1 << LL) __attribute__((amdgpu_waves_per_eu(4))) vo
 #pragma unroll
     for (int jm = 0; jm < 16; ++jm) v[jm] = lds[ka * S + (jp + PP * jm) * 16 + cl];
     stage_b<PP>(v, tb, jp);
-    float2 *dst = P.dst + addr::sym3_store_base(N1, blockIdx.x, tid, LL);
+    float2 *dst = P.dst + addr::sym3_store_base(N1, blk, tid, LL);
 #pragma unroll
     for (int i = 0; i < 16; ++i)
         dst[addr::sym3_store_off(N1, i)] = P.out_scale != 0.f ? conj_scale(v[i], P.out_scale) : v[i];

@@ -72,14 +72,19 @@ void audit_sym(uint32_t ll)
     const uint32_t N1 = 16u << ll, N2 = N1, T = 1u << ll;
     const uint64_t N = uint64_t(N1) * N2;
     {
-        Cover rd(N), wr(N);
-        for (uint32_t blk = 0; blk < addr::sym1_groups(N2); ++blk)
+        Cover rd(N), wr(N), blocks(addr::sym1_groups(N2));
+        for (uint32_t g = 0; g < addr::sym1_groups(N2); ++g) {
+            const uint32_t blk = addr::sym1_block(g, N2, ll);
+            CHECK(blk < addr::sym1_groups(N2), "sym pass 1 block id out of range");
+            blocks.hit(blk);
             for (uint32_t tid = 0; tid < T; ++tid)
                 for (uint32_t i = 0; i < 16; ++i) {
                     rd.hit(item(addr::sym1_load_base(N2, blk, tid), addr::sym1_load_off(N2, i, ll), N, "sym pass 1 load"));
                     wr.hit(item(addr::sym1_store_base(N2, blk, tid, ll), addr::sym1_store_off(N2, i), N,
                                 "sym pass 1 store"));
                 }
+        }
+        CHECK(blocks.exact(), "sym pass 1 block order is not a permutation (L = 2^%u)", ll);
         CHECK(rd.exact() && wr.exact(), "sym pass 1 is not a permutation (L = 2^%u)", ll);
     }
     {
@@ -99,9 +104,12 @@ void audit_sym(uint32_t ll)
         CHECK(rd.exact() && wr.exact(), "sym pass 2 is not a permutation (L = 2^%u)", ll);
     }
     {
-        Cover rd(N), wr(N);
+        Cover rd(N), wr(N), blocks(addr::sym3_groups(N1));
         std::vector<uint32_t> a, b;
-        for (uint32_t blk = 0; blk < addr::sym3_groups(N1); ++blk) {
+        for (uint32_t g = 0; g < addr::sym3_groups(N1); ++g) {
+            const uint32_t blk = addr::sym3_block(g, N1, ll);
+            CHECK(blk < addr::sym3_groups(N1), "sym pass 3 block id out of range");
+            blocks.hit(blk);
             a.clear();
             b.clear();
             for (uint32_t tid = 0; tid < T; ++tid)
@@ -117,6 +125,7 @@ void audit_sym(uint32_t ll)
             std::sort(b.begin(), b.end());
             CHECK(a == b, "sym pass 3 workgroup %u reads and writes different items (in place)", blk);
         }
+        CHECK(blocks.exact(), "sym pass 3 block order is not a permutation (L = 2^%u)", ll);
         CHECK(rd.exact() && wr.exact(), "sym pass 3 is not a permutation (L = 2^%u)", ll);
     }
     std::printf("ok symmetric split form %u x %u: three passes are permutations, pass 3 in place per workgroup\n", N1,
