@@ -296,7 +296,7 @@ def bench_batched(steps: int, warmup: int):
 
 PRECISION_WORKLOADS = [  # N = 2^24 and 2^26, |x| = 10^U[-4,4], arg x ~ U[0, 2 pi), seed 5
     dict(name="2^24", N1=4096, N2=4096, p=64, b=16),
-    dict(name="2^26", N1=4096, N2=1 << 14, p=64, b=4),
+    dict(name="2^26", N1=1 << 13, N2=1 << 13, p=64, b=2),  # the square shape: the symmetric form, 3 passes
 ]
 FORMS = [(0, "fp32"), (1, "fp16x3"), (2, "bf16x3"), (3, "bf16x6")]
 
@@ -651,8 +651,8 @@ def main():
         torch.cuda.empty_cache()
         rec["precision"], prec_outs = bench_precision(max(20, args.steps), 3)
         rec["precision"]["workload"] = ("log-uniform |x| = 10^U[-4,4], uniform phase (seed 5); N = 2^24 as 4096 x 4096 "
-                                       "(b = 16) and N = 2^26 as 4096 x 16384 (b = 4); split forms run every "
-                                       "radix-16 butterfly on MFMA")
+                                       "(b = 16) and N = 2^26 as 8192 x 8192 (b = 2), both in the symmetric split "
+                                       "form; split forms run every radix-16 butterfly on MFMA")
 
     if not args.skip_cpu_baseline:
         import oracle

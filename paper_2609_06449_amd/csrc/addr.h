@@ -225,6 +225,27 @@ PACO_HD int mf3_load(int g, int half, int i, int n)
     const int b0 = g * 260 + 144 * half + n;
     return ((i & 1) ? b0 - 32 * half : b0) + 16 * i;
 }
+// L = 512 (N1 = N2 = 8192): 16 rows of 512 columns, row stride 516.  Stage-B
+// butterflies of both passes pair up as groups 2 g + jp (jp: the half of
+// the 32-point transform), so their loads add 16 jp to the column: pass 1
+// loads row n, column 16 (jp + 2 (8 half + i)) + c; pass 3 loads row g,
+// column 16 (jp + 2 (8 half + i)) + n.  Pass 1: item (row, col) at
+// row * 516 + col + (col >> 8) + 2 (row >> 3 & 1); pass 3: row * 516 +
+// (col ^ 16 (col >> 8)).  Conflict-free as above (checked by the audit).
+constexpr int kMfLStride = 516, kMfLItems = 16 * kMfLStride;
+PACO_HD int mf1L_store(int kb, int i, int j, int n)
+{
+    return (4 * kb + i) * kMfLStride + 16 * j + n + (j >> 4) + 2 * (kb >> 1);
+}
+PACO_HD int mf1L_load(int n, int half, int i, int jp, int c)
+{
+    return n * kMfLStride + 2 * (n >> 3) + 257 * half + 32 * i + 16 * jp + c;
+}
+PACO_HD int mf3L_store(int kb, int i, int j, int n) { return (4 * kb + i) * kMfLStride + 16 * (j ^ (j >> 4)) + n; }
+PACO_HD int mf3L_load(int g, int half, int i, int jp, int n)
+{
+    return g * kMfLStride + 256 * half + 32 * i + n + 16 * (jp ^ half);
+}
 PACO_HD int mf2_store(int kb, int i, int j, int n)
 {
     const int f = (kb ^ (j >> 3)) & 1;

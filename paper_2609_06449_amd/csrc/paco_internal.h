@@ -243,6 +243,9 @@ hipError_t launch_split_middle(const SplitPass &p, hipStream_t s);
 hipError_t split_prepare();  // raises the dynamic-LDS limit of the three-stage pass 2 once
 // The three passes of the symmetric split form; hipErrorInvalidValue unless
 // N1 = N2 = 4096.
+// log2 L of a shape the symmetric form runs (N1 = N2 = 16 L, L = 256, 512,
+// 1024; the split MFMA forms: 256 and 512), else 0
+int sym_log2_child(const SymPass &p);
 hipError_t launch_sym_first(const SymPass &p, hipStream_t s);
 hipError_t launch_sym_middle(const SymPass &p, hipStream_t s);
 hipError_t launch_sym_last(const SymPass &p, hipStream_t s);

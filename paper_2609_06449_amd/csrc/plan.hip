@@ -257,10 +257,10 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
         for (int64_t k = 0; k < 16 * N1; ++k) tcw[k] = paco::root_neg(k, 16 * N1);
     }
     paco::middle_tables(P->lN, thi, tlo, ttile);
-    // the symmetric split form (N1 = N2 = 16 L: L = 256 for every dtype, 512
-    // and 1024 in FP32; option PACO_PLAN_NO_SYM)
+    // the symmetric split form (N1 = N2 = 16 L: L = 256 and 512 for every
+    // dtype, 1024 in FP32; option PACO_PLAN_NO_SYM)
     const bool sym_form = !no_split && !no_sym && !paper_layout && !generic && P->l1 == P->l2 &&
-                          (P->l1 == paco::kSymLog2N || (dt == PACO_C64 && (P->l1 == 13 || P->l1 == 14)));
+                          (P->l1 == paco::kSymLog2N || P->l1 == 13 || (dt == PACO_C64 && P->l1 == 14));
     if (sym_form) {  // its pass-2 factor w_{16 N2}^{-s jc}, s < 16, jc < L
         const int64_t L = N1 / 16;
         tsj.resize(size_t(16 * L));

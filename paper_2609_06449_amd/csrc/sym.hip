@@ -345,13 +345,7 @@ __global__ __launch_bounds__(1 << LL) __attribute__((amdgpu_waves_per_eu(4))) vo
         dst[addr::sym3_store_off(N1, i)] = P.out_scale != 0.f ? conj_scale(v[i], P.out_scale) : v[i];
 }
 
-// log2 L of a supported shape (N1 = N2 = 16 L, L = 256, 512, 1024), else 0
-int sym_ll(const SymPass &p)
-{
-    if (p.N1 != p.N2) return 0;
-    const int ll = p.N1 == 4096 ? 8 : p.N1 == 8192 ? 9 : p.N1 == 16384 ? 10 : 0;
-    return ll && p.log2L >= ll + 4 && p.log2N == 2 * (ll + 4) ? ll : 0;
-}
+int sym_ll(const SymPass &p) { return sym_log2_child(p); }
 
 bool sym_shape_ok(const SymPass &p)
 {
@@ -359,6 +353,13 @@ bool sym_shape_ok(const SymPass &p)
 }
 
 }  // namespace
+
+int sym_log2_child(const SymPass &p)
+{
+    if (p.N1 != p.N2) return 0;
+    const int ll = p.N1 == 4096 ? 8 : p.N1 == 8192 ? 9 : p.N1 == 16384 ? 10 : 0;
+    return ll && p.log2L >= ll + 4 && p.log2N == 2 * (ll + 4) ? ll : 0;
+}
 
 hipError_t launch_sym_first(const SymPass &p, hipStream_t s)
 {

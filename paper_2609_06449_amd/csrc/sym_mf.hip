@@ -187,34 +187,34 @@ __global__ __launch_bounds__(256) void sym_first_mf_kernel(SymPass P)
 
 // Pass 2: stage 1 butterfly (kk = n, rr = 4 w + G) over r, stage 2 butterfly
 // (kk = n, s = 4 w + G) over rr.  The twiddle of stage-1 output s of group G
-// is w_N^{-c (k + 256 s)}, c = jc + 256 rr, s = 4 kb + i: the first (i = 0)
-// from the two-level table, each next one times w_65536^{-c}, which is the
+// is w_N^{-c (k + L s)}, c = jc + L rr, s = 4 kb + i: the first (i = 0)
+// from the two-level table, each next one times w_{16 N2}^{-c}, which is the
 // same for the whole wave (scalar loads).  That keeps the twiddle loads few
 // (one pair per group) and issued right behind the data loads; with one
 // lookup per output the compiler spread 32 loads, each waited for, between
 // the butterflies.
-template <int PREC>
+template <int PREC, int LL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == kPrecBF16x6 ? 4 : 5))) void sym_middle_mf_kernel(SymPass P)
 {
     __shared__ float2 lds[16 * 256];
     const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n = lane & 15, kb = lane >> 4, comp = kb >> 1, half = kb & 1;
     const uint32_t N1 = uint32_t(P.N1), N2 = uint32_t(P.N2);
-    const uint32_t blk = addr::sym2_block(blockIdx.x);
-    const uint32_t jc = blk >> 4, k = 16u * (blk & 15) + n;
+    const uint32_t blk = addr::sym2_block(blockIdx.x, LL);
+    const uint32_t jc = blk >> (LL - 4), k = 16u * (blk & ((1u << (LL - 4)) - 1u)) + n;
     float2 it[4][4];
 #pragma unroll
     for (int G = 0; G < 4; ++G) {
-        const float2 *src = P.src + addr::sym2_load_base(N2, blk, uint32_t(n + 16 * (4 * w + G)));
+        const float2 *src = P.src + addr::sym2_load_base(N2, blk, uint32_t(n + 16 * (4 * w + G)), LL);
 #pragma unroll
         for (int q = 0; q < 4; ++q) it[G][q] = ld2_last(src + addr::sym2_load_off(uint32_t(8 * half + (comp ? 4 + q : q))));
     }
     const uint32_t nmask = uint32_t((uint64_t(1) << P.log2N) - 1), lomask = (1u << P.log2Lo) - 1u;
-    float2 th[4], tl[4];  // w_N^{-c (k + 1024 kb)} as its two table factors
+    float2 th[4], tl[4];  // w_N^{-c (k + 4 L kb)} as its two table factors
 #pragma unroll
     for (int G = 0; G < 4; ++G) {
-        const uint32_t c = jc + 256u * uint32_t(4 * w + G);
-        const uint32_t e = (c * (k + 1024u * uint32_t(kb))) & nmask;
+        const uint32_t c = jc + (uint32_t(4 * w + G) << LL);
+        const uint32_t e = (c * (k + (uint32_t(kb) << (LL + 2)))) & nmask;
         th[G] = P.tw_hi[e >> P.log2Lo];
         tl[G] = P.tw_lo[e & lomask];
     }
@@ -225,14 +225,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == kPr
     // FP16x3: one scale per butterfly (mf_scale_exp), scaled back inside the
     // twiddle factor; a scale per wave measured slower here, since no group
     // could start before the wave's last load had arrived
-    const float2 sj = P.tw_sj[256 + jc];  // w_65536^{-jc}
+    const float2 sj = P.tw_sj[(1u << LL) + jc];  // w_{16 N2}^{-jc}
     float2 o[4][4];
 #pragma unroll
     for (int G = 0; G < 4; ++G) {
         const int e1 = PREC == kPrecFP16x3 ? mf_scale_exp(x[G]) : 0;
         W.dft(x[G], o[G], e1);
         const int rr = 4 * w + G;
-        const float2 step = cmul(sj, root_of(P.tw, P.log2L, 8, uint32_t(rr)));  // w_65536^{-c}
+        const float2 step = cmul(sj, root_of(P.tw, P.log2L, 8, uint32_t(rr)));  // w_{16 N2}^{-c}
         float2 t = cmul(th[G], tl[G]);
         if constexpr (PREC == kPrecFP16x3) t = make_float2(ldexpf(t.x, e1), ldexpf(t.y, e1));
 #pragma unroll
@@ -245,7 +245,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == kPr
     __syncthreads();
     float2 t4[4];  // w_N2^{-q0 jc}, q0 = 4 kb + i
 #pragma unroll
-    for (int i = 0; i < 4; ++i) t4[i] = root_of(P.tw, P.log2L, 12, uint32_t(4 * kb + i) * jc);
+    for (int i = 0; i < 4; ++i) t4[i] = root_of(P.tw, P.log2L, LL + 4, uint32_t(4 * kb + i) * jc);
     const float *ldf = reinterpret_cast<const float *>(lds) + comp;
 #pragma unroll
     for (int G = 0; G < 4; ++G) {
@@ -264,7 +264,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == kPr
         const uint32_t q0 = uint32_t(4 * kb + i);
 #pragma unroll
         for (int G = 0; G < 4; ++G) {
-            float2 *d = P.dst + addr::sym2_store_base(N1, blk, uint32_t(n + 16 * (4 * w + G)));
+            float2 *d = P.dst + addr::sym2_store_base(N1, blk, uint32_t(n + 16 * (4 * w + G)), LL);
             d[addr::sym2_store_off(N1, q0)] = q0 ? cmul(o[G][i], t4[i]) : o[G][i];
         }
     }
@@ -327,16 +327,195 @@ __global__ __launch_bounds__(256) void sym_last_mf_kernel(SymPass P)
     }
 }
 
-template <int PREC>
-hipError_t launch_pass(int pass, const SymPass &p, hipStream_t s)
+// ---- L = 512 (N1 = N2 = 8192): passes 1 and 3, 512 threads -----------------
+// Stage A as at L = 256 (butterfly (cl = n, jl = 4 w + G) over jh, j = jl +
+// 32 jh).  Stage B: the 32-point transform over jl = jp + 2 jm of each (ka,
+// column) as radix 16 over jm in two MFMA groups G = 2 g + jp of one wave,
+// twiddle w_32^{-jp kb'}, and the radix-2 step between the two groups in
+// registers (both halves of a transform sit in the same lane): outputs
+// kb' + 16 kc, k = ka + 16 (kb' + 16 kc).  FP16x3: one scale for the tile,
+// the eight wave maxima met in a small LDS array.
+
+// the tile's scale from its eight waves' maxima
+__device__ __forceinline__ int tile_scale8(const float (&x)[4][8], float *red, int lane, int w)
 {
-    if (pass == 1)
-        hipLaunchKernelGGL(sym_first_mf_kernel<PREC>, dim3(addr::sym1_groups(uint32_t(p.N2))), dim3(256), 0, s, p);
-    else if (pass == 2)
-        hipLaunchKernelGGL(sym_middle_mf_kernel<PREC>, dim3(addr::sym2_groups(uint32_t(p.N1), uint32_t(p.N2))),
-                           dim3(256), 0, s, p);
-    else
-        hipLaunchKernelGGL(sym_last_mf_kernel<PREC>, dim3(addr::sym3_groups(uint32_t(p.N1))), dim3(256), 0, s, p);
+    const float m = wave_absmax(x);
+    if (lane == 0) red[w] = m;
+    __syncthreads();
+    float t = red[0];
+#pragma unroll
+    for (int i = 1; i < 8; ++i) t = fmaxf(t, red[i]);
+    return scale_of(t);
+}
+
+// stage-B tail: twiddle the jp = 1 group by w_32^{-kb'} and combine the two
+// groups of each pair (outputs kb' in group 2 g, kb' + 16 in group 2 g + 1)
+__device__ __forceinline__ void radix2_pairs(float2 (&o)[4][4], const float2 (&tb)[4])
+{
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float2 y0 = o[2 * g][i], y1 = cmul(o[2 * g + 1][i], tb[i]);
+            o[2 * g][i] = make_float2(y0.x + y1.x, y0.y + y1.y);
+            o[2 * g + 1][i] = make_float2(y0.x - y1.x, y0.y - y1.y);
+        }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void sym_first_mf_long_kernel(SymPass P)
+{
+    constexpr int LL = 9;
+    __shared__ float2 lds[addr::kMfLItems];
+    __shared__ float red[8];
+    const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int n = lane & 15, kb = lane >> 4, comp = kb >> 1, half = kb & 1;
+    const uint32_t N2 = uint32_t(P.N2);
+    const uint32_t blk = addr::sym1_block(blockIdx.x, N2, LL);
+    const uint32_t r = blk / (N2 >> 4);
+    const MfW16<PREC> W(P.w16, lane);
+    float x[4][8];
+    {
+        float2 it[4][4];
+#pragma unroll
+        for (int G = 0; G < 4; ++G) {
+            const float2 *src = P.src + addr::sym1_load_base(N2, blk, uint32_t(n + 16 * (4 * w + G)));
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                it[G][k] = src[addr::sym1_load_off(N2, uint32_t(8 * half + (comp ? 4 + k : k)), LL)];
+        }
+#pragma unroll
+        for (int G = 0; G < 4; ++G) mf_load_ops(it[G], x[G], comp, P.conj_in != 0);
+    }
+    float2 t1[4][4], tb[4];
+#pragma unroll
+    for (int G = 0; G < 4; ++G)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) t1[G][i] = root_of(P.tw, P.log2L, LL, uint32_t((4 * w + G) * (4 * kb + i)));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) tb[i] = root_of(P.tw, P.log2L, 5, uint32_t(4 * kb + i));  // w_32^{-kb'}
+    const int e = PREC == kPrecFP16x3 ? tile_scale8(x, red, lane, w) : 0;
+    float2 o[4][4];
+#pragma unroll
+    for (int G = 0; G < 4; ++G) {
+        W.dft(x[G], o[G], e);
+        const int jl = 4 * w + G;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) lds[addr::mf1L_store(kb, i, jl, n)] = cmul(o[G][i], t1[G][i]);
+    }
+    __syncthreads();
+    const float *ldf = reinterpret_cast<const float *>(lds) + comp;
+#pragma unroll
+    for (int G = 0; G < 4; ++G) {
+        const int cl2 = 2 * w + (G >> 1), jp = G & 1;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) x[G][i] = ldf[2 * addr::mf1L_load(n, half, i, jp, cl2)];
+        W.dft(x[G], o[G]);
+    }
+    radix2_pairs(o, tb);
+    // outputs k = ka + 16 (kb' + 16 kc), ka = n, kb' = 4 kb + i, times w_N1^{-k r}
+    const float2 a = root_of(P.tw, P.log2L, LL + 4, uint32_t(n) * r);
+#pragma unroll
+    for (int kc = 0; kc < 2; ++kc)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t kbp = uint32_t(4 * kb + i);
+            float2 t = cmul(a, root_of(P.tw, P.log2L, LL + 4, 16u * (kbp + 16u * kc) * r));
+            if constexpr (PREC == kPrecFP16x3) t = make_float2(ldexpf(t.x, e), ldexpf(t.y, e));
+#pragma unroll
+            for (int g = 0; g < 2; ++g) {
+                float2 *d = P.dst + addr::sym1_store_base(N2, blk, uint32_t(n + 16 * kc + 32 * (2 * w + g)), LL);
+                st2_stream(d + addr::sym1_store_off(N2, kbp), cmul(o[2 * g + kc][i], t));
+            }
+        }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void sym_last_mf_long_kernel(SymPass P)
+{
+    constexpr int LL = 9;
+    __shared__ float2 lds[addr::kMfLItems];
+    __shared__ float red[8];
+    const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int n = lane & 15, kb = lane >> 4, comp = kb >> 1, half = kb & 1;
+    const uint32_t N1 = uint32_t(P.N1);
+    const uint32_t blk = addr::sym3_block(blockIdx.x, N1, LL);
+    const MfW16<PREC> W(P.w16, lane);
+    float x[4][8];
+    {
+        float2 it[4][4];
+#pragma unroll
+        for (int G = 0; G < 4; ++G) {
+            const float2 *src = P.src + addr::sym3_load_base(N1, blk, uint32_t(n + 16 * (4 * w + G)));
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                it[G][q] = src[addr::sym3_load_off(N1, uint32_t(8 * half + (comp ? 4 + q : q)), LL)];
+        }
+#pragma unroll
+        for (int G = 0; G < 4; ++G) mf_swap_in(it[G], x[G]);
+    }
+    float2 t1[4][4], tb[4];
+#pragma unroll
+    for (int G = 0; G < 4; ++G)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) t1[G][i] = root_of(P.tw, P.log2L, LL, uint32_t((4 * w + G) * (4 * kb + i)));
+#pragma unroll
+    for (int i = 0; i < 4; ++i) tb[i] = root_of(P.tw, P.log2L, 5, uint32_t(4 * kb + i));
+    const int e = PREC == kPrecFP16x3 ? tile_scale8(x, red, lane, w) : 0;
+    float2 o[4][4];
+#pragma unroll
+    for (int G = 0; G < 4; ++G) {
+        W.dft(x[G], o[G], e);
+        const int jl = 4 * w + G;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) lds[addr::mf3L_store(kb, i, jl, n)] = cmul(o[G][i], t1[G][i]);
+    }
+    __syncthreads();
+    const float *ldf = reinterpret_cast<const float *>(lds) + comp;
+#pragma unroll
+    for (int G = 0; G < 4; ++G) {
+        const int ka = 2 * w + (G >> 1), jp = G & 1;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) x[G][i] = ldf[2 * addr::mf3L_load(ka, half, i, jp, n)];
+        W.dft(x[G], o[G]);
+    }
+    radix2_pairs(o, tb);
+    // outputs q = ka + 16 (kb' + 16 kc) of column v = 16 vb + n, row q0 + 16 q
+    const float osc = ldexpf(1.0f, e);  // 1 except in FP16x3
+#pragma unroll
+    for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int kc = 0; kc < 2; ++kc) {
+            float2 *d = P.dst + addr::sym3_store_base(N1, blk, uint32_t(n + 16 * kc + 32 * (2 * w + g)), LL);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float2 y = o[2 * g + kc][i];
+                d[addr::sym3_store_off(N1, uint32_t(4 * kb + i))] =
+                    P.out_scale != 0.f ? conj_scale(y, P.out_scale * osc) : make_float2(y.x * osc, y.y * osc);
+            }
+        }
+}
+
+template <int PREC>
+hipError_t launch_pass(int pass, int ll, const SymPass &p, hipStream_t s)
+{
+    const dim3 g1(addr::sym1_groups(uint32_t(p.N2))), g2(addr::sym2_groups(uint32_t(p.N1), uint32_t(p.N2))),
+        g3(addr::sym3_groups(uint32_t(p.N1)));
+    if (ll == 8) {
+        if (pass == 1)
+            hipLaunchKernelGGL(sym_first_mf_kernel<PREC>, g1, dim3(256), 0, s, p);
+        else if (pass == 2)
+            hipLaunchKernelGGL((sym_middle_mf_kernel<PREC, 8>), g2, dim3(256), 0, s, p);
+        else
+            hipLaunchKernelGGL(sym_last_mf_kernel<PREC>, g3, dim3(256), 0, s, p);
+    } else {
+        if (pass == 1)
+            hipLaunchKernelGGL(sym_first_mf_long_kernel<PREC>, g1, dim3(512), 0, s, p);
+        else if (pass == 2)
+            hipLaunchKernelGGL((sym_middle_mf_kernel<PREC, 9>), g2, dim3(256), 0, s, p);
+        else
+            hipLaunchKernelGGL(sym_last_mf_long_kernel<PREC>, g3, dim3(512), 0, s, p);
+    }
     return hipGetLastError();
 }
 
@@ -356,14 +535,14 @@ void w16_operands(float *t)
 
 hipError_t launch_sym_mf(int prec, int pass, const SymPass &p, hipStream_t s)
 {
-    if (!(p.N1 == 4096 && p.N2 == 4096 && p.log2L >= 12 && p.log2N == 24 && p.src && p.dst && p.tw && p.tw_hi &&
-          p.tw_lo && p.tw_sj && p.w16) ||
-        pass < 1 || pass > 3)
+    const int ll = sym_log2_child(p);  // L = 256 or 512 for these forms
+    if (!(ll == 8 || ll == 9) || !(p.src && p.dst && p.tw && p.tw_hi && p.tw_lo && p.tw_sj && p.w16) || pass < 1 ||
+        pass > 3)
         return hipErrorInvalidValue;
     switch (prec) {
-    case kPrecFP16x3: return launch_pass<kPrecFP16x3>(pass, p, s);
-    case kPrecBF16x3: return launch_pass<kPrecBF16x3>(pass, p, s);
-    case kPrecBF16x6: return launch_pass<kPrecBF16x6>(pass, p, s);
+    case kPrecFP16x3: return launch_pass<kPrecFP16x3>(pass, ll, p, s);
+    case kPrecBF16x3: return launch_pass<kPrecBF16x3>(pass, ll, p, s);
+    case kPrecBF16x6: return launch_pass<kPrecBF16x6>(pass, ll, p, s);
     default: return hipErrorInvalidValue;
     }
 }

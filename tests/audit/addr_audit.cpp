@@ -279,6 +279,54 @@ void audit_mf_exchange(const char *name, int items, Store store, Load load, bool
     std::printf("ok   MFMA exchange buffer %s (%d items)\n", name, items);
 }
 
+// The L = 512 exchange buffers (8 waves; stage-B groups 2 g + jp): the same
+// checks as audit_mf_exchange.  across: pass 1 (stage-B loads run across
+// rows n), else pass 3 (one row g per group).
+template <class Store, class Load>
+void audit_mf_exchange_512(const char *name, Store store, Load load, bool across)
+{
+    const int items = addr::kMfLItems;
+    std::vector<int> at(items, -1);
+    for (int w = 0; w < 8; ++w)
+        for (int G = 0; G < 4; ++G)
+            for (int i = 0; i < 4; ++i) {
+                const int j = 4 * w + G;
+                int slots[64];
+                for (int l = 0; l < 64; ++l) {
+                    const int n = l & 15, kb = l >> 4;
+                    const int a = store(kb, i, j, n);
+                    CHECK(a >= 0 && a < items, "%s: store %d outside %d items", name, a, items);
+                    CHECK(at[a] < 0, "%s: slot %d stored twice", name, a);
+                    at[a] = (4 * kb + i) * 512 + 16 * j + n;
+                    slots[l] = a & 31;
+                }
+                for (int h = 0; h < 2; ++h) {
+                    uint32_t seen = 0;
+                    for (int l = 32 * h; l < 32 * h + 32; ++l) seen |= 1u << slots[l];
+                    CHECK(seen == 0xffffffffu, "%s: store half-wave shares a slot", name);
+                }
+            }
+    for (int w = 0; w < 8; ++w)
+        for (int G = 0; G < 4; ++G)
+            for (int i = 0; i < 8; ++i) {
+                const int g = 2 * w + (G >> 1), jp = G & 1;
+                uint64_t banks = 0;
+                for (int l = 0; l < 64; ++l) {
+                    const int n = l & 15, kb = l >> 4, half = kb & 1, comp = kb >> 1;
+                    const int col = 16 * (jp + 2 * (8 * half + i)) + (across ? g : n);
+                    const int row = across ? n : g;
+                    const int a = across ? load(n, half, i, jp, g) : load(g, half, i, jp, n);
+                    CHECK(a >= 0 && a < items && at[a] == row * 512 + col, "%s: load reads slot %d", name, a);
+                    banks |= uint64_t(1) << ((2 * a + comp) & 63);
+                }
+                CHECK(banks == ~uint64_t(0), "%s: load wave shares a bank", name);
+            }
+    int stored = 0;
+    for (int v : at) stored += v >= 0;
+    CHECK(stored == 16 * 512, "%s: not every logical item stored", name);
+    std::printf("ok   MFMA exchange buffer %s (%d items)\n", name, items);
+}
+
 int main(int argc, char **argv)
 {
     const bool full = argc > 1;  // also the 2^28 shapes (about 2 x 2^28 items per pass)
@@ -288,6 +336,8 @@ int main(int argc, char **argv)
     audit_mf_exchange("pass 1", addr::kMf1Items, addr::mf1_store, addr::mf1_load, true, addr::kMf1Spare);
     audit_mf_exchange("pass 2", 16 * 256, addr::mf2_store, addr::mf2_load, false, -1);
     audit_mf_exchange("pass 3", addr::kMf1Items, addr::mf3_store, addr::mf3_load, false, addr::kMf3Spare);
+    audit_mf_exchange_512("pass 1, L = 512", addr::mf1L_store, addr::mf1L_load, true);
+    audit_mf_exchange_512("pass 3, L = 512", addr::mf3L_store, addr::mf3L_load, false);
     const uint32_t n1s[] = {4096, 8192, 16384};
     const uint32_t n2s[] = {16, 64, 256, 2048, 4096};
     for (uint32_t N1 : n1s)

@@ -4,9 +4,13 @@ radix-2 step across lanes 16 apart) on the GPU, FP32, against the FP64
 oracle: every output of the 2^26 transform, each pass on its own against
 expected values built from the oracle's DFTs (sampled columns or blocks of
 seeded input), the stage hooks composing to paco_execute bit for bit, in
-place, the inverse, and independence of b and p.  N1 = N2 = 16384 (L = 1024,
-radix 4 across lanes) has every 2^28 output compared with the oracle in
-test_gpu_full_size.py."""
+place, the inverse, and independence of b and p.  The split MFMA forms at
+the same size (their 32-point stage as two MFMA groups of one wave joined by
+a radix-2 step in registers): each pass against the FP32 pass, every output
+against the oracle, stage hooks, in place, inverse, exact power-of-two scale
+invariance and spikes in every lane (FP16x3).  N1 = N2 = 16384 (L = 1024,
+radix 4 across lanes; FP32 only) has every 2^28 output compared with the
+oracle in test_gpu_full_size.py."""
 
 import numpy as np
 import pytest
@@ -53,6 +57,13 @@ def _w(n, e):
     return np.exp(-2j * np.pi * (np.asarray(e, dtype=np.int64) % n) / n)
 
 
+# the split MFMA forms and their bounds (see test_gpu_mfma.py)
+MFMA_FORMS = {
+    "fp16x3": (paco.PACO_C64_MFMA_FP16X3, 1e-6),
+    "bf16x3": (paco.PACO_C64_MFMA_BF16X3, 3e-5),
+    "bf16x6": (paco.PACO_C64_MFMA_BF16X6, 1e-6),
+}
+
 _X = {}
 
 
@@ -70,8 +81,11 @@ def test_plan_takes_the_symmetric_form():
     assert plan.description.startswith("sym[pass1: phase1 512-point"), plan.description
     sq = paco.Plan(1 << 14, 1 << 14, 256, 4)
     assert sq.has_split == 2 and sq.launches == 3 and "1024-point" in sq.description, sq.description
-    # the split MFMA forms keep the symmetric form at 4096 x 4096 only
-    assert paco.Plan(N1, N2, 64, 2, paco.PACO_C64_MFMA_FP16X3).has_split != 2
+    # the split MFMA forms run it at 8192 x 8192 too, not at 16384 x 16384
+    for dt, _ in MFMA_FORMS.values():
+        mp = paco.Plan(N1, N2, 64, 2, dt)
+        assert mp.has_split == 2 and mp.launches == 3, mp.description
+        assert paco.Plan(1 << 14, 1 << 14, 256, 4, dt).has_split != 2
     assert paco.Plan(N1, N2, 64, 2, flags=paco.PACO_PLAN_NO_SYM).has_split != 2
 
 
@@ -176,3 +190,70 @@ def test_stage_hooks_compose_to_execute_in_place_and_inverse():
     err = oracle.rel_l2(back, x)
     print(f"symmetric split 8192 x 8192 inverse: rel-L2 vs x {err:.3e}", flush=True)
     assert err <= TOL
+
+
+@pytest.mark.parametrize("form", sorted(MFMA_FORMS))
+def test_mfma_passes_against_the_fp32_passes(form):
+    dt, tol = MFMA_FORMS[form]
+    fp32 = paco.Plan(N1, N2, 64, 2)
+    mf = paco.Plan(N1, N2, 64, 2, dt)
+    for stage, seed in ((1, 75), (2, 76), (3, 77)):
+        src = _dev(inputs.loguniform(N, seed=seed))
+        a = _stage(fp32, stage, src).cpu().numpy()
+        b = _stage(mf, stage, src).cpu().numpy()
+        err = oracle.rel_l2(b, a)
+        print(f"{form} 8192 x 8192 pass {stage}: rel-L2 against the FP32 pass {err:.3e}", flush=True)
+        assert err <= tol, (stage, err)
+
+
+@pytest.mark.parametrize("form", sorted(MFMA_FORMS))
+def test_mfma_full_output_stage_hooks_and_inverse(form):
+    dt, tol = MFMA_FORMS[form]
+    x = inputs.loguniform(N, seed=78)
+    xd = _dev(x)
+    plan = paco.Plan(N1, N2, 64, 2, dt)
+    y = _execute(plan, xd).cpu().numpy()
+    ref = oracle.fft_radix2(x, threads=oracle.cpu_threads())
+    err = oracle.rel_l2(y, ref)
+    print(f"{form} 8192 x 8192: rel-L2 vs FP64 oracle over all 2^26 outputs {err:.3e}", flush=True)
+    assert err <= tol
+    u = _stage(plan, 1, xd)
+    w = _stage(plan, 2, u)
+    del u
+    _stage(plan, 3, w, dst=w)
+    assert np.array_equal(w.cpu().numpy().view(np.uint64), y.view(np.uint64))
+    del w
+    buf = xd.clone()
+    _execute(plan, buf, out=buf)
+    assert np.array_equal(buf.cpu().numpy().view(np.uint64), y.view(np.uint64))
+    del buf
+    back = _execute(plan, _dev(ref), fn=plan.execute_inverse).cpu().numpy()
+    assert oracle.rel_l2(back, x) <= 2 * tol
+
+
+@pytest.mark.parametrize("form", sorted(MFMA_FORMS))
+def test_mfma_power_of_two_input_scale_passes_through_exactly(form):
+    plan = paco.Plan(N1, N2, 64, 2, MFMA_FORMS[form][0])
+    x = inputs.loguniform(N, seed=79)
+    y = _execute(plan, _dev(x)).cpu().numpy()
+    for s in (60, -80):
+        ys = _execute(plan, _dev(np.ldexp(x.view(np.float32), s).view(np.complex64))).cpu().numpy()
+        assert np.array_equal(ys.view(np.uint64), np.ldexp(y.view(np.float32), s).view(np.uint64)), (form, s)
+
+
+def test_fp16x3_scale_sees_every_lane():
+    # 10^6 spikes over 1e-3 noise: a scale that missed a spike's lane would
+    # overflow FP16 (see test_gpu_sym.py)
+    dt, tol = MFMA_FORMS["fp16x3"]
+    fp32 = paco.Plan(N1, N2, 64, 2)
+    mf = paco.Plan(N1, N2, 64, 2, dt)
+    rng = np.random.default_rng(80)
+    x = (1e-3 * inputs.normal(N, seed=80)).astype(np.complex64)
+    pos = rng.choice(N, size=16384, replace=False)
+    x[pos] = (1e6 * np.exp(2j * np.pi * rng.random(16384))).astype(np.complex64)
+    src = _dev(x)
+    for stage in (1, 2, 3):
+        a = _stage(fp32, stage, src).cpu().numpy()
+        b = _stage(mf, stage, src).cpu().numpy()
+        assert np.all(np.isfinite(b.view(np.float32))), stage
+        assert oracle.rel_l2(b, a) <= tol, stage
