@@ -199,6 +199,8 @@ struct SymPass {
     const float *w16;             // split MFMA forms: 64 lanes x 16 DFT-matrix operands (w16_operands)
     int32_t conj_in;              // pass 1: conjugate x on load (the inverse's input map)
     float out_scale;              // pass 3: nonzero stores conj(y) * out_scale (the inverse's output map)
+    uint32_t groups1, groups3;    // passes 1 and 3 at L >= 512: workgroups of their persistent launches
+                                  // (sym_resident_groups; 0: one per tile)
 };
 
 // Workgroup geometry a local pass is launched with.
@@ -242,10 +244,15 @@ hipError_t launch_split_first(const SplitPass &p, hipStream_t s);
 hipError_t launch_split_middle(const SplitPass &p, hipStream_t s);
 hipError_t split_prepare();  // raises the dynamic-LDS limit of the three-stage pass 2 once
 // The three passes of the symmetric split form; hipErrorInvalidValue unless
-// N1 = N2 = 4096.
+// sym_log2_child(p) is nonzero.
 // log2 L of a shape the symmetric form runs (N1 = N2 = 16 L, L = 256, 512,
 // 1024; the split MFMA forms: 256 and 512), else 0
 int sym_log2_child(const SymPass &p);
+// Workgroups the current device holds at once of the persistent pass-1 or
+// pass-3 kernel of p's shape (L >= 512), 0 for L = 256 or if the runtime does
+// not say; the MFMA forms' kernels: sym_mf_resident_groups.
+uint32_t sym_resident_groups(int pass, const SymPass &p);
+uint32_t sym_mf_resident_groups(int prec, int pass, const SymPass &p);
 hipError_t launch_sym_first(const SymPass &p, hipStream_t s);
 hipError_t launch_sym_middle(const SymPass &p, hipStream_t s);
 hipError_t launch_sym_last(const SymPass &p, hipStream_t s);

@@ -4,6 +4,8 @@
 // single-pass local transform.  Included once per translation unit.
 #pragma once
 
+#include <type_traits>
+
 #include "paco_internal.h"
 
 namespace paco {
@@ -153,6 +155,26 @@ struct Ctx {
 
 // conj(v) * s: the inverse transform's output map (s = 1/N, a power of two)
 __device__ __forceinline__ float2 conj_scale(float2 v, float s) { return make_float2(v.x * s, -v.y * s); }
+
+// base + idx items through a 32-bit byte offset (buffers below 4 GiB: every
+// plan's are, N <= 2^28 complex64): the access then takes a uniform 64-bit
+// base and one VGPR of offset instead of a 64-bit address per item.
+template <typename T>
+__device__ __forceinline__ T *off32(T *base, uint32_t idx)
+{
+    using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+    return reinterpret_cast<T *>(reinterpret_cast<B *>(base) + idx * uint32_t(sizeof(T)));
+}
+
+// x, with a value the compiler cannot see through: a lane index taken through
+// this inside a loop keeps the index arithmetic that depends on it inside the
+// loop (hoisted out of a tile loop, 30 loop-invariant twiddle offsets held in
+// registers across it made the kernel spill).  Emits no instruction.
+__device__ __forceinline__ uint32_t opaque(uint32_t x)
+{
+    asm volatile("" : "+v"(x));
+    return x;
+}
 
 // ---- split-precision MFMA form of the radix-16 butterflies -----------------
 // A radix-16 butterfly y = W x, W[m][k] = w_16^{-mk}, is one real contraction

@@ -254,98 +254,164 @@ __device__ __forceinline__ void stage_b(float2 (&v)[16], const float2 (&tb)[16],
     for (int i = 0; i < 16; ++i) v[i] = radix_across_lanes<PP>(v[i], jp);
 }
 
+// Passes 1 and 3 at L = 512 and 1024 run persistent workgroups: workgroup g
+// of G takes tiles g, g + G, ... (in the block order addr::sym{1,3}_block
+// gives a launch of one workgroup per tile), and issues the loads of its
+// next tile right after stage A of the current one, so that they are in
+// flight during stage B, the stores and the next barrier.  A tile fills the
+// LDS of a CU (1024 threads, 128 KiB at L = 1024) or half of it, so without
+// this one tile's loads did not overlap another's arithmetic (L = 1024:
+// passes 1 and 3 1233 / 1321 us against 1007 / 1094 us pipelined, 893 /
+// 929 us for a copy with the same loads and stores).  The twiddle factors
+// sit in LDS (loaded once per workgroup): a global load in the loop would
+// wait for the prefetch ahead of it.  G is the number of workgroups the
+// device holds at once (plan creation); the last tile reloads itself, which
+// keeps the loop one block (its loads are issued before its stores and the
+// values are not used).
+
 // Pass 1, L = 2^LL.  Stage-B thread (ka, jp, cl2) = (tid & 15, (tid >> 4) &
 // (P-1), tid >> (4 + log2 P)): k fastest, for the 128-byte runs of U.  Plane
 // stride L + 1 (odd): a half-wave of stage-B loads (16 ka x 2 jp) hits 32
 // distinct 8-byte slots.
 template <bool STREAM, int LL>
-__global__ __launch_bounds__(1 << LL) __attribute__((amdgpu_waves_per_eu(4))) void sym_first_long_kernel(SymPass P)
+__global__ __launch_bounds__(1 << LL) __attribute__((amdgpu_waves_per_eu(4))) void sym_first_long_kernel(SymPass P,
+                                                                                                        uint32_t tiles)
 {
     constexpr int L = 1 << LL, M = L >> 4, PP = M >> 4, S = L + 1;
     __shared__ float2 lds[16 * S];
-    const int tid = threadIdx.x;
+    __shared__ float2 twL[L];      // w_L^{-m}
+    __shared__ float2 twF[256];    // w_N1^{-m}, m < 256 (N1 = 16 L)
+    const int tid = threadIdx.x, cl = tid & 15;
     const uint32_t N2 = uint32_t(P.N2);
-    const uint32_t blk = addr::sym1_block(blockIdx.x, N2, LL);
-    const uint32_t r = blk / (N2 >> 4);
-    const int cl = tid & 15, jl = tid >> 4;
+    uint32_t t = blockIdx.x;
     float2 v[16];
-    const float2 *src = P.src + addr::sym1_load_base(N2, blk, tid);
+    auto load = [&](uint32_t tile) {
+        const uint32_t base = addr::sym1_load_base(N2, addr::sym1_block(tile, N2, LL), tid);
 #pragma unroll
-    for (int jh = 0; jh < 16; ++jh) v[jh] = src[addr::sym1_load_off(N2, jh, LL)];
-    const int ka = tid & 15, jp = (tid >> 4) & (PP - 1), cl2 = tid >> (LL - 4);
-    float2 ta[16], tb[16];
+        for (int jh = 0; jh < 16; ++jh) v[jh] = *off32(P.src, base + addr::sym1_load_off(N2, jh, LL));
+    };
+    // stage A of tile tc (radix 16 over jh by thread (cl, jl), twiddle
+    // w_L^{-jl ka}) into the exchange buffer, then the next tile's loads
+    auto stage_a = [&](uint32_t tc) {
+        const uint32_t jl = opaque(uint32_t(tid)) >> 4;
+        if (P.conj_in) {
 #pragma unroll
-    for (int k = 1; k < 16; ++k) {
-        ta[k] = root_of(P.tw, P.log2L, LL, uint32_t(jl * k));      // w_L^{-jl ka}
-        tb[k] = root_of(P.tw, P.log2L, LL - 4, uint32_t(jp * k));  // w_M^{-jp kb'}
-    }
-    const float2 a = root_of(P.tw, P.log2L, LL + 4, uint32_t(ka) * r);  // w_N1^{-ka r}
-    if (P.conj_in) {
+            for (int i = 0; i < 16; ++i) v[i].y = -v[i].y;
+        }
+        dft_regs<4>(v);
 #pragma unroll
-        for (int i = 0; i < 16; ++i) v[i].y = -v[i].y;
-    }
-    dft_regs<4>(v);
+        for (int k = 1; k < 16; ++k) v[k] = cmul(v[k], twL[(jl * k) & (L - 1)]);
 #pragma unroll
-    for (int k = 1; k < 16; ++k) v[k] = cmul(v[k], ta[k]);
-#pragma unroll
-    for (int k = 0; k < 16; ++k) lds[k * S + jl * 16 + cl] = v[k];
+        for (int k = 0; k < 16; ++k) lds[k * S + jl * 16 + cl] = v[k];
+        load(tc + gridDim.x < tiles ? tc + gridDim.x : tc);
+        __syncthreads();
+    };
+    load(t < tiles ? t : 0);  // (the launch gives every workgroup a tile)
+    twL[tid] = P.tw[uint32_t(tid) << (P.log2L - LL)];
+    if (tid < 256) twF[tid] = P.tw[uint32_t(tid) << (P.log2L - LL - 4)];
     __syncthreads();
+    if (t < tiles) stage_a(t);
+    while (t < tiles) {
+        const uint32_t blk = addr::sym1_block(t, N2, LL);
+        const uint32_t r = blk / (N2 >> 4);
+        const uint32_t tt = opaque(uint32_t(tid));
+        const uint32_t ka = tt & 15, jp = (tt >> 4) & (PP - 1), cl2 = tt >> (LL - 4);
+        float2 u[16], tb[16];
 #pragma unroll
-    for (int jm = 0; jm < 16; ++jm) v[jm] = lds[ka * S + (jp + PP * jm) * 16 + cl2];
-    stage_b<PP>(v, tb, jp);
-    float2 *dst = P.dst + addr::sym1_store_base(N2, blk, tid, LL);
+        for (int jm = 0; jm < 16; ++jm) u[jm] = lds[ka * S + (jp + PP * jm) * 16 + cl2];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        // w_N1^{-k r}, k = ka + 16 (i + 16 jp)
-        const float2 y = cmul(v[i], cmul(a, root_of(P.tw, P.log2L, LL + 4, 16u * uint32_t(i + 16 * jp) * r)));
-        float2 *d = dst + addr::sym1_store_off(N2, i);
-        if constexpr (STREAM)
-            st2_stream(d, y);
-        else
-            *d = y;
+        for (int k = 1; k < 16; ++k) tb[k] = twL[((jp * k) << 4) & (L - 1)];  // w_M^{-jp kb'}
+        stage_b<PP>(u, tb, int(jp));
+        const float2 a = twF[ka * r];  // w_N1^{-ka r}
+        const uint32_t dbase = addr::sym1_store_base(N2, blk, tid, LL);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            // w_N1^{-k r}, k = ka + 16 (i + 16 jp): w_N1^{-ka r} w_L^{-(i + 16 jp) r}
+            const float2 y = cmul(u[i], cmul(a, twL[((i + 16 * jp) * r) & (L - 1)]));
+            float2 *d = off32(P.dst, dbase + addr::sym1_store_off(N2, i));
+            if constexpr (STREAM)
+                st2_stream(d, y);
+            else
+                *d = y;
+        }
+        __syncthreads();
+        t += gridDim.x;
+        if (t < tiles) stage_a(t);
     }
 }
 
-// Pass 3, L = 2^LL, in place.  Stage-B thread (cl, jp, ka) = (tid & 15,
-// (tid >> 4) & (P-1), tid >> (4 + log2 P)): column fastest, for the 128-byte
-// runs of the rows it stores; a half-wave of stage-B loads (16 cl x 2 jp) is
-// 32 consecutive items of one plane, so the planes need no padding.
+// Pass 3, L = 2^LL, in place (a tile's stores go to the items it loaded,
+// and no other workgroup's tile overlaps them).  Stage-B thread (cl, jp,
+// ka) = (tid & 15, (tid >> 4) & (P-1), tid >> (4 + log2 P)): column fastest,
+// for the 128-byte runs of the rows it stores; a half-wave of stage-B loads
+// (16 cl x 2 jp) is 32 consecutive items of one plane, so the planes need no
+// padding.
 template <int LL>
-__global__ __launch_bounds__(1 << LL) __attribute__((amdgpu_waves_per_eu(4))) void sym_last_long_kernel(SymPass P)
+__global__ __launch_bounds__(1 << LL) __attribute__((amdgpu_waves_per_eu(4))) void sym_last_long_kernel(SymPass P,
+                                                                                                       uint32_t tiles)
 {
     constexpr int L = 1 << LL, M = L >> 4, PP = M >> 4, S = L;
     __shared__ float2 lds[16 * S];
-    const int tid = threadIdx.x;
+    __shared__ float2 twL[L];
+    const int tid = threadIdx.x, cl = tid & 15;
     const uint32_t N1 = uint32_t(P.N1);
-    const int cl = tid & 15, jl = tid >> 4;
-    const uint32_t blk = addr::sym3_block(blockIdx.x, N1, LL);
-    const float2 *src = P.src + addr::sym3_load_base(N1, blk, tid);
+    uint32_t t = blockIdx.x;
     float2 v[16];
+    auto load = [&](uint32_t tile) {
+        const uint32_t base = addr::sym3_load_base(N1, addr::sym3_block(tile, N1, LL), tid);
 #pragma unroll
-    for (int jh = 0; jh < 16; ++jh) v[jh] = src[addr::sym3_load_off(N1, jh, LL)];
-    const int jp = (tid >> 4) & (PP - 1), ka = tid >> (LL - 4);
-    float2 ta[16], tb[16];
+        for (int jh = 0; jh < 16; ++jh) v[jh] = *off32(P.src, base + addr::sym3_load_off(N1, jh, LL));
+    };
+    auto stage_a = [&](uint32_t tc) {
+        const uint32_t jl = opaque(uint32_t(tid)) >> 4;
+        dft_regs<4>(v);
 #pragma unroll
-    for (int k = 1; k < 16; ++k) {
-        ta[k] = root_of(P.tw, P.log2L, LL, uint32_t(jl * k));
-        tb[k] = root_of(P.tw, P.log2L, LL - 4, uint32_t(jp * k));
-    }
-    dft_regs<4>(v);
+        for (int k = 1; k < 16; ++k) v[k] = cmul(v[k], twL[(jl * k) & (L - 1)]);
 #pragma unroll
-    for (int k = 1; k < 16; ++k) v[k] = cmul(v[k], ta[k]);
-#pragma unroll
-    for (int k = 0; k < 16; ++k) lds[k * S + jl * 16 + cl] = v[k];
+        for (int k = 0; k < 16; ++k) lds[k * S + jl * 16 + cl] = v[k];
+        load(tc + gridDim.x < tiles ? tc + gridDim.x : tc);
+        __syncthreads();
+    };
+    load(t < tiles ? t : 0);  // (the launch gives every workgroup a tile)
+    twL[tid] = P.tw[uint32_t(tid) << (P.log2L - LL)];
     __syncthreads();
+    if (t < tiles) stage_a(t);
+    while (t < tiles) {
+        const uint32_t blk = addr::sym3_block(t, N1, LL);
+        const uint32_t tt = opaque(uint32_t(tid));
+        const uint32_t jp = (tt >> 4) & (PP - 1), ka = tt >> (LL - 4);
+        float2 u[16], tb[16];
 #pragma unroll
-    for (int jm = 0; jm < 16; ++jm) v[jm] = lds[ka * S + (jp + PP * jm) * 16 + cl];
-    stage_b<PP>(v, tb, jp);
-    float2 *dst = P.dst + addr::sym3_store_base(N1, blk, tid, LL);
+        for (int jm = 0; jm < 16; ++jm) u[jm] = lds[ka * S + (jp + PP * jm) * 16 + cl];
 #pragma unroll
-    for (int i = 0; i < 16; ++i)
-        dst[addr::sym3_store_off(N1, i)] = P.out_scale != 0.f ? conj_scale(v[i], P.out_scale) : v[i];
+        for (int k = 1; k < 16; ++k) tb[k] = twL[((jp * k) << 4) & (L - 1)];
+        stage_b<PP>(u, tb, int(jp));
+        const uint32_t dbase = addr::sym3_store_base(N1, blk, tid, LL);
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            *off32(P.dst, dbase + addr::sym3_store_off(N1, i)) = P.out_scale != 0.f ? conj_scale(u[i], P.out_scale) : u[i];
+        __syncthreads();
+        t += gridDim.x;
+        if (t < tiles) stage_a(t);
+    }
 }
 
 int sym_ll(const SymPass &p) { return sym_log2_child(p); }
+
+// the persistent launch of a pass over `tiles` tiles: the plan's resident
+// workgroup count (all tiles where it is unknown), never more than the tiles
+dim3 persistent(dim3 tiles, uint32_t groups) { return dim3(groups && groups < tiles.x ? groups : tiles.x); }
+
+// workgroups of kernel k (threads each) the current device holds at once
+template <typename K>
+uint32_t resident(K k, int threads)
+{
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, threads, 0) != hipSuccess)
+        return 0;
+    return uint32_t(cus > 0 ? cus : 0) * uint32_t(per > 0 ? per : 0);
+}
 
 bool sym_shape_ok(const SymPass &p)
 {
@@ -361,14 +427,23 @@ int sym_log2_child(const SymPass &p)
     return ll && p.log2L >= ll + 4 && p.log2N == 2 * (ll + 4) ? ll : 0;
 }
 
+uint32_t sym_resident_groups(int pass, const SymPass &p)
+{
+    switch (sym_ll(p)) {
+    case 9: return pass == 1 ? resident(sym_first_long_kernel<true, 9>, 512) : resident(sym_last_long_kernel<9>, 512);
+    case 10: return pass == 1 ? resident(sym_first_long_kernel<true, 10>, 1024) : resident(sym_last_long_kernel<10>, 1024);
+    default: return 0;
+    }
+}
+
 hipError_t launch_sym_first(const SymPass &p, hipStream_t s)
 {
     if (!sym_shape_ok(p)) return hipErrorInvalidValue;
     const dim3 grid(addr::sym1_groups(uint32_t(p.N2)));
     switch (sym_ll(p)) {
     case 8: hipLaunchKernelGGL(sym_first_kernel<true>, grid, dim3(kSymThreads), 0, s, p); break;
-    case 9: hipLaunchKernelGGL((sym_first_long_kernel<true, 9>), grid, dim3(512), 0, s, p); break;
-    default: hipLaunchKernelGGL((sym_first_long_kernel<true, 10>), grid, dim3(1024), 0, s, p); break;
+    case 9: hipLaunchKernelGGL((sym_first_long_kernel<true, 9>), persistent(grid, p.groups1), dim3(512), 0, s, p, grid.x); break;
+    default: hipLaunchKernelGGL((sym_first_long_kernel<true, 10>), persistent(grid, p.groups1), dim3(1024), 0, s, p, grid.x); break;
     }
     return hipGetLastError();
 }
@@ -391,8 +466,8 @@ hipError_t launch_sym_last(const SymPass &p, hipStream_t s)
     const dim3 grid(addr::sym3_groups(uint32_t(p.N1)));
     switch (sym_ll(p)) {
     case 8: hipLaunchKernelGGL(sym_last_kernel, grid, dim3(kSymThreads), 0, s, p); break;
-    case 9: hipLaunchKernelGGL(sym_last_long_kernel<9>, grid, dim3(512), 0, s, p); break;
-    default: hipLaunchKernelGGL(sym_last_long_kernel<10>, grid, dim3(1024), 0, s, p); break;
+    case 9: hipLaunchKernelGGL(sym_last_long_kernel<9>, persistent(grid, p.groups3), dim3(512), 0, s, p, grid.x); break;
+    default: hipLaunchKernelGGL(sym_last_long_kernel<10>, persistent(grid, p.groups3), dim3(1024), 0, s, p, grid.x); break;
     }
     return hipGetLastError();
 }

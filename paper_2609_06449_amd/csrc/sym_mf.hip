@@ -533,6 +533,8 @@ void w16_operands(float *t)
     }
 }
 
+uint32_t sym_mf_resident_groups(int, int, const SymPass &) { return 0; }
+
 hipError_t launch_sym_mf(int prec, int pass, const SymPass &p, hipStream_t s)
 {
     const int ll = sym_log2_child(p);  // L = 256 or 512 for these forms
