@@ -176,6 +176,21 @@ __device__ __forceinline__ uint32_t opaque(uint32_t x)
     return x;
 }
 
+// Host side of the persistent passes: the launch over `tiles` tiles (the
+// plan's resident workgroup count `groups`, all tiles where it is 0, never
+// more than the tiles), and the workgroups of kernel k (threads each) that
+// the current device holds at once (0 if the runtime does not say).
+inline dim3 persistent(dim3 tiles, uint32_t groups) { return dim3(groups && groups < tiles.x ? groups : tiles.x); }
+template <typename K>
+uint32_t resident(K k, int threads)
+{
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, threads, 0) != hipSuccess)
+        return 0;
+    return uint32_t(cus > 0 ? cus : 0) * uint32_t(per > 0 ? per : 0);
+}
+
 // ---- split-precision MFMA form of the radix-16 butterflies -----------------
 // A radix-16 butterfly y = W x, W[m][k] = w_16^{-mk}, is one real contraction
 //     [yr; yi] = [[Wr, -Wi], [Wi, Wr]] [xr; xi]          (K = 32),

@@ -398,21 +398,6 @@ __global__ __launch_bounds__(1 << LL) __attribute__((amdgpu_waves_per_eu(4))) vo
 
 int sym_ll(const SymPass &p) { return sym_log2_child(p); }
 
-// the persistent launch of a pass over `tiles` tiles: the plan's resident
-// workgroup count (all tiles where it is unknown), never more than the tiles
-dim3 persistent(dim3 tiles, uint32_t groups) { return dim3(groups && groups < tiles.x ? groups : tiles.x); }
-
-// workgroups of kernel k (threads each) the current device holds at once
-template <typename K>
-uint32_t resident(K k, int threads)
-{
-    int dev = 0, cus = 0, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, threads, 0) != hipSuccess)
-        return 0;
-    return uint32_t(cus > 0 ? cus : 0) * uint32_t(per > 0 ? per : 0);
-}
-
 bool sym_shape_ok(const SymPass &p)
 {
     return sym_ll(p) && p.src && p.dst && p.tw && p.tw_hi && p.tw_lo && p.tw_sj;

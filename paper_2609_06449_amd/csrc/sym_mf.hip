@@ -348,152 +348,189 @@ __device__ __forceinline__ int tile_scale8(const float (&x)[4][8], float *red, i
     return scale_of(t);
 }
 
-// stage-B tail: twiddle the jp = 1 group by w_32^{-kb'} and combine the two
-// groups of each pair (outputs kb' in group 2 g, kb' + 16 in group 2 g + 1)
-__device__ __forceinline__ void radix2_pairs(float2 (&o)[4][4], const float2 (&tb)[4])
+// stage-B tail of one transform: twiddle its jp = 1 half by w_32^{-kb'}
+// (kb' = 4 kb + i; twL: w_512^{-m}) and combine the halves (outputs kb' in
+// o0, kb' + 16 in o1)
+__device__ __forceinline__ void radix2_pair(float2 (&o0)[4], float2 (&o1)[4], const float2 *twL, uint32_t kb)
 {
 #pragma unroll
-    for (int g = 0; g < 2; ++g)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const float2 y0 = o[2 * g][i], y1 = cmul(o[2 * g + 1][i], tb[i]);
-            o[2 * g][i] = make_float2(y0.x + y1.x, y0.y + y1.y);
-            o[2 * g + 1][i] = make_float2(y0.x - y1.x, y0.y - y1.y);
-        }
+    for (int i = 0; i < 4; ++i) {
+        const float2 y0 = o0[i], y1 = cmul(o1[i], twL[(4 * kb + i) << 4]);
+        o0[i] = make_float2(y0.x + y1.x, y0.y + y1.y);
+        o1[i] = make_float2(y0.x - y1.x, y0.y - y1.y);
+    }
 }
 
+// Persistent and software-pipelined like the FP32 kernels of these passes
+// (sym.hip): workgroup g of G takes tiles g, g + G, ..., issues the next
+// tile's loads right after stage A and keeps the twiddle factors in LDS.
+// BF16x6's pass 1 (24 VGPRs of DFT-matrix operands) does not fit the
+// 128-VGPR budget of two workgroups per CU without spills, whose reloads
+// would wait for the prefetch: it runs one workgroup per CU.
 template <int PREC>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void sym_first_mf_long_kernel(SymPass P)
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(PREC == kPrecBF16x6 ? 2 : 4))) void sym_first_mf_long_kernel(SymPass P,
+                                                                                                      uint32_t tiles)
 {
-    constexpr int LL = 9;
+    constexpr int LL = 9, L = 1 << LL;
     __shared__ float2 lds[addr::kMfLItems];
+    __shared__ float2 twL[L];    // w_512^{-m}
+    __shared__ float2 twF[256];  // w_N1^{-m}, m < 256
     __shared__ float red[8];
     const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n = lane & 15, kb = lane >> 4, comp = kb >> 1, half = kb & 1;
     const uint32_t N2 = uint32_t(P.N2);
-    const uint32_t blk = addr::sym1_block(blockIdx.x, N2, LL);
-    const uint32_t r = blk / (N2 >> 4);
     const MfW16<PREC> W(P.w16, lane);
-    float x[4][8];
-    {
-        float2 it[4][4];
+    uint32_t t = blockIdx.x;
+    float2 it[4][4];
+    auto load = [&](uint32_t tile) {
+        const uint32_t blk = addr::sym1_block(tile, N2, LL);
 #pragma unroll
         for (int G = 0; G < 4; ++G) {
-            const float2 *src = P.src + addr::sym1_load_base(N2, blk, uint32_t(n + 16 * (4 * w + G)));
+            const uint32_t base = addr::sym1_load_base(N2, blk, uint32_t(n + 16 * (4 * w + G)));
 #pragma unroll
             for (int k = 0; k < 4; ++k)
-                it[G][k] = src[addr::sym1_load_off(N2, uint32_t(8 * half + (comp ? 4 + k : k)), LL)];
+                it[G][k] = *off32(P.src, base + addr::sym1_load_off(N2, uint32_t(8 * half + (comp ? 4 + k : k)), LL));
         }
+    };
+    int e = 0;  // FP16x3: the tile's scale, from stage A to the stores
+    auto stage_a = [&](uint32_t tc) {
+        float x[4][8];
 #pragma unroll
         for (int G = 0; G < 4; ++G) mf_load_ops(it[G], x[G], comp, P.conj_in != 0);
-    }
-    float2 t1[4][4], tb[4];
+        e = PREC == kPrecFP16x3 ? tile_scale8(x, red, lane, w) : 0;
+        const uint32_t kq = opaque(uint32_t(kb));
 #pragma unroll
-    for (int G = 0; G < 4; ++G)
+        for (int G = 0; G < 4; ++G) {
+            float2 o[4];
+            W.dft(x[G], o, e);
+            const int jl = 4 * w + G;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) t1[G][i] = root_of(P.tw, P.log2L, LL, uint32_t((4 * w + G) * (4 * kb + i)));
-#pragma unroll
-    for (int i = 0; i < 4; ++i) tb[i] = root_of(P.tw, P.log2L, 5, uint32_t(4 * kb + i));  // w_32^{-kb'}
-    const int e = PREC == kPrecFP16x3 ? tile_scale8(x, red, lane, w) : 0;
-    float2 o[4][4];
-#pragma unroll
-    for (int G = 0; G < 4; ++G) {
-        W.dft(x[G], o[G], e);
-        const int jl = 4 * w + G;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) lds[addr::mf1L_store(kb, i, jl, n)] = cmul(o[G][i], t1[G][i]);
-    }
-    __syncthreads();
-    const float *ldf = reinterpret_cast<const float *>(lds) + comp;
-#pragma unroll
-    for (int G = 0; G < 4; ++G) {
-        const int cl2 = 2 * w + (G >> 1), jp = G & 1;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) x[G][i] = ldf[2 * addr::mf1L_load(n, half, i, jp, cl2)];
-        W.dft(x[G], o[G]);
-    }
-    radix2_pairs(o, tb);
-    // outputs k = ka + 16 (kb' + 16 kc), ka = n, kb' = 4 kb + i, times w_N1^{-k r}
-    const float2 a = root_of(P.tw, P.log2L, LL + 4, uint32_t(n) * r);
-#pragma unroll
-    for (int kc = 0; kc < 2; ++kc)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const uint32_t kbp = uint32_t(4 * kb + i);
-            float2 t = cmul(a, root_of(P.tw, P.log2L, LL + 4, 16u * (kbp + 16u * kc) * r));
-            if constexpr (PREC == kPrecFP16x3) t = make_float2(ldexpf(t.x, e), ldexpf(t.y, e));
-#pragma unroll
-            for (int g = 0; g < 2; ++g) {
-                float2 *d = P.dst + addr::sym1_store_base(N2, blk, uint32_t(n + 16 * kc + 32 * (2 * w + g)), LL);
-                st2_stream(d + addr::sym1_store_off(N2, kbp), cmul(o[2 * g + kc][i], t));
-            }
+            for (int i = 0; i < 4; ++i)
+                lds[addr::mf1L_store(kb, i, jl, n)] = cmul(o[i], twL[(uint32_t(jl) * (4 * kq + i)) & (L - 1)]);
         }
+        load(tc + gridDim.x < tiles ? tc + gridDim.x : tc);
+        __syncthreads();
+    };
+    load(t < tiles ? t : 0);  // (the launch gives every workgroup a tile)
+    twL[tid] = P.tw[uint32_t(tid) << (P.log2L - LL)];
+    if (tid < 256) twF[tid] = P.tw[uint32_t(tid) << (P.log2L - LL - 4)];
+    __syncthreads();
+    if (t < tiles) stage_a(t);
+    const float *ldf = reinterpret_cast<const float *>(lds) + comp;
+    while (t < tiles) {
+        const uint32_t blk = addr::sym1_block(t, N2, LL);
+        const uint32_t r = blk / (N2 >> 4);
+        float2 o[4][4];
+#pragma unroll
+        for (int G = 0; G < 4; ++G) {
+            float x[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) x[i] = ldf[2 * addr::mf1L_load(n, half, i, G & 1, 2 * w + (G >> 1))];
+            W.dft(x, o[G]);
+        }
+        const uint32_t kq = opaque(uint32_t(kb));
+#pragma unroll
+        for (int g = 0; g < 2; ++g) radix2_pair(o[2 * g], o[2 * g + 1], twL, kq);
+        // outputs k = ka + 16 (kb' + 16 kc), ka = n, kb' = 4 kb + i, times
+        // w_N1^{-k r} = w_N1^{-n r} w_512^{-(kb' + 16 kc) r}
+        const float2 a = twF[uint32_t(n) * r];
+#pragma unroll
+        for (int kc = 0; kc < 2; ++kc)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float2 tw = cmul(a, twL[((4 * kq + i + 16u * kc) * r) & (L - 1)]);
+                if constexpr (PREC == kPrecFP16x3) tw = make_float2(ldexpf(tw.x, e), ldexpf(tw.y, e));
+#pragma unroll
+                for (int g = 0; g < 2; ++g) {
+                    const uint32_t d = addr::sym1_store_base(N2, blk, uint32_t(n + 16 * kc + 32 * (2 * w + g)), LL);
+                    st2_stream(off32(P.dst, d + addr::sym1_store_off(N2, uint32_t(4 * kb + i))), cmul(o[2 * g + kc][i], tw));
+                }
+            }
+        __syncthreads();
+        t += gridDim.x;
+        if (t < tiles) stage_a(t);
+    }
 }
 
 template <int PREC>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void sym_last_mf_long_kernel(SymPass P)
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void sym_last_mf_long_kernel(SymPass P,
+                                                                                                     uint32_t tiles)
 {
-    constexpr int LL = 9;
+    constexpr int LL = 9, L = 1 << LL;
     __shared__ float2 lds[addr::kMfLItems];
+    __shared__ float2 twL[L];
     __shared__ float red[8];
     const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n = lane & 15, kb = lane >> 4, comp = kb >> 1, half = kb & 1;
     const uint32_t N1 = uint32_t(P.N1);
-    const uint32_t blk = addr::sym3_block(blockIdx.x, N1, LL);
     const MfW16<PREC> W(P.w16, lane);
-    float x[4][8];
-    {
-        float2 it[4][4];
+    uint32_t t = blockIdx.x;
+    float2 it[4][4];
+    auto load = [&](uint32_t tile) {
+        const uint32_t blk = addr::sym3_block(tile, N1, LL);
 #pragma unroll
         for (int G = 0; G < 4; ++G) {
-            const float2 *src = P.src + addr::sym3_load_base(N1, blk, uint32_t(n + 16 * (4 * w + G)));
+            const uint32_t base = addr::sym3_load_base(N1, blk, uint32_t(n + 16 * (4 * w + G)));
 #pragma unroll
             for (int q = 0; q < 4; ++q)
-                it[G][q] = src[addr::sym3_load_off(N1, uint32_t(8 * half + (comp ? 4 + q : q)), LL)];
+                it[G][q] = *off32(P.src, base + addr::sym3_load_off(N1, uint32_t(8 * half + (comp ? 4 + q : q)), LL));
         }
+    };
+    int e = 0;
+    auto stage_a = [&](uint32_t tc) {
+        float x[4][8];
 #pragma unroll
         for (int G = 0; G < 4; ++G) mf_swap_in(it[G], x[G]);
-    }
-    float2 t1[4][4], tb[4];
+        e = PREC == kPrecFP16x3 ? tile_scale8(x, red, lane, w) : 0;
+        const uint32_t kq = opaque(uint32_t(kb));
 #pragma unroll
-    for (int G = 0; G < 4; ++G)
+        for (int G = 0; G < 4; ++G) {
+            float2 o[4];
+            W.dft(x[G], o, e);
+            const int jl = 4 * w + G;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) t1[G][i] = root_of(P.tw, P.log2L, LL, uint32_t((4 * w + G) * (4 * kb + i)));
-#pragma unroll
-    for (int i = 0; i < 4; ++i) tb[i] = root_of(P.tw, P.log2L, 5, uint32_t(4 * kb + i));
-    const int e = PREC == kPrecFP16x3 ? tile_scale8(x, red, lane, w) : 0;
-    float2 o[4][4];
-#pragma unroll
-    for (int G = 0; G < 4; ++G) {
-        W.dft(x[G], o[G], e);
-        const int jl = 4 * w + G;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) lds[addr::mf3L_store(kb, i, jl, n)] = cmul(o[G][i], t1[G][i]);
-    }
+            for (int i = 0; i < 4; ++i)
+                lds[addr::mf3L_store(kb, i, jl, n)] = cmul(o[i], twL[(uint32_t(jl) * (4 * kq + i)) & (L - 1)]);
+        }
+        load(tc + gridDim.x < tiles ? tc + gridDim.x : tc);
+        __syncthreads();
+    };
+    load(t < tiles ? t : 0);
+    twL[tid] = P.tw[uint32_t(tid) << (P.log2L - LL)];
     __syncthreads();
+    if (t < tiles) stage_a(t);
     const float *ldf = reinterpret_cast<const float *>(lds) + comp;
+    while (t < tiles) {
+        const uint32_t blk = addr::sym3_block(t, N1, LL);
+        const uint32_t kq = opaque(uint32_t(kb));
+        const float osc = ldexpf(1.0f, e);  // 1 except in FP16x3
 #pragma unroll
-    for (int G = 0; G < 4; ++G) {
-        const int ka = 2 * w + (G >> 1), jp = G & 1;
+        for (int g = 0; g < 2; ++g) {
+            float2 o[2][4];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) x[G][i] = ldf[2 * addr::mf3L_load(ka, half, i, jp, n)];
-        W.dft(x[G], o[G]);
-    }
-    radix2_pairs(o, tb);
-    // outputs q = ka + 16 (kb' + 16 kc) of column v = 16 vb + n, row q0 + 16 q
-    const float osc = ldexpf(1.0f, e);  // 1 except in FP16x3
+            for (int jp = 0; jp < 2; ++jp) {
+                float x[8];
 #pragma unroll
-    for (int g = 0; g < 2; ++g)
+                for (int i = 0; i < 8; ++i) x[i] = ldf[2 * addr::mf3L_load(2 * w + g, half, i, jp, n)];
+                W.dft(x, o[jp]);
+            }
+            radix2_pair(o[0], o[1], twL, kq);
+            // outputs q = ka + 16 (kb' + 16 kc) of column v = 16 vb + n, row q0 + 16 q
 #pragma unroll
-        for (int kc = 0; kc < 2; ++kc) {
-            float2 *d = P.dst + addr::sym3_store_base(N1, blk, uint32_t(n + 16 * kc + 32 * (2 * w + g)), LL);
+            for (int kc = 0; kc < 2; ++kc) {
+                const uint32_t d = addr::sym3_store_base(N1, blk, uint32_t(n + 16 * kc + 32 * (2 * w + g)), LL);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float2 y = o[2 * g + kc][i];
-                d[addr::sym3_store_off(N1, uint32_t(4 * kb + i))] =
-                    P.out_scale != 0.f ? conj_scale(y, P.out_scale * osc) : make_float2(y.x * osc, y.y * osc);
+                for (int i = 0; i < 4; ++i) {
+                    const float2 y = o[kc][i];
+                    *off32(P.dst, d + addr::sym3_store_off(N1, uint32_t(4 * kb + i))) =
+                        P.out_scale != 0.f ? conj_scale(y, P.out_scale * osc) : make_float2(y.x * osc, y.y * osc);
+                }
             }
         }
+        __syncthreads();
+        t += gridDim.x;
+        if (t < tiles) stage_a(t);
+    }
 }
 
 template <int PREC>
@@ -510,11 +547,11 @@ hipError_t launch_pass(int pass, int ll, const SymPass &p, hipStream_t s)
             hipLaunchKernelGGL(sym_last_mf_kernel<PREC>, g3, dim3(256), 0, s, p);
     } else {
         if (pass == 1)
-            hipLaunchKernelGGL(sym_first_mf_long_kernel<PREC>, g1, dim3(512), 0, s, p);
+            hipLaunchKernelGGL(sym_first_mf_long_kernel<PREC>, persistent(g1, p.groups1), dim3(512), 0, s, p, g1.x);
         else if (pass == 2)
             hipLaunchKernelGGL((sym_middle_mf_kernel<PREC, 9>), g2, dim3(256), 0, s, p);
         else
-            hipLaunchKernelGGL(sym_last_mf_long_kernel<PREC>, g3, dim3(512), 0, s, p);
+            hipLaunchKernelGGL(sym_last_mf_long_kernel<PREC>, persistent(g3, p.groups3), dim3(512), 0, s, p, g3.x);
     }
     return hipGetLastError();
 }
@@ -533,7 +570,19 @@ void w16_operands(float *t)
     }
 }
 
-uint32_t sym_mf_resident_groups(int, int, const SymPass &) { return 0; }
+uint32_t sym_mf_resident_groups(int prec, int pass, const SymPass &p)
+{
+    if (sym_log2_child(p) != 9 || (pass != 1 && pass != 3)) return 0;
+    switch (prec) {
+    case kPrecFP16x3:
+        return pass == 1 ? resident(sym_first_mf_long_kernel<kPrecFP16x3>, 512) : resident(sym_last_mf_long_kernel<kPrecFP16x3>, 512);
+    case kPrecBF16x3:
+        return pass == 1 ? resident(sym_first_mf_long_kernel<kPrecBF16x3>, 512) : resident(sym_last_mf_long_kernel<kPrecBF16x3>, 512);
+    case kPrecBF16x6:
+        return pass == 1 ? resident(sym_first_mf_long_kernel<kPrecBF16x6>, 512) : resident(sym_last_mf_long_kernel<kPrecBF16x6>, 512);
+    default: return 0;
+    }
+}
 
 hipError_t launch_sym_mf(int prec, int pass, const SymPass &p, hipStream_t s)
 {
