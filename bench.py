@@ -9,7 +9,10 @@ resident in HBM before the timed region.  Prints one JSON line: GFLOP/s =
 5 N log2 N / t, plus the dominant kernel's roofline (HIP events on the stream
 the kernels run on; phase_us times passes 1, 2 and 3 one launch each) and the
 CPU oracle baseline (one thread and all host cores, with the core count and
-CPU model).
+CPU model).  Cold figures: the same transform with the 256 MB MALL flushed
+before each one, by reading a 1 GiB buffer (cold_*), and by writing it
+(cold_dirty_*: the transform also pays for writing back 256 MB of the
+flush's dirty lines).
 
 Further fields of the same line (each leg can be skipped by a flag):
   two_pass   the two-HBM-pass form of the same transform (an ablation,
@@ -524,20 +527,35 @@ def main():
     ph = np.array([[hev.ms(ev[i][k], ev[i][k + 1]) for k in range(3)] for i in range(args.steps)])
     ph_us = ph.mean(axis=0) * 1e3
 
-    # ---- cold: a 1 GiB scratch write between transforms flushes the 256 MB MALL
+    # ---- cold: the 256 MB MALL flushed before each transform.  The flush
+    # reads a 1 GiB scratch buffer, which leaves the MALL holding clean lines
+    # of that buffer only: the transform then reads its input from HBM.
+    # Writing the buffer instead (the dirty variant, also reported) leaves
+    # 256 MB of dirty lines there, whose write-back the transform's first
+    # pass then pays for (measured: pass 1 61 -> 87 us at 2^24).
     flush = torch.empty(1 << 28, dtype=torch.float32, device=dev)
-    cold = []
-    for i in range(0 if args.skip_cold else min(args.steps, 50)):
-        flush.fill_(float(i))
-        a = torch.cuda.Event(enable_timing=True)
-        z = torch.cuda.Event(enable_timing=True)
-        a.record(stream)
-        step()
-        z.record(stream)
-        torch.cuda.synchronize()
-        cold.append(a.elapsed_time(z))
-    del flush
-    cold_ms = float(np.median(cold)) if cold else None
+    flush.fill_(1.0)
+    sink = torch.empty(1, dtype=torch.float32, device=dev)
+
+    def cold_run(dirty):
+        ms = []
+        for i in range(0 if args.skip_cold else min(args.steps, 50)):
+            if dirty:
+                flush.fill_(float(i))
+            else:
+                sink.copy_(flush.sum().view(1))
+            a = torch.cuda.Event(enable_timing=True)
+            z = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            step()
+            z.record(stream)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(z))
+        return float(np.median(ms)) if ms else None
+
+    cold_ms = cold_run(False)
+    cold_dirty_ms = cold_run(True)
+    del flush, sink
 
     y = out.cpu().numpy()  # the three-pass output (out is reused below)
 
@@ -626,6 +644,9 @@ def main():
                phase_roofline=phase_roofline,
                cold_ms_per_step=round(cold_ms, 5) if cold_ms else None,
                cold_hbm_frac_3pass=round(48.0 * N / (cold_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4) if cold_ms else None,
+               cold_dirty_ms_per_step=round(cold_dirty_ms, 5) if cold_dirty_ms else None,
+               cold_dirty_hbm_frac_3pass=(round(48.0 * N / (cold_dirty_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                                          if cold_dirty_ms else None),
                plan=plan.description)
     if two is not None:
         rec["two_pass"] = two

@@ -199,8 +199,8 @@ struct SymPass {
     const float *w16;             // split MFMA forms: 64 lanes x 16 DFT-matrix operands (w16_operands)
     int32_t conj_in;              // pass 1: conjugate x on load (the inverse's input map)
     float out_scale;              // pass 3: nonzero stores conj(y) * out_scale (the inverse's output map)
-    uint32_t groups1, groups3;    // passes 1 and 3 at L >= 512: workgroups of their persistent launches
-                                  // (sym_resident_groups; 0: one per tile)
+    uint32_t resident1, resident3;  // passes 1 and 3 at L >= 512: workgroups of their persistent launches
+                                    // (sym_resident_groups; 0: one per tile)
 };
 
 // Workgroup geometry a local pass is launched with.

@@ -545,8 +545,8 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
         q.tw_sj = d_tsj;
         q.w16 = d_tw16;
         // passes 1 and 3 at L >= 512: one workgroup per resident slot
-        q.groups1 = dt == PACO_C64 ? paco::sym_resident_groups(1, q) : paco::sym_mf_resident_groups(int(dt), 1, q);
-        q.groups3 = dt == PACO_C64 ? paco::sym_resident_groups(3, q) : paco::sym_mf_resident_groups(int(dt), 3, q);
+        q.resident1 = dt == PACO_C64 ? paco::sym_resident_groups(1, q) : paco::sym_mf_resident_groups(int(dt), 1, q);
+        q.resident3 = dt == PACO_C64 ? paco::sym_resident_groups(3, q) : paco::sym_mf_resident_groups(int(dt), 3, q);
         P->sym = true;
     }
 

@@ -427,8 +427,8 @@ hipError_t launch_sym_first(const SymPass &p, hipStream_t s)
     const dim3 grid(addr::sym1_groups(uint32_t(p.N2)));
     switch (sym_ll(p)) {
     case 8: hipLaunchKernelGGL(sym_first_kernel<true>, grid, dim3(kSymThreads), 0, s, p); break;
-    case 9: hipLaunchKernelGGL((sym_first_long_kernel<true, 9>), persistent(grid, p.groups1), dim3(512), 0, s, p, grid.x); break;
-    default: hipLaunchKernelGGL((sym_first_long_kernel<true, 10>), persistent(grid, p.groups1), dim3(1024), 0, s, p, grid.x); break;
+    case 9: hipLaunchKernelGGL((sym_first_long_kernel<true, 9>), persistent(grid, p.resident1), dim3(512), 0, s, p, grid.x); break;
+    default: hipLaunchKernelGGL((sym_first_long_kernel<true, 10>), persistent(grid, p.resident1), dim3(1024), 0, s, p, grid.x); break;
     }
     return hipGetLastError();
 }
@@ -451,8 +451,8 @@ hipError_t launch_sym_last(const SymPass &p, hipStream_t s)
     const dim3 grid(addr::sym3_groups(uint32_t(p.N1)));
     switch (sym_ll(p)) {
     case 8: hipLaunchKernelGGL(sym_last_kernel, grid, dim3(kSymThreads), 0, s, p); break;
-    case 9: hipLaunchKernelGGL(sym_last_long_kernel<9>, persistent(grid, p.groups3), dim3(512), 0, s, p, grid.x); break;
-    default: hipLaunchKernelGGL(sym_last_long_kernel<10>, persistent(grid, p.groups3), dim3(1024), 0, s, p, grid.x); break;
+    case 9: hipLaunchKernelGGL(sym_last_long_kernel<9>, persistent(grid, p.resident3), dim3(512), 0, s, p, grid.x); break;
+    default: hipLaunchKernelGGL(sym_last_long_kernel<10>, persistent(grid, p.resident3), dim3(1024), 0, s, p, grid.x); break;
     }
     return hipGetLastError();
 }

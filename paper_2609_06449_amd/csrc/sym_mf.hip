@@ -547,11 +547,11 @@ hipError_t launch_pass(int pass, int ll, const SymPass &p, hipStream_t s)
             hipLaunchKernelGGL(sym_last_mf_kernel<PREC>, g3, dim3(256), 0, s, p);
     } else {
         if (pass == 1)
-            hipLaunchKernelGGL(sym_first_mf_long_kernel<PREC>, persistent(g1, p.groups1), dim3(512), 0, s, p, g1.x);
+            hipLaunchKernelGGL(sym_first_mf_long_kernel<PREC>, persistent(g1, p.resident1), dim3(512), 0, s, p, g1.x);
         else if (pass == 2)
             hipLaunchKernelGGL((sym_middle_mf_kernel<PREC, 9>), g2, dim3(256), 0, s, p);
         else
-            hipLaunchKernelGGL(sym_last_mf_long_kernel<PREC>, persistent(g3, p.groups3), dim3(512), 0, s, p, g3.x);
+            hipLaunchKernelGGL(sym_last_mf_long_kernel<PREC>, persistent(g3, p.resident3), dim3(512), 0, s, p, g3.x);
     }
     return hipGetLastError();
 }
