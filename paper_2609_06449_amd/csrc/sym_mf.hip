@@ -236,8 +236,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == kPr
         float2 t = cmul(th[G], tl[G]);
         if constexpr (PREC == kPrecFP16x3) t = make_float2(ldexpf(t.x, e1), ldexpf(t.y, e1));
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int s = 4 * kb + i;
+        for (int i = 0; i < 4; ++i) {  // output s = 4 kb + i
             lds[addr::mf2_store(kb, i, rr, n)] = cmul(o[G][i], t);
             if (i < 3) t = cmul(t, step);
         }
