@@ -54,6 +54,15 @@ def test_traffic_from_scales_by_the_copy(tmp_path, monkeypatch):
     assert bench.load_traffic("local_fft_fast_kernel<12,2,1,2,16,0>") is None
 
 
+def test_committed_traffic_covers_the_default_plans_kernels():
+    # the roofline's traffic field looks each pass up by its kernel's name:
+    # the committed counter summary must hold all three under those names
+    with open(bench.TRAFFIC_PATH) as f:
+        kernels = json.load(f)["kernels"]
+    for name in bench.SYM_KERNELS:
+        assert name.split()[1] in kernels, name
+
+
 def test_short_kernel_names():
     n = "void paco::(anonymous namespace)::middle_packed2_kernel<false, true>(paco::MiddlePass)"
     assert bench.short_kernel_name(n) == "middle_packed2_kernel<false,true>"
