@@ -88,7 +88,7 @@ typedef struct paco_plan_s paco_plan;
  * N2 = b^m2 with m1, m2 >= 1; p >= 2 with p | N1 and p | N2 (p itself need
  * not be a power of b; the balance argument of section 4.2 uses only the
  * divisibility).  Pure host code: no HIP call, usable without a GPU.
- * Returns PACO_ERR_UNSUPPORTED for sizes this build has no kernels for
+ * Returns PACO_ERR_UNSUPPORTED for sizes the library has no kernels for
  * (N1 or N2 above 2^16, or N1*N2 above 2^28: every buffer stays below
  * 4 GiB, so the kernels address it with 32-bit byte offsets). */
 paco_status paco_plan_validate(int64_t N1, int64_t N2, int64_t p, int32_t b, paco_dtype dt);

@@ -113,7 +113,7 @@ const char *paco_status_string(paco_status st)
     case PACO_ERR_INVALID_ARG: return "invalid argument";
     case PACO_ERR_NOT_POWER_OF_B: return "N1/N2 not a power of b (or b not a power of two >= 2)";
     case PACO_ERR_DIVISIBILITY: return "p must satisfy p >= 2, p | N1 and p | N2";
-    case PACO_ERR_UNSUPPORTED: return "size not supported by this build";
+    case PACO_ERR_UNSUPPORTED: return "size not supported by the library";
     case PACO_ERR_WORKSPACE: return "workspace too small";
     case PACO_ERR_ALLOC: return "allocation failed";
     case PACO_ERR_HIP: return "HIP runtime error";
@@ -142,7 +142,7 @@ paco_status validate_impl(int64_t N1, int64_t N2, int64_t p, int32_t b, paco_dty
     }
     if (p < 2 || N1 % p || N2 % p) return fail(PACO_ERR_DIVISIBILITY, "need p >= 2, p | N1, p | N2");
     if (l1 > kMaxLocalLog2 || l2 > kMaxLocalLog2 || l1 + l2 > kMaxTotalLog2)
-        return fail(PACO_ERR_UNSUPPORTED, "this build supports N1, N2 <= 2^16 and N1*N2 <= 2^28");
+        return fail(PACO_ERR_UNSUPPORTED, "the library supports N1, N2 <= 2^16 and N1*N2 <= 2^28");
     if (N1 / p < 16 || N2 / p < 16)
         g_last_error = "note: slab width N1/p or N2/p below 16 items (one 128-byte line)";
     else
