@@ -94,7 +94,10 @@ typedef struct paco_plan_s paco_plan;
 paco_status paco_plan_validate(int64_t N1, int64_t N2, int64_t p, int32_t b, paco_dtype dt);
 
 /* Validates, builds the pass plan and uploads the plan's tables to the
- * current HIP device.  *plan is NULL on failure. */
+ * current HIP device.  *plan is NULL on failure.  A plan is meant for the
+ * device current at its creation: its tables live there, and the persistent
+ * passes of the symmetric form at N1 = N2 >= 8192 launch as many workgroups
+ * as that device holds at once (counted here). */
 paco_status paco_plan_create(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int32_t b,
                              paco_dtype dt);
 
