@@ -112,7 +112,7 @@ def kernel_hash() -> str:
 
 TRAFFIC_PATH = os.path.join(ROOT, "profiles", "traffic_2p24_4096x4096.json")
 # the passes of the default plan of the 2^24 workload, as rocprofv3 names their kernels
-SYM_KERNELS = ["pass1 sym_first_kernel<true>", "pass2 sym_middle_kernel<8>", "pass3 sym_last_kernel"]
+SYM_KERNELS = ["pass1 sym_first_kernel<true>", "pass2 sym_middle_kernel<8,8>", "pass3 sym_last_kernel"]
 COPY_BYTES = 1 << 28  # the --calibrate-copy device-to-device copy
 
 

@@ -186,20 +186,22 @@ paco_status paco_plan_workspace_size(const paco_plan *plan, size_t *bytes);
  * paco_plan_has_split tells; the plan option PACO_PLAN_NO_SPLIT keeps the
  * other plan.
  *
- * Symmetric split form.  A plan with N1 = N2 = 4096 (any valid b and p,
- * every dtype: the split MFMA forms run each 16-point transform on MFMA in
- * the operand layout) splits Phase III the same way, with its 16-point child moved into
- * the redistribution pass (Lemma 1 on both local phases; Phase I:
- * j1 = 16 j + r, k1 = k + 256 s; Phase III: j2 = jc + 256 rr,
- * k2 = q0 + 16 q):
+ * Symmetric split form.  A plan with N1 = 16 L1 and N2 = 16 L2, L1 and L2
+ * in {256, 512, 1024} (any valid b and p; square shapes with L1 = L2 = 256
+ * or 512 in every dtype, the split MFMA forms running each 16-point
+ * transform on MFMA in the operand layout; L1 = L2 = 1024 and the
+ * non-square shapes in PACO_C64) splits Phase III the same way, with its
+ * 16-point child moved into the redistribution pass (Lemma 1 on both local
+ * phases; Phase I: j1 = 16 j + r, k1 = k + L1 s; Phase III:
+ * j2 = jc + L2 rr, k2 = q0 + 16 q):
  *   pass 1: workspace[((k >> 4)*N2 + c)*256 + 16 r + (k & 15)] = U[c][r][k]
- *           = w_N1^{-k r} sum_j X[16 j + r, c] w_256^{-k j}
- *   pass 2: A[k + 256 s, c] = sum_r w_16^{-s r} U[c][r][k],
+ *           = w_N1^{-k r} sum_j X[16 j + r, c] w_L1^{-k j}
+ *   pass 2: A[k + L1 s, c] = sum_r w_16^{-s r} U[c][r][k],
  *           Z[v, c] = A[v, c] w_N^{-v c},
  *           out[(16 jc + q0)*N1 + v] = W[v][jc][q0]
- *           = w_N2^{-q0 jc} sum_rr Z[v, jc + 256 rr] w_16^{-q0 rr}
+ *           = w_N2^{-q0 jc} sum_rr Z[v, jc + L2 rr] w_16^{-q0 rr}
  *   pass 3: out[(q0 + 16 q)*N1 + v] = Y[q0 + 16 q, v]
- *           = sum_jc w_256^{-q jc} W[v][jc][q0]   (in place)
+ *           = sum_jc w_L2^{-q jc} W[v][jc][q0]   (in place)
  * so that every pass reads and writes whole 128-byte lines; the paper's
  * digit reversals cancel between the redistribution and Phase III's input
  * layout, as in the packed form.  Three HBM passes, the same workspace and

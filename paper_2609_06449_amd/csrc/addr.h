@@ -153,26 +153,27 @@ PACO_HD uint32_t sym1_store_base(uint32_t N2, uint32_t blk, uint32_t tid, uint32
     return ((16u * jp * N2 + (cb << 4) + cl) << 8) + 16u * r + (tid & 15u);
 }
 PACO_HD uint32_t sym1_store_off(uint32_t N2, uint32_t i) { return i * N2 * 256u; }
-// pass 2: tile blk = (L/16) jc + kb.  L = 256: the hardware's workgroup id g
-// maps to (jc, kb) = (g mod L, g / L) (jc fastest: neighbouring workgroups
-// read neighbouring 2 KiB runs); L >= 512: blk = g (kb fastest: the running
-// workgroups' stores fill whole rows of W).  Thread (kk, rr) loads
-// U[jc + L rr][i][16 kb + kk].
-PACO_HD uint32_t sym2_block(uint32_t g, uint32_t ll = 8)
+// pass 2 (children L1 = N1/16 of Phase I, L2 = N2/16 of Phase III; ll1,
+// ll2 their log2): tile blk = (L1/16) jc + kb, jc < L2, kb < L1/16.
+// L1 = 256: the hardware's workgroup id g maps to (jc, kb) = (g mod L2,
+// g / L2) (jc fastest: neighbouring workgroups read neighbouring 2 KiB runs);
+// L1 >= 512: blk = g (kb fastest: the running workgroups' stores fill whole
+// rows of W).  Thread (kk, rr) loads U[jc + L2 rr][i][16 kb + kk].
+PACO_HD uint32_t sym2_block(uint32_t g, uint32_t ll1, uint32_t ll2)
 {
-    return ll == 8 ? ((g & ((1u << ll) - 1u)) << (ll - 4)) | (g >> ll) : g;
+    return ll1 == 8 ? ((g & ((1u << ll2) - 1u)) << (ll1 - 4)) | (g >> ll2) : g;
 }
-PACO_HD uint32_t sym2_load_base(uint32_t N2, uint32_t blk, uint32_t tid, uint32_t ll = 8)
+PACO_HD uint32_t sym2_load_base(uint32_t N2, uint32_t blk, uint32_t tid, uint32_t ll1, uint32_t ll2)
 {
-    const uint32_t kb = blk & ((1u << (ll - 4)) - 1u), jc = blk >> (ll - 4);
-    return ((kb * N2 + jc + ((tid >> 4) << ll)) << 8) + (tid & 15u);
+    const uint32_t kb = blk & ((1u << (ll1 - 4)) - 1u), jc = blk >> (ll1 - 4);
+    return ((kb * N2 + jc + ((tid >> 4) << ll2)) << 8) + (tid & 15u);
 }
 PACO_HD uint32_t sym2_load_off(uint32_t i) { return 16u * i; }
-// thread (kk, s) stores W at row 16 jc + i, column 16 kb + kk + L s
-PACO_HD uint32_t sym2_store_base(uint32_t N1, uint32_t blk, uint32_t tid, uint32_t ll = 8)
+// thread (kk, s) stores W at row 16 jc + i, column 16 kb + kk + L1 s
+PACO_HD uint32_t sym2_store_base(uint32_t N1, uint32_t blk, uint32_t tid, uint32_t ll1)
 {
-    const uint32_t kb = blk & ((1u << (ll - 4)) - 1u), jc = blk >> (ll - 4);
-    return 16u * jc * N1 + 16u * kb + (tid & 15u) + ((tid >> 4) << ll);
+    const uint32_t kb = blk & ((1u << (ll1 - 4)) - 1u), jc = blk >> (ll1 - 4);
+    return 16u * jc * N1 + 16u * kb + (tid & 15u) + ((tid >> 4) << ll1);
 }
 PACO_HD uint32_t sym2_store_off(uint32_t N1, uint32_t i) { return i * N1; }
 // pass 3: workgroup (q0, vb) = (blk / (N1/16), blk mod (N1/16)); thread

@@ -186,7 +186,7 @@ constexpr int kTwTile = 128;  // tile-twiddle table side: [i*128 + j] = w_N^{-(i
 //   pass 3: Y[q0 + 16 q, v] = sum_jc w_L^{-q jc} W[v][jc][q0]
 //           -> out[(q0 + 16 q) N1 + v], in place (a tile reads and writes the
 //           same rows {q0 + 16 t})
-constexpr int kSymLog2N = 12;  // N1 = N2 = 2^12: every dtype
+constexpr int kSymLog2N = 12;  // the smallest side of the symmetric split form (L = 256)
 struct SymPass {
     const float2 *src;
     float2 *dst;
@@ -245,8 +245,11 @@ hipError_t launch_split_middle(const SplitPass &p, hipStream_t s);
 hipError_t split_prepare();  // raises the dynamic-LDS limit of the three-stage pass 2 once
 // The three passes of the symmetric split form; hipErrorInvalidValue unless
 // sym_log2_child(p) is nonzero.
-// log2 L of a shape the symmetric form runs (N1 = N2 = 16 L, L = 256, 512,
-// 1024; the split MFMA forms: 256 and 512), else 0
+// The child sizes L1 = N1/16 and L2 = N2/16 of a shape the symmetric form
+// runs, as log2 (8, 9 or 10 each: N1, N2 in {2^12, 2^13, 2^14}), or false.
+bool sym_children(const SymPass &p, int &ll1, int &ll2);
+// log2 L of a square shape the symmetric form runs (N1 = N2 = 16 L; the
+// split MFMA forms run L = 256 and 512), else 0
 int sym_log2_child(const SymPass &p);
 // Workgroups the current device holds at once of the persistent pass-1 or
 // pass-3 kernel of p's shape (L >= 512), 0 for L = 256 or if the runtime does

@@ -257,15 +257,19 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
         for (int64_t k = 0; k < 16 * N1; ++k) tcw[k] = paco::root_neg(k, 16 * N1);
     }
     paco::middle_tables(P->lN, thi, tlo, ttile);
-    // the symmetric split form (N1 = N2 = 16 L: L = 256 and 512 for every
-    // dtype, 1024 in FP32; option PACO_PLAN_NO_SYM)
-    const bool sym_form = !no_split && !no_sym && !paper_layout && !generic && P->l1 == P->l2 &&
-                          (P->l1 == paco::kSymLog2N || P->l1 == 13 || (dt == PACO_C64 && P->l1 == 14));
-    if (sym_form) {  // its pass-2 factor w_{16 N2}^{-s jc}, s < 16, jc < L
-        const int64_t L = N1 / 16;
-        tsj.resize(size_t(16 * L));
+    // the symmetric split form (N1 = 16 L1, N2 = 16 L2; option
+    // PACO_PLAN_NO_SYM): square shapes with L = 256 and 512 for every dtype,
+    // 1024 in FP32; in FP32 also every non-square pair of N1, N2 in {2^12,
+    // 2^13, 2^14} (N1 N2 <= 2^28 by validation)
+    const auto sym_side = [](int l) { return l >= paco::kSymLog2N && l <= paco::kSymLog2N + 2; };
+    const bool sym_square = P->l1 == P->l2 && (P->l1 == paco::kSymLog2N || P->l1 == 13 || (dt == PACO_C64 && P->l1 == 14));
+    const bool sym_rect = dt == PACO_C64 && P->l1 != P->l2 && sym_side(P->l1) && sym_side(P->l2);
+    const bool sym_form = !no_split && !no_sym && !paper_layout && !generic && (sym_square || sym_rect);
+    if (sym_form) {  // its pass-2 factor w_{16 N2}^{-s jc}, s < 16, jc < L2
+        const int64_t L2 = N2 / 16;
+        tsj.resize(size_t(16 * L2));
         for (int64_t sv = 0; sv < 16; ++sv)
-            for (int64_t jc = 0; jc < L; ++jc) tsj[sv * L + jc] = paco::root_neg((sv * jc) % (16 * N2), 16 * N2);
+            for (int64_t jc = 0; jc < L2; ++jc) tsj[sv * L2 + jc] = paco::root_neg((sv * jc) % (16 * N2), 16 * N2);
         if (dt != PACO_C64) {  // the MFMA lanes' DFT-matrix operands
             tw16.resize(64 * 16);
             paco::w16_operands(tw16.data());

@@ -1,4 +1,6 @@
-// The symmetric split form (FP32) for N1 = N2 = 4096.
+// The symmetric split form (FP32), N1 = 16 L1 and N2 = 16 L2 with L1, L2 in
+// {256, 512, 1024}; written out below for N1 = N2 = 4096 (L = 256), the
+// other sizes replacing 256 by L1 in Phase I and by L2 in Phase III.
 //
 // Both local phases are split once more by Cooley-Tukey (Lemma 1), each with
 // one 16-point child, and both 16-point children run in the redistribution
@@ -122,20 +124,22 @@ __global__ __launch_bounds__(kSymThreads) void sym_first_kernel(SymPass P)
 // fastest, padded LDS, the factor as a product of two-level table entries):
 // 54 against 63 us, and pass 1, which now stores 128-byte runs, 45 against
 // 50 us.  Five waves per SIMD (96 VGPRs, 32 KiB of LDS).
-// L = 2^LL (N1 = N2 = 16 L): jc < L, kb < L/16, c = jc + L rr, and the
-// pass-2 factor table holds w_{16 N2}^{-s jc} at [s L + jc].
-template <int LL>
+// Children L1 = 2^LL1 = N1/16 (Phase I) and L2 = 2^LL2 = N2/16 (Phase III):
+// jc < L2, kb < L1/16, c = jc + L2 rr, v = k + L1 s, and the pass-2 factor
+// table holds w_{16 N2}^{-s jc} at [s L2 + jc].  The split of the top-level
+// factor holds for any L1, L2: N / L1 = 16 N2 and 16 N2 / L2 = 256.
+template <int LL1, int LL2>
 __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(5))) void sym_middle_kernel(SymPass P)
 {
     __shared__ float2 lds[16 * 256];
     const int tid = threadIdx.x;
     const uint32_t N1 = uint32_t(P.N1), N2 = uint32_t(P.N2);
-    const uint32_t blk = addr::sym2_block(blockIdx.x, LL);
-    const uint32_t kb = blk & ((1u << (LL - 4)) - 1u), jc = blk >> (LL - 4);
+    const uint32_t blk = addr::sym2_block(blockIdx.x, LL1, LL2);
+    const uint32_t kb = blk & ((1u << (LL1 - 4)) - 1u), jc = blk >> (LL1 - 4);
     const int kk = tid & 15, rr = tid >> 4;
-    const uint32_t c = jc + (uint32_t(rr) << LL), k = 16u * kb + kk;
+    const uint32_t c = jc + (uint32_t(rr) << LL2), k = 16u * kb + kk;
     float2 v[16];
-    const float2 *src = P.src + addr::sym2_load_base(N2, blk, tid, LL);
+    const float2 *src = P.src + addr::sym2_load_base(N2, blk, tid, LL1, LL2);
 #pragma unroll
     for (int r = 0; r < 16; ++r) v[r] = ld2_last(src + addr::sym2_load_off(r));  // last use
     const uint32_t nmask = uint32_t((uint64_t(1) << P.log2N) - 1), lomask = (1u << P.log2Lo) - 1u;
@@ -144,9 +148,9 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(5))
     float2 t2[16], t3[16], t4[16];
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
-        t2[s] = P.tw_sj[(s << LL) + jc];                             // w_{16 N2}^{-s jc}
+        t2[s] = P.tw_sj[(s << LL2) + jc];                            // w_{16 N2}^{-s jc}
         t3[s] = root_of(P.tw, P.log2L, 8, uint32_t(s * rr));        // w_256^{-s rr}
-        t4[s] = root_of(P.tw, P.log2L, LL + 4, uint32_t(s) * jc);  // w_N2^{-q0 jc}, q0 = s
+        t4[s] = root_of(P.tw, P.log2L, LL2 + 4, uint32_t(s) * jc);  // w_N2^{-q0 jc}, q0 = s
     }
     dft_regs<4>(v);
     const float2 t1 = cmul(h1, l1);
@@ -160,7 +164,7 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(5))
 #pragma unroll
     for (int i = 0; i < 16; ++i) v[i] = lds[s2 * 256 + ((i ^ (s2 & 1)) << 4) + kk];
     dft_regs<4>(v);
-    float2 *dst = P.dst + addr::sym2_store_base(N1, blk, tid, LL);
+    float2 *dst = P.dst + addr::sym2_store_base(N1, blk, tid, LL1);
 #pragma unroll
     for (int q0 = 0; q0 < 16; ++q0) dst[addr::sym2_store_off(N1, q0)] = q0 ? cmul(v[q0], t4[q0]) : v[q0];
 }
@@ -396,25 +400,44 @@ __global__ __launch_bounds__(1 << LL) __attribute__((amdgpu_waves_per_eu(4))) vo
     }
 }
 
-int sym_ll(const SymPass &p) { return sym_log2_child(p); }
-
-bool sym_shape_ok(const SymPass &p)
+bool sym_shape_ok(const SymPass &p, int &ll1, int &ll2)
 {
-    return sym_ll(p) && p.src && p.dst && p.tw && p.tw_hi && p.tw_lo && p.tw_sj;
+    return sym_children(p, ll1, ll2) && p.src && p.dst && p.tw && p.tw_hi && p.tw_lo && p.tw_sj;
+}
+
+int log2_child(int64_t n) { return n == 4096 ? 8 : n == 8192 ? 9 : n == 16384 ? 10 : 0; }
+
+// pass 2 for L1 = 2^LL1 and L2 = 2^ll2
+template <int LL1>
+void launch_middle(int ll2, dim3 grid, const SymPass &p, hipStream_t s)
+{
+    switch (ll2) {
+    case 8: hipLaunchKernelGGL((sym_middle_kernel<LL1, 8>), grid, dim3(kSymThreads), 0, s, p); break;
+    case 9: hipLaunchKernelGGL((sym_middle_kernel<LL1, 9>), grid, dim3(kSymThreads), 0, s, p); break;
+    default: hipLaunchKernelGGL((sym_middle_kernel<LL1, 10>), grid, dim3(kSymThreads), 0, s, p); break;
+    }
 }
 
 }  // namespace
 
+bool sym_children(const SymPass &p, int &ll1, int &ll2)
+{
+    ll1 = log2_child(p.N1);
+    ll2 = log2_child(p.N2);
+    return ll1 && ll2 && p.log2L >= (ll1 > ll2 ? ll1 : ll2) + 4 && p.log2N == ll1 + ll2 + 8;
+}
+
 int sym_log2_child(const SymPass &p)
 {
-    if (p.N1 != p.N2) return 0;
-    const int ll = p.N1 == 4096 ? 8 : p.N1 == 8192 ? 9 : p.N1 == 16384 ? 10 : 0;
-    return ll && p.log2L >= ll + 4 && p.log2N == 2 * (ll + 4) ? ll : 0;
+    int ll1 = 0, ll2 = 0;
+    return sym_children(p, ll1, ll2) && ll1 == ll2 ? ll1 : 0;
 }
 
 uint32_t sym_resident_groups(int pass, const SymPass &p)
 {
-    switch (sym_ll(p)) {
+    int ll1 = 0, ll2 = 0;
+    if (!sym_children(p, ll1, ll2)) return 0;
+    switch (pass == 1 ? ll1 : ll2) {
     case 9: return pass == 1 ? resident(sym_first_long_kernel<true, 9>, 512) : resident(sym_last_long_kernel<9>, 512);
     case 10: return pass == 1 ? resident(sym_first_long_kernel<true, 10>, 1024) : resident(sym_last_long_kernel<10>, 1024);
     default: return 0;
@@ -423,9 +446,10 @@ uint32_t sym_resident_groups(int pass, const SymPass &p)
 
 hipError_t launch_sym_first(const SymPass &p, hipStream_t s)
 {
-    if (!sym_shape_ok(p)) return hipErrorInvalidValue;
+    int ll1 = 0, ll2 = 0;
+    if (!sym_shape_ok(p, ll1, ll2)) return hipErrorInvalidValue;
     const dim3 grid(addr::sym1_groups(uint32_t(p.N2)));
-    switch (sym_ll(p)) {
+    switch (ll1) {
     case 8: hipLaunchKernelGGL(sym_first_kernel<true>, grid, dim3(kSymThreads), 0, s, p); break;
     case 9: hipLaunchKernelGGL((sym_first_long_kernel<true, 9>), persistent(grid, p.resident1), dim3(512), 0, s, p, grid.x); break;
     default: hipLaunchKernelGGL((sym_first_long_kernel<true, 10>), persistent(grid, p.resident1), dim3(1024), 0, s, p, grid.x); break;
@@ -435,21 +459,23 @@ hipError_t launch_sym_first(const SymPass &p, hipStream_t s)
 
 hipError_t launch_sym_middle(const SymPass &p, hipStream_t s)
 {
-    if (!sym_shape_ok(p)) return hipErrorInvalidValue;
+    int ll1 = 0, ll2 = 0;
+    if (!sym_shape_ok(p, ll1, ll2)) return hipErrorInvalidValue;
     const dim3 grid(addr::sym2_groups(uint32_t(p.N1), uint32_t(p.N2)));
-    switch (sym_ll(p)) {
-    case 8: hipLaunchKernelGGL(sym_middle_kernel<8>, grid, dim3(kSymThreads), 0, s, p); break;
-    case 9: hipLaunchKernelGGL(sym_middle_kernel<9>, grid, dim3(kSymThreads), 0, s, p); break;
-    default: hipLaunchKernelGGL(sym_middle_kernel<10>, grid, dim3(kSymThreads), 0, s, p); break;
+    switch (ll1) {
+    case 8: launch_middle<8>(ll2, grid, p, s); break;
+    case 9: launch_middle<9>(ll2, grid, p, s); break;
+    default: launch_middle<10>(ll2, grid, p, s); break;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_sym_last(const SymPass &p, hipStream_t s)
 {
-    if (!sym_shape_ok(p)) return hipErrorInvalidValue;
+    int ll1 = 0, ll2 = 0;
+    if (!sym_shape_ok(p, ll1, ll2)) return hipErrorInvalidValue;
     const dim3 grid(addr::sym3_groups(uint32_t(p.N1)));
-    switch (sym_ll(p)) {
+    switch (ll2) {
     case 8: hipLaunchKernelGGL(sym_last_kernel, grid, dim3(kSymThreads), 0, s, p); break;
     case 9: hipLaunchKernelGGL(sym_last_long_kernel<9>, persistent(grid, p.resident3), dim3(512), 0, s, p, grid.x); break;
     default: hipLaunchKernelGGL(sym_last_long_kernel<10>, persistent(grid, p.resident3), dim3(1024), 0, s, p, grid.x); break;

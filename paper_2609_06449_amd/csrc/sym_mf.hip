@@ -200,12 +200,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PREC == kPr
     const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n = lane & 15, kb = lane >> 4, comp = kb >> 1, half = kb & 1;
     const uint32_t N1 = uint32_t(P.N1), N2 = uint32_t(P.N2);
-    const uint32_t blk = addr::sym2_block(blockIdx.x, LL);
+    const uint32_t blk = addr::sym2_block(blockIdx.x, LL, LL);
     const uint32_t jc = blk >> (LL - 4), k = 16u * (blk & ((1u << (LL - 4)) - 1u)) + n;
     float2 it[4][4];
 #pragma unroll
     for (int G = 0; G < 4; ++G) {
-        const float2 *src = P.src + addr::sym2_load_base(N2, blk, uint32_t(n + 16 * (4 * w + G)), LL);
+        const float2 *src = P.src + addr::sym2_load_base(N2, blk, uint32_t(n + 16 * (4 * w + G)), LL, LL);
 #pragma unroll
         for (int q = 0; q < 4; ++q) it[G][q] = ld2_last(src + addr::sym2_load_off(uint32_t(8 * half + (comp ? 4 + q : q))));
     }

@@ -67,56 +67,57 @@ uint32_t item(uint32_t base, uint32_t off, uint64_t N, const char *what)
 }
 
 // N1 = N2 = 16 L, L = 2^ll: L threads per workgroup in passes 1 and 3, 256 in pass 2
-void audit_sym(uint32_t ll)
+void audit_sym(uint32_t ll1, uint32_t ll2)
 {
-    const uint32_t N1 = 16u << ll, N2 = N1, T = 1u << ll;
+    const uint32_t N1 = 16u << ll1, N2 = 16u << ll2, T1 = 1u << ll1, T3 = 1u << ll2;
     const uint64_t N = uint64_t(N1) * N2;
     {
         Cover rd(N), wr(N), blocks(addr::sym1_groups(N2));
         for (uint32_t g = 0; g < addr::sym1_groups(N2); ++g) {
-            const uint32_t blk = addr::sym1_block(g, N2, ll);
+            const uint32_t blk = addr::sym1_block(g, N2, ll1);
             CHECK(blk < addr::sym1_groups(N2), "sym pass 1 block id out of range");
             blocks.hit(blk);
-            for (uint32_t tid = 0; tid < T; ++tid)
+            for (uint32_t tid = 0; tid < T1; ++tid)
                 for (uint32_t i = 0; i < 16; ++i) {
-                    rd.hit(item(addr::sym1_load_base(N2, blk, tid), addr::sym1_load_off(N2, i, ll), N, "sym pass 1 load"));
-                    wr.hit(item(addr::sym1_store_base(N2, blk, tid, ll), addr::sym1_store_off(N2, i), N,
+                    rd.hit(item(addr::sym1_load_base(N2, blk, tid), addr::sym1_load_off(N2, i, ll1), N, "sym pass 1 load"));
+                    wr.hit(item(addr::sym1_store_base(N2, blk, tid, ll1), addr::sym1_store_off(N2, i), N,
                                 "sym pass 1 store"));
                 }
         }
-        CHECK(blocks.exact(), "sym pass 1 block order is not a permutation (L = 2^%u)", ll);
-        CHECK(rd.exact() && wr.exact(), "sym pass 1 is not a permutation (L = 2^%u)", ll);
+        CHECK(blocks.exact(), "sym pass 1 block order is not a permutation (%u x %u)", N1, N2);
+        CHECK(rd.exact() && wr.exact(), "sym pass 1 is not a permutation (%u x %u)", N1, N2);
     }
     {
         Cover rd(N), wr(N), blocks(addr::sym2_groups(N1, N2));
         for (uint32_t g = 0; g < addr::sym2_groups(N1, N2); ++g) {
-            const uint32_t blk = addr::sym2_block(g, ll);
+            const uint32_t blk = addr::sym2_block(g, ll1, ll2);
             CHECK(blk < addr::sym2_groups(N1, N2), "sym pass 2 block id out of range");
             blocks.hit(blk);
             for (uint32_t tid = 0; tid < 256; ++tid)
                 for (uint32_t i = 0; i < 16; ++i) {
-                    rd.hit(item(addr::sym2_load_base(N2, blk, tid, ll), addr::sym2_load_off(i), N, "sym pass 2 load"));
-                    wr.hit(item(addr::sym2_store_base(N1, blk, tid, ll), addr::sym2_store_off(N1, i), N,
+                    rd.hit(item(addr::sym2_load_base(N2, blk, tid, ll1, ll2), addr::sym2_load_off(i), N,
+                                "sym pass 2 load"));
+                    wr.hit(item(addr::sym2_store_base(N1, blk, tid, ll1), addr::sym2_store_off(N1, i), N,
                                 "sym pass 2 store"));
                 }
         }
-        CHECK(blocks.exact(), "sym pass 2 block order is not a permutation (L = 2^%u)", ll);
-        CHECK(rd.exact() && wr.exact(), "sym pass 2 is not a permutation (L = 2^%u)", ll);
+        CHECK(blocks.exact(), "sym pass 2 block order is not a permutation (%u x %u)", N1, N2);
+        CHECK(rd.exact() && wr.exact(), "sym pass 2 is not a permutation (%u x %u)", N1, N2);
     }
     {
         Cover rd(N), wr(N), blocks(addr::sym3_groups(N1));
         std::vector<uint32_t> a, b;
         for (uint32_t g = 0; g < addr::sym3_groups(N1); ++g) {
-            const uint32_t blk = addr::sym3_block(g, N1, ll);
+            const uint32_t blk = addr::sym3_block(g, N1, ll2);
             CHECK(blk < addr::sym3_groups(N1), "sym pass 3 block id out of range");
             blocks.hit(blk);
             a.clear();
             b.clear();
-            for (uint32_t tid = 0; tid < T; ++tid)
+            for (uint32_t tid = 0; tid < T3; ++tid)
                 for (uint32_t i = 0; i < 16; ++i) {
-                    a.push_back(item(addr::sym3_load_base(N1, blk, tid), addr::sym3_load_off(N1, i, ll), N,
+                    a.push_back(item(addr::sym3_load_base(N1, blk, tid), addr::sym3_load_off(N1, i, ll2), N,
                                      "sym pass 3 load"));
-                    b.push_back(item(addr::sym3_store_base(N1, blk, tid, ll), addr::sym3_store_off(N1, i), N,
+                    b.push_back(item(addr::sym3_store_base(N1, blk, tid, ll2), addr::sym3_store_off(N1, i), N,
                                      "sym pass 3 store"));
                 }
             for (uint32_t x : a) rd.hit(x);
@@ -125,8 +126,8 @@ void audit_sym(uint32_t ll)
             std::sort(b.begin(), b.end());
             CHECK(a == b, "sym pass 3 workgroup %u reads and writes different items (in place)", blk);
         }
-        CHECK(blocks.exact(), "sym pass 3 block order is not a permutation (L = 2^%u)", ll);
-        CHECK(rd.exact() && wr.exact(), "sym pass 3 is not a permutation (L = 2^%u)", ll);
+        CHECK(blocks.exact(), "sym pass 3 block order is not a permutation (%u x %u)", N1, N2);
+        CHECK(rd.exact() && wr.exact(), "sym pass 3 is not a permutation (%u x %u)", N1, N2);
     }
     std::printf("ok symmetric split form %u x %u: three passes are permutations, pass 3 in place per workgroup\n", N1,
                 N2);
@@ -331,8 +332,10 @@ int main(int argc, char **argv)
 {
     const bool full = argc > 1;  // also the 2^28 shapes (about 2 x 2^28 items per pass)
     audit_digit_maps();
-    audit_sym(8);
-    audit_sym(9);
+    audit_sym(8, 8);
+    audit_sym(9, 9);
+    audit_sym(8, 9);
+    audit_sym(9, 8);
     audit_mf_exchange("pass 1", addr::kMf1Items, addr::mf1_store, addr::mf1_load, true, addr::kMf1Spare);
     audit_mf_exchange("pass 2", 16 * 256, addr::mf2_store, addr::mf2_load, false, -1);
     audit_mf_exchange("pass 3", addr::kMf1Items, addr::mf3_store, addr::mf3_load, false, addr::kMf3Spare);
@@ -345,7 +348,11 @@ int main(int argc, char **argv)
             for (int t : {1, 2, 3, 4})
                 audit_split(N1, N2, t, true);
     if (full) {  // the 2^28 shapes the benchmark times, every workgroup
-        audit_sym(10);
+        audit_sym(10, 10);
+        audit_sym(8, 10);
+        audit_sym(10, 8);
+        audit_sym(9, 10);
+        audit_sym(10, 9);
         audit_split(16384, 16384, 2, false);
         audit_split(16384, 16384, 4, true);
         audit_split(8192, 32768, 1, false);

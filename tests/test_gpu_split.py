@@ -69,7 +69,9 @@ SHAPES = [(4096, 64, 4, 4), (4096, 256, 16, 16), (4096, 512, 8, 2), (4096, 1024,
 @pytest.mark.parametrize("N1,N2,p,b", SHAPES)
 def test_split_matches_oracle(N1, N2, p, b):
     x = inputs.normal(N1 * N2, seed=N2 + 7)
-    plan = paco.Plan(N1, N2, p, b)
+    # (4096 x 16384 runs the symmetric split form by default: the option
+    # keeps this form, which the other shapes take anyway)
+    plan = paco.Plan(N1, N2, p, b, flags=paco.PACO_PLAN_NO_SYM)
     assert plan.has_split, plan.description
     assert plan.description.startswith("fused[") and "split[" in plan.description
     y = _execute(plan, _dev(x))
@@ -225,8 +227,10 @@ def test_which_plans_split():
     assert paco.Plan(4096, 4096, 64, 16, flags=paco.PACO_PLAN_NO_SYM).has_split == 1
     assert not paco.Plan(256, 4096, 4, 16).has_split          # N1 != 4096
     assert not paco.Plan(1024, 4096, 4, 4).has_split
-    assert paco.Plan(4096, 8192, 64, 2).has_split
-    assert paco.Plan(4096, 16384, 64, 4).has_split
+    assert paco.Plan(4096, 8192, 64, 2).has_split == 2                         # non-square symmetric form
+    assert paco.Plan(4096, 16384, 64, 4).has_split == 2
+    assert paco.Plan(4096, 16384, 64, 4, flags=paco.PACO_PLAN_NO_SYM).has_split == 1
+    assert paco.Plan(4096, 16384, 64, 4, paco.PACO_C64_MFMA_FP16X3).has_split != 2  # FP32 only there
     assert not paco.Plan(4096, 32768, 64, 2).has_split        # N2 above 2^14: not measured, the packed form
     assert paco.Plan(16384, 64, 4, 4).has_split and paco.Plan(8192, 64, 4, 2).has_split
     # launches paco_execute makes: pass 1, pass 2 and Phase III's passes
