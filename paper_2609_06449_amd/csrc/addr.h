@@ -197,6 +197,50 @@ PACO_HD uint32_t sym1_groups(uint32_t N2) { return 16u * (N2 >> 4); }
 PACO_HD uint32_t sym2_groups(uint32_t N1, uint32_t N2) { return (N2 >> 4) * (N1 >> 8); }
 PACO_HD uint32_t sym3_groups(uint32_t N1) { return 16u * (N1 >> 4); }
 
+// ---- Phase III child of radix R = 2^lr in pass 2 (lr = 4 as above, or 5) --
+// With N2 = R L2 the Phase III split is j2 = jc + L2 rr, k2 = q0 + R q (rr,
+// q0 < R; jc, q < L2): pass 2 stores W at row R jc + q0, pass 3 transforms
+// rows R t + q0 (t < L2) of each 16-column tile and stores row q0 + R q.
+// R = 32 (the wide form) takes N2 = 2^15 with L2 = 1024 on chip; pass 1 and
+// its workspace do not depend on R.  For lr = 4 the pass-3 maps below equal
+// the sym3_ maps above.
+// Pass 2, R = 32: 512 threads per workgroup.  Loads as sym2_load_base with
+// thread (kk, rr), rr < 32.  Stores by thread (kk, p, s) = (tid & 15,
+// (tid >> 4) & 1, tid >> 5), which holds outputs q0 = i + 16 p of the
+// 32-point transform: row 32 jc + 16 p + i, column 16 kb + kk + L1 s.
+PACO_HD uint32_t sym2w_store_base(uint32_t N1, uint32_t blk, uint32_t tid, uint32_t ll1)
+{
+    const uint32_t kb = blk & ((1u << (ll1 - 4)) - 1u), jc = blk >> (ll1 - 4);
+    return (32u * jc + 16u * ((tid >> 4) & 1u)) * N1 + 16u * kb + (tid & 15u) + ((tid >> 5) << ll1);
+}
+PACO_HD uint32_t sym2w_store_off(uint32_t N1, uint32_t i) { return i * N1; }
+PACO_HD uint32_t sym2w_groups(uint32_t N1, uint32_t N2) { return (N2 >> 5) * (N1 >> 8); }
+// Pass 3 at L = 2^ll >= 512 (the persistent kernels): tile (q0, vb),
+// q0 < R fastest at ll >= 10 as in sym3_block
+PACO_HD uint32_t sym3r_block(uint32_t g, uint32_t N1, uint32_t ll, uint32_t lr)
+{
+    return ll >= 10 ? (g & ((1u << lr) - 1u)) * (N1 >> 4) + (g >> lr) : g;
+}
+// thread (cl, jl) loads row R (jl + (L/16) i) + q0, column 16 vb + cl
+PACO_HD uint32_t sym3r_load_base(uint32_t N1, uint32_t blk, uint32_t tid, uint32_t lr)
+{
+    const uint32_t nvb = N1 >> 4, vb = blk % nvb, q0 = blk / nvb;
+    return (((tid >> 4) << lr) + q0) * N1 + (vb << 4) + (tid & 15u);
+}
+PACO_HD uint32_t sym3r_load_off(uint32_t N1, uint32_t i, uint32_t ll, uint32_t lr)
+{
+    return (i << (ll + lr - 4)) * N1;
+}
+// stage-B thread (cl, jp, ka) stores row q0 + R q, q = ka + 16 (i + 16 jp)
+PACO_HD uint32_t sym3r_store_base(uint32_t N1, uint32_t blk, uint32_t tid, uint32_t ll, uint32_t lr)
+{
+    const uint32_t nvb = N1 >> 4, vb = blk % nvb, q0 = blk / nvb;
+    const uint32_t jp = (tid >> 4) & ((1u << (ll - 8)) - 1u), ka = tid >> (ll - 4);
+    return (q0 + (ka << lr) + (jp << (lr + 8))) * N1 + (vb << 4) + (tid & 15u);
+}
+PACO_HD uint32_t sym3r_store_off(uint32_t N1, uint32_t i, uint32_t lr) { return (i << (lr + 4)) * N1; }
+PACO_HD uint32_t sym3r_groups(uint32_t N1, uint32_t lr) { return (N1 >> 4) << lr; }
+
 // Exchange buffers of the MFMA passes (sym_mf.hip): 16 rows of 256 items.
 // Stage-1 results: lane (n, kb) stores output i of group j, logical row
 // 4 kb + i, column 16 j + n (8-byte stores; a half-wave covers two rows).

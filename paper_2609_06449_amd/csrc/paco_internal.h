@@ -195,7 +195,7 @@ struct SymPass {
     int32_t log2L;
     const float2 *tw_hi, *tw_lo;  // w_N^{-e} = tw_hi[e >> log2Lo] * tw_lo[e mod 2^log2Lo]
     int32_t log2N, log2Lo;
-    const float2 *tw_sj;          // [s L + jc] = w_{16 N2}^{-s jc}, s < 16, jc < L = N2 / 16
+    const float2 *tw_sj;          // [s N2/16 + j] = w_{16 N2}^{-s j}, s < 16, j < N2 / 16
     const float *w16;             // split MFMA forms: 64 lanes x 16 DFT-matrix operands (w16_operands)
     int32_t conj_in;              // pass 1: conjugate x on load (the inverse's input map)
     float out_scale;              // pass 3: nonzero stores conj(y) * out_scale (the inverse's output map)
@@ -245,9 +245,11 @@ hipError_t launch_split_middle(const SplitPass &p, hipStream_t s);
 hipError_t split_prepare();  // raises the dynamic-LDS limit of the three-stage pass 2 once
 // The three passes of the symmetric split form; hipErrorInvalidValue unless
 // sym_log2_child(p) is nonzero.
-// The child sizes L1 = N1/16 and L2 = N2/16 of a shape the symmetric form
-// runs, as log2 (8, 9 or 10 each: N1, N2 in {2^12, 2^13, 2^14}), or false.
-bool sym_children(const SymPass &p, int &ll1, int &ll2);
+// The child sizes of a shape the symmetric form runs, or false: L1 = N1/16
+// and L2 = N2/R as log2 ll1, ll2 (8, 9 or 10 each), and lr2 = log2 R, the
+// radix of pass 2's Phase III child: 4 for N1, N2 in {2^12, 2^13, 2^14}, 5
+// (the wide form) for N2 = 2^15 with N1 = 2^12 or 2^13.
+bool sym_children(const SymPass &p, int &ll1, int &ll2, int &lr2);
 // log2 L of a square shape the symmetric form runs (N1 = N2 = 16 L; the
 // split MFMA forms run L = 256 and 512), else 0
 int sym_log2_child(const SymPass &p);

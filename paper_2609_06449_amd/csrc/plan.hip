@@ -260,12 +260,14 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
     // the symmetric split form (N1 = 16 L1, N2 = 16 L2; option
     // PACO_PLAN_NO_SYM): square shapes with L = 256 and 512 for every dtype,
     // 1024 in FP32; in FP32 also every non-square pair of N1, N2 in {2^12,
-    // 2^13, 2^14} (N1 N2 <= 2^28 by validation)
+    // 2^13, 2^14} (N1 N2 <= 2^28 by validation), and the wide form N2 = 2^15
+    // = 32 L2 (L2 = 1024) with N1 = 2^12 or 2^13
     const auto sym_side = [](int l) { return l >= paco::kSymLog2N && l <= paco::kSymLog2N + 2; };
     const bool sym_square = P->l1 == P->l2 && (P->l1 == paco::kSymLog2N || P->l1 == 13 || (dt == PACO_C64 && P->l1 == 14));
     const bool sym_rect = dt == PACO_C64 && P->l1 != P->l2 && sym_side(P->l1) && sym_side(P->l2);
-    const bool sym_form = !no_split && !no_sym && !paper_layout && !generic && (sym_square || sym_rect);
-    if (sym_form) {  // its pass-2 factor w_{16 N2}^{-s jc}, s < 16, jc < L2
+    const bool sym_wide = dt == PACO_C64 && P->l2 == 15 && (P->l1 == 12 || P->l1 == 13);
+    const bool sym_form = !no_split && !no_sym && !paper_layout && !generic && (sym_square || sym_rect || sym_wide);
+    if (sym_form) {  // its pass-2 factor w_{16 N2}^{-s j}, s < 16, j < N2 / 16 (jc < L2 <= N2 / 16)
         const int64_t L2 = N2 / 16;
         tsj.resize(size_t(16 * L2));
         for (int64_t sv = 0; sv < 16; ++sv)
@@ -576,10 +578,11 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
     }
     if (P->fused) desc = "fused[phase1 -> packed transposed slab, phase2 row unpack+twiddle] " + desc;
     if (P->sym) {
+        const int64_t r2 = sym_wide ? 32 : 16;
         std::snprintf(buf, sizeof buf,
                       "sym[pass1: phase1 %lld-point children over rows 16j+r -> ws; pass2: phase1 radix-16 + twiddle + "
-                      "phase3 radix-16; pass3: phase3 %lld-point children, in place] ",
-                      (long long)(N1 / 16), (long long)(N2 / 16));
+                      "phase3 radix-%lld; pass3: phase3 %lld-point children, in place] ",
+                      (long long)(N1 / 16), (long long)r2, (long long)(N2 / r2));
         desc = buf + desc;
     }
     if (P->two_pass) {

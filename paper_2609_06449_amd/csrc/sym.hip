@@ -349,8 +349,8 @@ __global__ __launch_bounds__(1 << LL) __attribute__((amdgpu_waves_per_eu(4))) vo
 // ka) = (tid & 15, (tid >> 4) & (P-1), tid >> (4 + log2 P)): column fastest,
 // for the 128-byte runs of the rows it stores; a half-wave of stage-B loads
 // (16 cl x 2 jp) is 32 consecutive items of one plane, so the planes need no
-// padding.
-template <int LL>
+// padding.  R = 2^LR: the radix of pass 2's Phase III child (rows R t + q0).
+template <int LL, int LR>
 __global__ __launch_bounds__(1 << LL) __attribute__((amdgpu_waves_per_eu(4))) void sym_last_long_kernel(SymPass P,
                                                                                                        uint32_t tiles)
 {
@@ -362,9 +362,9 @@ __global__ __launch_bounds__(1 << LL) __attribute__((amdgpu_waves_per_eu(4))) vo
     uint32_t t = blockIdx.x;
     float2 v[16];
     auto load = [&](uint32_t tile) {
-        const uint32_t base = addr::sym3_load_base(N1, addr::sym3_block(tile, N1, LL), tid);
+        const uint32_t base = addr::sym3r_load_base(N1, addr::sym3r_block(tile, N1, LL, LR), tid, LR);
 #pragma unroll
-        for (int jh = 0; jh < 16; ++jh) v[jh] = *off32(P.src, base + addr::sym3_load_off(N1, jh, LL));
+        for (int jh = 0; jh < 16; ++jh) v[jh] = *off32(P.src, base + addr::sym3r_load_off(N1, jh, LL, LR));
     };
     auto stage_a = [&](uint32_t tc) {
         const uint32_t jl = opaque(uint32_t(tid)) >> 4;
@@ -381,7 +381,7 @@ __global__ __launch_bounds__(1 << LL) __attribute__((amdgpu_waves_per_eu(4))) vo
     __syncthreads();
     if (t < tiles) stage_a(t);
     while (t < tiles) {
-        const uint32_t blk = addr::sym3_block(t, N1, LL);
+        const uint32_t blk = addr::sym3r_block(t, N1, LL, LR);
         const uint32_t tt = opaque(uint32_t(tid));
         const uint32_t jp = (tt >> 4) & (PP - 1), ka = tt >> (LL - 4);
         float2 u[16], tb[16];
@@ -390,19 +390,74 @@ __global__ __launch_bounds__(1 << LL) __attribute__((amdgpu_waves_per_eu(4))) vo
 #pragma unroll
         for (int k = 1; k < 16; ++k) tb[k] = twL[((jp * k) << 4) & (L - 1)];
         stage_b<PP>(u, tb, int(jp));
-        const uint32_t dbase = addr::sym3_store_base(N1, blk, tid, LL);
+        const uint32_t dbase = addr::sym3r_store_base(N1, blk, tid, LL, LR);
 #pragma unroll
         for (int i = 0; i < 16; ++i)
-            *off32(P.dst, dbase + addr::sym3_store_off(N1, i)) = P.out_scale != 0.f ? conj_scale(u[i], P.out_scale) : u[i];
+            *off32(P.dst, dbase + addr::sym3r_store_off(N1, i, LR)) =
+                P.out_scale != 0.f ? conj_scale(u[i], P.out_scale) : u[i];
         __syncthreads();
         t += gridDim.x;
         if (t < tiles) stage_a(t);
     }
 }
 
-bool sym_shape_ok(const SymPass &p, int &ll1, int &ll2)
+// Pass 2 of the wide form (N2 = 32 L2, L2 = 2^LL2): Phase III's child in
+// this pass has 32 points, j2 = jc + L2 rr, k2 = q0 + 32 q (rr, q0 < 32).
+// Workgroup (jc, kb) owns k = 16 kb + kk and the columns c = jc + L2 rr:
+// thread (kk, rr) of 512 reads U[c][r][k] (r < 16), transforms over r (-> s,
+// v = k + L1 s) and applies w_N^{-v c} = w_N^{-k c} w_{16 N2}^{-s jc}
+// w_512^{-s rr} (N = 512 L1 L2); thread (kk, p, s) then transforms over
+// rr = p + 2 m: radix 16 over m, twiddle w_32^{-p i}, radix 2 with the
+// thread 16 lanes away (stage_b), keeping q0 = i + 16 p; applies
+// w_N2^{-q0 jc} and stores W at row 32 jc + q0, columns v (four 128-byte runs
+// per instruction).  The exchange buffer is [s][rr][kk] (64 KiB): each
+// half-wave writes and reads 32 consecutive items.
+template <int LL1, int LL2>
+__global__ __launch_bounds__(512) void sym_middle_wide_kernel(SymPass P)
 {
-    return sym_children(p, ll1, ll2) && p.src && p.dst && p.tw && p.tw_hi && p.tw_lo && p.tw_sj;
+    __shared__ float2 lds[16 * 512];
+    const int tid = threadIdx.x;
+    const uint32_t N1 = uint32_t(P.N1), N2 = uint32_t(P.N2);
+    const uint32_t blk = addr::sym2_block(blockIdx.x, LL1, LL2);
+    const uint32_t kb = blk & ((1u << (LL1 - 4)) - 1u), jc = blk >> (LL1 - 4);
+    const int kk = tid & 15, rr = tid >> 4;
+    const uint32_t c = jc + (uint32_t(rr) << LL2), k = 16u * kb + kk;
+    float2 v[16];
+    const float2 *src = P.src + addr::sym2_load_base(N2, blk, tid, LL1, LL2);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = ld2_last(src + addr::sym2_load_off(r));  // last use
+    const uint32_t nmask = uint32_t((uint64_t(1) << P.log2N) - 1), lomask = (1u << P.log2Lo) - 1u;
+    const uint32_t e1 = (k * c) & nmask;
+    const float2 h1 = P.tw_hi[e1 >> P.log2Lo], l1 = P.tw_lo[e1 & lomask];
+    float2 t2[16], t3[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        t2[s] = P.tw_sj[(s << (LL2 + 1)) + jc];                // w_{16 N2}^{-s jc} (row stride N2/16)
+        t3[s] = root_of(P.tw, P.log2L, 9, uint32_t(s * rr));  // w_512^{-s rr}
+    }
+    dft_regs<4>(v);
+    const float2 t1 = cmul(h1, l1);
+#pragma unroll
+    for (int s = 0; s < 16; ++s) lds[s * 512 + rr * 16 + kk] = cmul(v[s], cmul(t1, cmul(t2[s], t3[s])));
+    __syncthreads();
+    const int p = (tid >> 4) & 1, s2 = tid >> 5;
+    float2 tb[16], t4[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) v[m] = lds[s2 * 512 + (p + 2 * m) * 16 + kk];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        tb[i] = root_of(P.tw, P.log2L, 5, uint32_t(p * i));                     // w_32^{-p i}
+        t4[i] = root_of(P.tw, P.log2L, LL2 + 5, uint32_t(i + 16 * p) * jc);  // w_N2^{-q0 jc}
+    }
+    stage_b<2>(v, tb, p);
+    float2 *dst = P.dst + addr::sym2w_store_base(N1, blk, tid, LL1);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) dst[addr::sym2w_store_off(N1, i)] = cmul(v[i], t4[i]);
+}
+
+bool sym_shape_ok(const SymPass &p, int &ll1, int &ll2, int &lr2)
+{
+    return sym_children(p, ll1, ll2, lr2) && p.src && p.dst && p.tw && p.tw_hi && p.tw_lo && p.tw_sj;
 }
 
 int log2_child(int64_t n) { return n == 4096 ? 8 : n == 8192 ? 9 : n == 16384 ? 10 : 0; }
@@ -420,34 +475,45 @@ void launch_middle(int ll2, dim3 grid, const SymPass &p, hipStream_t s)
 
 }  // namespace
 
-bool sym_children(const SymPass &p, int &ll1, int &ll2)
+bool sym_children(const SymPass &p, int &ll1, int &ll2, int &lr2)
 {
     ll1 = log2_child(p.N1);
-    ll2 = log2_child(p.N2);
-    return ll1 && ll2 && p.log2L >= (ll1 > ll2 ? ll1 : ll2) + 4 && p.log2N == ll1 + ll2 + 8;
+    const bool wide = p.N2 == 32768 && (ll1 == 8 || ll1 == 9);
+    ll2 = wide ? 10 : log2_child(p.N2);
+    lr2 = wide ? 5 : 4;
+    const int lmax = ll1 + 4 > ll2 + lr2 ? ll1 + 4 : ll2 + lr2;
+    return ll1 && ll2 && p.log2L >= lmax && p.log2N == ll1 + 4 + ll2 + lr2;
 }
 
 int sym_log2_child(const SymPass &p)
 {
-    int ll1 = 0, ll2 = 0;
-    return sym_children(p, ll1, ll2) && ll1 == ll2 ? ll1 : 0;
+    int ll1 = 0, ll2 = 0, lr2 = 0;
+    return sym_children(p, ll1, ll2, lr2) && ll1 == ll2 && lr2 == 4 ? ll1 : 0;
 }
 
 uint32_t sym_resident_groups(int pass, const SymPass &p)
 {
-    int ll1 = 0, ll2 = 0;
-    if (!sym_children(p, ll1, ll2)) return 0;
-    switch (pass == 1 ? ll1 : ll2) {
-    case 9: return pass == 1 ? resident(sym_first_long_kernel<true, 9>, 512) : resident(sym_last_long_kernel<9>, 512);
-    case 10: return pass == 1 ? resident(sym_first_long_kernel<true, 10>, 1024) : resident(sym_last_long_kernel<10>, 1024);
+    int ll1 = 0, ll2 = 0, lr2 = 0;
+    if (!sym_children(p, ll1, ll2, lr2)) return 0;
+    if (pass == 1) {
+        switch (ll1) {
+        case 9: return resident(sym_first_long_kernel<true, 9>, 512);
+        case 10: return resident(sym_first_long_kernel<true, 10>, 1024);
+        default: return 0;
+        }
+    }
+    if (lr2 == 5) return resident(sym_last_long_kernel<10, 5>, 1024);
+    switch (ll2) {
+    case 9: return resident(sym_last_long_kernel<9, 4>, 512);
+    case 10: return resident(sym_last_long_kernel<10, 4>, 1024);
     default: return 0;
     }
 }
 
 hipError_t launch_sym_first(const SymPass &p, hipStream_t s)
 {
-    int ll1 = 0, ll2 = 0;
-    if (!sym_shape_ok(p, ll1, ll2)) return hipErrorInvalidValue;
+    int ll1 = 0, ll2 = 0, lr2 = 0;
+    if (!sym_shape_ok(p, ll1, ll2, lr2)) return hipErrorInvalidValue;
     const dim3 grid(addr::sym1_groups(uint32_t(p.N2)));
     switch (ll1) {
     case 8: hipLaunchKernelGGL(sym_first_kernel<true>, grid, dim3(kSymThreads), 0, s, p); break;
@@ -459,8 +525,16 @@ hipError_t launch_sym_first(const SymPass &p, hipStream_t s)
 
 hipError_t launch_sym_middle(const SymPass &p, hipStream_t s)
 {
-    int ll1 = 0, ll2 = 0;
-    if (!sym_shape_ok(p, ll1, ll2)) return hipErrorInvalidValue;
+    int ll1 = 0, ll2 = 0, lr2 = 0;
+    if (!sym_shape_ok(p, ll1, ll2, lr2)) return hipErrorInvalidValue;
+    if (lr2 == 5) {
+        const dim3 grid(addr::sym2w_groups(uint32_t(p.N1), uint32_t(p.N2)));
+        if (ll1 == 8)
+            hipLaunchKernelGGL((sym_middle_wide_kernel<8, 10>), grid, dim3(512), 0, s, p);
+        else
+            hipLaunchKernelGGL((sym_middle_wide_kernel<9, 10>), grid, dim3(512), 0, s, p);
+        return hipGetLastError();
+    }
     const dim3 grid(addr::sym2_groups(uint32_t(p.N1), uint32_t(p.N2)));
     switch (ll1) {
     case 8: launch_middle<8>(ll2, grid, p, s); break;
@@ -472,13 +546,18 @@ hipError_t launch_sym_middle(const SymPass &p, hipStream_t s)
 
 hipError_t launch_sym_last(const SymPass &p, hipStream_t s)
 {
-    int ll1 = 0, ll2 = 0;
-    if (!sym_shape_ok(p, ll1, ll2)) return hipErrorInvalidValue;
+    int ll1 = 0, ll2 = 0, lr2 = 0;
+    if (!sym_shape_ok(p, ll1, ll2, lr2)) return hipErrorInvalidValue;
+    if (lr2 == 5) {
+        const dim3 grid(addr::sym3r_groups(uint32_t(p.N1), 5));
+        hipLaunchKernelGGL((sym_last_long_kernel<10, 5>), persistent(grid, p.resident3), dim3(1024), 0, s, p, grid.x);
+        return hipGetLastError();
+    }
     const dim3 grid(addr::sym3_groups(uint32_t(p.N1)));
     switch (ll2) {
     case 8: hipLaunchKernelGGL(sym_last_kernel, grid, dim3(kSymThreads), 0, s, p); break;
-    case 9: hipLaunchKernelGGL(sym_last_long_kernel<9>, persistent(grid, p.resident3), dim3(512), 0, s, p, grid.x); break;
-    default: hipLaunchKernelGGL(sym_last_long_kernel<10>, persistent(grid, p.resident3), dim3(1024), 0, s, p, grid.x); break;
+    case 9: hipLaunchKernelGGL((sym_last_long_kernel<9, 4>), persistent(grid, p.resident3), dim3(512), 0, s, p, grid.x); break;
+    default: hipLaunchKernelGGL((sym_last_long_kernel<10, 4>), persistent(grid, p.resident3), dim3(1024), 0, s, p, grid.x); break;
     }
     return hipGetLastError();
 }

@@ -66,11 +66,16 @@ uint32_t item(uint32_t base, uint32_t off, uint64_t N, const char *what)
     return uint32_t(exact);
 }
 
-// N1 = N2 = 16 L, L = 2^ll: L threads per workgroup in passes 1 and 3, 256 in pass 2
-void audit_sym(uint32_t ll1, uint32_t ll2)
+// N1 = 16 L1, N2 = R L2 (L1 = 2^ll1, L2 = 2^ll2, R = 2^lr: 16, or 32 in the
+// wide form): L1 (L2) threads per workgroup in pass 1 (3), 16 R in pass 2.
+// The pass-3 maps of the persistent kernels (sym3r_, L2 >= 512) are checked
+// for every R, and for R = 16 also against the sym3_ maps the L = 256 and
+// MFMA kernels use, item by item.
+void audit_sym(uint32_t ll1, uint32_t ll2, uint32_t lr = 4)
 {
-    const uint32_t N1 = 16u << ll1, N2 = 16u << ll2, T1 = 1u << ll1, T3 = 1u << ll2;
+    const uint32_t R = 1u << lr, N1 = 16u << ll1, N2 = R << ll2, T1 = 1u << ll1, T3 = 1u << ll2;
     const uint64_t N = uint64_t(N1) * N2;
+    const bool wide = lr == 5;
     {
         Cover rd(N), wr(N), blocks(addr::sym1_groups(N2));
         for (uint32_t g = 0; g < addr::sym1_groups(N2); ++g) {
@@ -88,37 +93,58 @@ void audit_sym(uint32_t ll1, uint32_t ll2)
         CHECK(rd.exact() && wr.exact(), "sym pass 1 is not a permutation (%u x %u)", N1, N2);
     }
     {
-        Cover rd(N), wr(N), blocks(addr::sym2_groups(N1, N2));
-        for (uint32_t g = 0; g < addr::sym2_groups(N1, N2); ++g) {
+        const uint32_t groups = wide ? addr::sym2w_groups(N1, N2) : addr::sym2_groups(N1, N2);
+        Cover rd(N), wr(N), blocks(groups);
+        for (uint32_t g = 0; g < groups; ++g) {
             const uint32_t blk = addr::sym2_block(g, ll1, ll2);
-            CHECK(blk < addr::sym2_groups(N1, N2), "sym pass 2 block id out of range");
+            CHECK(blk < groups, "sym pass 2 block id out of range");
             blocks.hit(blk);
-            for (uint32_t tid = 0; tid < 256; ++tid)
+            for (uint32_t tid = 0; tid < 16 * R; ++tid)
                 for (uint32_t i = 0; i < 16; ++i) {
                     rd.hit(item(addr::sym2_load_base(N2, blk, tid, ll1, ll2), addr::sym2_load_off(i), N,
                                 "sym pass 2 load"));
-                    wr.hit(item(addr::sym2_store_base(N1, blk, tid, ll1), addr::sym2_store_off(N1, i), N,
-                                "sym pass 2 store"));
+                    wr.hit(wide ? item(addr::sym2w_store_base(N1, blk, tid, ll1), addr::sym2w_store_off(N1, i), N,
+                                       "sym pass 2 store")
+                                : item(addr::sym2_store_base(N1, blk, tid, ll1), addr::sym2_store_off(N1, i), N,
+                                       "sym pass 2 store"));
                 }
         }
         CHECK(blocks.exact(), "sym pass 2 block order is not a permutation (%u x %u)", N1, N2);
         CHECK(rd.exact() && wr.exact(), "sym pass 2 is not a permutation (%u x %u)", N1, N2);
     }
-    {
-        Cover rd(N), wr(N), blocks(addr::sym3_groups(N1));
+    for (int maps = wide ? 1 : 0; maps < (ll2 < 9 ? 1 : 2); ++maps) {  // 0: sym3_, 1: sym3r_ (L2 >= 512)
+        const bool r = maps == 1;
+        const uint32_t groups = r ? addr::sym3r_groups(N1, lr) : addr::sym3_groups(N1);
+        Cover rd(N), wr(N), blocks(groups);
         std::vector<uint32_t> a, b;
-        for (uint32_t g = 0; g < addr::sym3_groups(N1); ++g) {
-            const uint32_t blk = addr::sym3_block(g, N1, ll2);
-            CHECK(blk < addr::sym3_groups(N1), "sym pass 3 block id out of range");
+        for (uint32_t g = 0; g < groups; ++g) {
+            const uint32_t blk = r ? addr::sym3r_block(g, N1, ll2, lr) : addr::sym3_block(g, N1, ll2);
+            CHECK(blk < groups, "sym pass 3 block id out of range");
             blocks.hit(blk);
             a.clear();
             b.clear();
             for (uint32_t tid = 0; tid < T3; ++tid)
                 for (uint32_t i = 0; i < 16; ++i) {
-                    a.push_back(item(addr::sym3_load_base(N1, blk, tid), addr::sym3_load_off(N1, i, ll2), N,
-                                     "sym pass 3 load"));
-                    b.push_back(item(addr::sym3_store_base(N1, blk, tid, ll2), addr::sym3_store_off(N1, i), N,
-                                     "sym pass 3 store"));
+                    const uint32_t ld =
+                        r ? item(addr::sym3r_load_base(N1, blk, tid, lr), addr::sym3r_load_off(N1, i, ll2, lr), N,
+                                 "sym pass 3 load")
+                          : item(addr::sym3_load_base(N1, blk, tid), addr::sym3_load_off(N1, i, ll2), N,
+                                 "sym pass 3 load");
+                    const uint32_t st =
+                        r ? item(addr::sym3r_store_base(N1, blk, tid, ll2, lr), addr::sym3r_store_off(N1, i, lr), N,
+                                 "sym pass 3 store")
+                          : item(addr::sym3_store_base(N1, blk, tid, ll2), addr::sym3_store_off(N1, i), N,
+                                 "sym pass 3 store");
+                    if (r && !wide) {
+                        CHECK(addr::sym3r_block(g, N1, ll2, lr) == addr::sym3_block(g, N1, ll2) &&
+                                  ld == item(addr::sym3_load_base(N1, blk, tid), addr::sym3_load_off(N1, i, ll2), N,
+                                             "sym pass 3 load") &&
+                                  st == item(addr::sym3_store_base(N1, blk, tid, ll2), addr::sym3_store_off(N1, i), N,
+                                             "sym pass 3 store"),
+                              "sym pass 3: the R = 16 maps differ from sym3_ (%u x %u)", N1, N2);
+                    }
+                    a.push_back(ld);
+                    b.push_back(st);
                 }
             for (uint32_t x : a) rd.hit(x);
             for (uint32_t x : b) wr.hit(x);
@@ -129,8 +155,9 @@ void audit_sym(uint32_t ll1, uint32_t ll2)
         CHECK(blocks.exact(), "sym pass 3 block order is not a permutation (%u x %u)", N1, N2);
         CHECK(rd.exact() && wr.exact(), "sym pass 3 is not a permutation (%u x %u)", N1, N2);
     }
-    std::printf("ok symmetric split form %u x %u: three passes are permutations, pass 3 in place per workgroup\n", N1,
-                N2);
+    std::printf("ok symmetric split form %u x %u (pass-2 Phase III radix %u): three passes are permutations, "
+                "pass 3 in place per workgroup\n",
+                N1, N2, R);
 }
 
 // the split form of Phase I for N1 = 16 M, every pass over every workgroup;
@@ -336,6 +363,7 @@ int main(int argc, char **argv)
     audit_sym(9, 9);
     audit_sym(8, 9);
     audit_sym(9, 8);
+    audit_sym(8, 10, 5);  // 4096 x 32768, the wide form
     audit_mf_exchange("pass 1", addr::kMf1Items, addr::mf1_store, addr::mf1_load, true, addr::kMf1Spare);
     audit_mf_exchange("pass 2", 16 * 256, addr::mf2_store, addr::mf2_load, false, -1);
     audit_mf_exchange("pass 3", addr::kMf1Items, addr::mf3_store, addr::mf3_load, false, addr::kMf3Spare);
@@ -353,6 +381,7 @@ int main(int argc, char **argv)
         audit_sym(10, 8);
         audit_sym(9, 10);
         audit_sym(10, 9);
+        audit_sym(9, 10, 5);  // 8192 x 32768
         audit_split(16384, 16384, 2, false);
         audit_split(16384, 16384, 4, true);
         audit_split(8192, 32768, 1, false);

@@ -3,7 +3,7 @@
 * N = 2^28 (2 GiB per complex64 buffer) in all four shapes the benchmark
   times: 16384 x 16384 with b = 4 and with its literal base b = 16 (mixed
   radix), 8192 x 32768 with b = 2 and with its literal base b = 8 (mixed
-  radix).  Every one of the 2^28 outputs is compared with the oracle's
+  radix); the last also in the long-column split form (PACO_PLAN_NO_SYM).  Every one of the 2^28 outputs is compared with the oracle's
   recursive radix-2 FFT (run on all host cores, bit-identical to its one-thread
   form) at the same rel-L2 bound as up to 2^24 (1e-6: an FP32 FFT's error grows
   like sqrt(log N), sqrt(28/24) ~ 1.08).  The inverse of each shape is then
@@ -60,14 +60,18 @@ def _reference(cfg):
     return _CACHE[key]
 
 
-@pytest.mark.parametrize("name", ["n2p28_16384x16384_b4", "n2p28_16384x16384_b16", "n2p28_8192x32768_b2",
-                                  "n2p28_8192x32768_b8"])
-def test_2p28_complete_output_against_oracle(name):
+# (the default plans run the symmetric split form, 8192 x 32768 its wide form;
+# the last case keeps the long-column split form, which the other dtypes and
+# PACO_PLAN_NO_SYM take, checked at full size)
+@pytest.mark.parametrize("name,flags", [("n2p28_16384x16384_b4", 0), ("n2p28_16384x16384_b16", 0),
+                                        ("n2p28_8192x32768_b2", 0), ("n2p28_8192x32768_b8", 0),
+                                        ("n2p28_8192x32768_b8", paco.PACO_PLAN_NO_SYM)])
+def test_2p28_complete_output_against_oracle(name, flags):
     cfg = inputs.CONFIGS[name]
     N1, N2, p, b = cfg["N1"], cfg["N2"], cfg["p"], cfg["b"]
     mixed = paco.paco_plan_validate(N1, N2, p, b) != paco.PACO_OK
     x, ref = _reference(cfg)
-    plan = paco.Plan(N1, N2, p, b, mixed=mixed)
+    plan = paco.Plan(N1, N2, p, b, mixed=mixed, flags=flags)
     print(f"{name}: {plan.description}", flush=True)
     yd = _call(plan.execute, plan, _dev(x))
     y = yd.cpu().numpy()

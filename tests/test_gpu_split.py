@@ -231,14 +231,17 @@ def test_which_plans_split():
     assert paco.Plan(4096, 16384, 64, 4).has_split == 2
     assert paco.Plan(4096, 16384, 64, 4, flags=paco.PACO_PLAN_NO_SYM).has_split == 1
     assert paco.Plan(4096, 16384, 64, 4, paco.PACO_C64_MFMA_FP16X3).has_split != 2  # FP32 only there
-    assert not paco.Plan(4096, 32768, 64, 2).has_split        # N2 above 2^14: not measured, the packed form
+    assert paco.Plan(4096, 32768, 64, 2).has_split == 2                        # the wide symmetric form
+    # N2 above 2^14 outside the symmetric forms: not measured, the packed form
+    assert not paco.Plan(4096, 32768, 64, 2, flags=paco.PACO_PLAN_NO_SYM).has_split
     assert paco.Plan(16384, 64, 4, 4).has_split and paco.Plan(8192, 64, 4, 2).has_split
     # launches paco_execute makes: pass 1, pass 2 and Phase III's passes
     assert paco.Plan(4096, 4096, 64, 16).launches == 3
     assert paco.Plan(16384, 64, 4, 4).launches == 3
     assert paco.Plan(16384, 16384, 256, 4).launches == 3                     # the symmetric split form
     assert paco.Plan(16384, 16384, 256, 4, flags=paco.PACO_PLAN_NO_SYM).launches == 4
-    assert paco.Plan(8192, 32768, 128, 2).launches == 4                      # not square: long-column split
+    assert paco.Plan(8192, 32768, 128, 2).launches == 3                      # the wide symmetric form
+    assert paco.Plan(8192, 32768, 128, 2, flags=paco.PACO_PLAN_NO_SYM).launches == 4  # long-column split
     assert not paco.Plan(16384, 32, 2, 2).has_split           # N2 below 64
     assert not paco.Plan(16384, 64, 4, 4, paco.PACO_C64_MFMA_FP16X3).has_split
     assert not paco.Plan(4096, 256, 16, 16, paco.PACO_C64_MFMA_BF16X3).has_split  # FP32 only

@@ -4,10 +4,14 @@ children of Phase I over the N2 columns, pass 2 both 16-point children with
 the top-level twiddle (w_N^{-v c} split as w_N^{-k c} w_{16 N2}^{-s jc}
 w_256^{-s rr}, which holds for any L1, L2 because N / L1 = 16 N2 and
 16 N2 / L2 = 256), pass 3 the L2-point children of Phase III over the N1
-columns.  Every output against the FP64 oracle, for both orientations of
-each pair of sides up to 2^27 items; the inverse (whose passes are the
-N2 x N1 plan's); the stage hooks composing to paco_execute bit for bit; and
-the plan choice (the split MFMA forms keep their own plan on these shapes)."""
+columns.  The wide form N2 = 2^15 = 32 L2 (L2 = 1024; N1 = 2^12 here, 2^13
+in the full-size tests) gives pass 2 a 32-point Phase III child instead
+(w_N^{-v c} = w_N^{-k c} w_{16 N2}^{-s jc} w_512^{-s rr}, rr < 32) and
+pass 3 the rows 32 t + q0.  Every output against the FP64 oracle, for both
+orientations of each pair of sides up to 2^27 items; the inverse (whose
+passes are the N2 x N1 plan's); the stage hooks composing to paco_execute
+bit for bit; and the plan choice (the split MFMA forms keep their own plan
+on these shapes)."""
 
 import numpy as np
 import pytest
@@ -22,7 +26,7 @@ TOL = 1e-6
 
 # (N1, N2, p, b): b = 2 or 4 so that both sides are powers of it
 SHAPES = [(4096, 8192, 64, 2), (8192, 4096, 64, 2), (4096, 16384, 64, 4), (16384, 4096, 64, 4),
-          (8192, 16384, 128, 2), (16384, 8192, 128, 2)]
+          (8192, 16384, 128, 2), (16384, 8192, 128, 2), (4096, 32768, 64, 8)]
 
 
 def _stream() -> int:
@@ -66,8 +70,9 @@ def _x_and_reference(n: int):
 @pytest.mark.parametrize("N1,N2,p,b", SHAPES)
 def test_plan_takes_the_symmetric_form(N1, N2, p, b):
     plan = paco.Plan(N1, N2, p, b)
+    r2 = 32 if N2 == 32768 else 16  # the radix of pass 2's Phase III child
     assert plan.description.startswith(f"sym[pass1: phase1 {N1 // 16}-point children"), plan.description
-    assert f"pass3: phase3 {N2 // 16}-point children" in plan.description
+    assert f"phase3 radix-{r2}; pass3: phase3 {N2 // r2}-point children" in plan.description
     assert plan.launches == 3 and plan.has_split == 2
     plan.close()
     for dt in (paco.PACO_C64_MFMA_FP16X3, paco.PACO_C64_MFMA_BF16X6):  # FP32 only on these shapes
@@ -102,7 +107,7 @@ def test_inverse_of_the_oracle_output(N1, N2, p, b):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("N1,N2,p,b", [(8192, 4096, 64, 2), (4096, 16384, 64, 4)])
+@pytest.mark.parametrize("N1,N2,p,b", [(8192, 4096, 64, 2), (4096, 16384, 64, 4), (4096, 32768, 64, 8)])
 def test_stage_hooks_compose_to_execute_and_in_place(N1, N2, p, b):
     x = inputs.normal(N1 * N2, seed=12)
     xd = _dev(x)
