@@ -205,8 +205,13 @@ paco_status paco_plan_workspace_size(const paco_plan *plan, size_t *bytes);
  * so that every pass reads and writes whole 128-byte lines; the paper's
  * digit reversals cancel between the redistribution and Phase III's input
  * layout, as in the packed form.  Three HBM passes, the same workspace and
- * out.  paco_plan_has_split reports 2; the option PACO_PLAN_NO_SYM keeps the
- * split form of Phase I alone. */
+ * out.  In PACO_C64 the wide variant takes N2 = 2^15 = 32 L2 (L2 = 1024)
+ * with N1 = 2^12 or 2^13: Phase III splits as j2 = jc + L2 rr, k2 = q0 +
+ * 32 q (rr, q0 < 32), pass 2 stores W at out[(32 jc + q0)*N1 + v] after a
+ * 32-point transform over rr, and pass 3 transforms rows 32 t + q0 into
+ * out[(q0 + 32 q)*N1 + v]; pass 1 is the same.  paco_plan_has_split
+ * reports 2; the option PACO_PLAN_NO_SYM keeps the split form of Phase I
+ * alone. */
 paco_status paco_execute(const paco_plan *plan, const void *in, void *out, void *workspace,
                          size_t workspace_bytes, void *stream);
 
