@@ -201,6 +201,7 @@ struct SymPass {
     float out_scale;              // pass 3: nonzero stores conj(y) * out_scale (the inverse's output map)
     uint32_t resident1, resident3;  // passes 1 and 3 at L >= 512: workgroups of their persistent launches
                                     // (sym_resident_groups; 0: one per tile)
+    uint32_t resident2;             // pass 2 of the wide form (N2 = 2^15), likewise
 };
 
 // Workgroup geometry a local pass is launched with.
@@ -254,8 +255,9 @@ bool sym_children(const SymPass &p, int &ll1, int &ll2, int &lr2);
 // split MFMA forms run L = 256 and 512), else 0
 int sym_log2_child(const SymPass &p);
 // Workgroups the current device holds at once of the persistent pass-1 or
-// pass-3 kernel of p's shape (L >= 512), 0 for L = 256 or if the runtime does
-// not say; the MFMA forms' kernels: sym_mf_resident_groups.
+// pass-3 kernel of p's shape (L >= 512) or of the wide form's pass 2, 0 for
+// the other passes or if the runtime does not say; the MFMA forms' kernels:
+// sym_mf_resident_groups.
 uint32_t sym_resident_groups(int pass, const SymPass &p);
 uint32_t sym_mf_resident_groups(int prec, int pass, const SymPass &p);
 hipError_t launch_sym_first(const SymPass &p, hipStream_t s);

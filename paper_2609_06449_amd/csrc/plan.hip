@@ -553,6 +553,7 @@ paco_status create_impl(paco_plan **plan, int64_t N1, int64_t N2, int64_t p, int
         // passes 1 and 3 at L >= 512: one workgroup per resident slot
         q.resident1 = dt == PACO_C64 ? paco::sym_resident_groups(1, q) : paco::sym_mf_resident_groups(int(dt), 1, q);
         q.resident3 = dt == PACO_C64 ? paco::sym_resident_groups(3, q) : paco::sym_mf_resident_groups(int(dt), 3, q);
+        q.resident2 = dt == PACO_C64 ? paco::sym_resident_groups(2, q) : 0;
         P->sym = true;
     }
 

@@ -403,56 +403,82 @@ __global__ __launch_bounds__(1 << LL) __attribute__((amdgpu_waves_per_eu(4))) vo
 
 // Pass 2 of the wide form (N2 = 32 L2, L2 = 2^LL2): Phase III's child in
 // this pass has 32 points, j2 = jc + L2 rr, k2 = q0 + 32 q (rr, q0 < 32).
-// Workgroup (jc, kb) owns k = 16 kb + kk and the columns c = jc + L2 rr:
-// thread (kk, rr) of 512 reads U[c][r][k] (r < 16), transforms over r (-> s,
-// v = k + L1 s) and applies w_N^{-v c} = w_N^{-k c} w_{16 N2}^{-s jc}
-// w_512^{-s rr} (N = 512 L1 L2); thread (kk, p, s) then transforms over
-// rr = p + 2 m: radix 16 over m, twiddle w_32^{-p i}, radix 2 with the
-// thread 16 lanes away (stage_b), keeping q0 = i + 16 p; applies
-// w_N2^{-q0 jc} and stores W at row 32 jc + q0, columns v (four 128-byte runs
-// per instruction).  The exchange buffer is [s][rr][kk] (64 KiB): each
-// half-wave writes and reads 32 consecutive items.
+// Tile (jc, kb) owns k = 16 kb + kk and the columns c = jc + L2 rr: thread
+// (kk, rr) of 512 reads U[c][r][k] (r < 16), transforms over r (-> s,
+// v = k + L1 s) and applies w_N^{-k c} w_512^{-s rr}; thread (kk, p, s) then
+// transforms over rr = p + 2 m: radix 16 over m, twiddle w_32^{-p i}, radix 2
+// with the thread 16 lanes away (stage_b), keeping q0 = i + 16 p, and
+// applies w_{16 N2}^{-s jc} w_N2^{-q0 jc} (the first factor, the same for
+// all rr of the thread's transform, moved past it; together with the
+// others it is w_N^{-v c} w_N2^{-q0 jc}, N = 512 L1 L2).  W goes to row
+// 32 jc + q0, columns v (four 128-byte runs per instruction).  The exchange
+// buffer is [s][rr][kk] (64 KiB: each half-wave writes and reads 32
+// consecutive items), so two workgroups fit on a CU; they run persistent
+// and pipelined like passes 1 and 3 at L >= 512, issuing the next tile's
+// loads after stage A.  The factors that depend on the tile's jc (16 of
+// w_{16 N2}, 32 of w_N2) are loaded by threads 0..47 with that tile's data
+// and pass through LDS; w_512 sits in LDS for the whole launch.
 template <int LL1, int LL2>
-__global__ __launch_bounds__(512) void sym_middle_wide_kernel(SymPass P)
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void sym_middle_wide_kernel(SymPass P,
+                                                                                                     uint32_t tiles)
 {
     __shared__ float2 lds[16 * 512];
-    const int tid = threadIdx.x;
+    __shared__ float2 tw512[512];  // w_512^{-m}
+    __shared__ float2 tjc[48];     // the current tile's w_{16 N2}^{-s jc} (s < 16), w_N2^{-q0 jc} (q0 < 32)
+    const int tid = threadIdx.x, kk = tid & 15;
     const uint32_t N1 = uint32_t(P.N1), N2 = uint32_t(P.N2);
-    const uint32_t blk = addr::sym2_block(blockIdx.x, LL1, LL2);
-    const uint32_t kb = blk & ((1u << (LL1 - 4)) - 1u), jc = blk >> (LL1 - 4);
-    const int kk = tid & 15, rr = tid >> 4;
-    const uint32_t c = jc + (uint32_t(rr) << LL2), k = 16u * kb + kk;
-    float2 v[16];
-    const float2 *src = P.src + addr::sym2_load_base(N2, blk, tid, LL1, LL2);
-#pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = ld2_last(src + addr::sym2_load_off(r));  // last use
     const uint32_t nmask = uint32_t((uint64_t(1) << P.log2N) - 1), lomask = (1u << P.log2Lo) - 1u;
-    const uint32_t e1 = (k * c) & nmask;
-    const float2 h1 = P.tw_hi[e1 >> P.log2Lo], l1 = P.tw_lo[e1 & lomask];
-    float2 t2[16], t3[16];
+    uint32_t t = blockIdx.x;
+    float2 v[16], h1, l1, tu;
+    auto load = [&](uint32_t tile) {
+        const uint32_t blk = addr::sym2_block(tile, LL1, LL2);
+        const uint32_t kb = blk & ((1u << (LL1 - 4)) - 1u), jc = blk >> (LL1 - 4);
+        const uint32_t c = jc + ((uint32_t(tid) >> 4) << LL2), k = 16u * kb + kk;
+        const uint32_t e1 = (k * c) & nmask;
+        // threads 48.. repeat the loads of 16..47 (no branch in the loop)
+        const uint32_t u = tid < 16 ? uint32_t(tid) : 16u + ((uint32_t(tid) - 16u) & 31u);
+        tu = u < 16 ? P.tw_sj[(u << (LL2 + 1)) + jc] : root_of(P.tw, P.log2L, LL2 + 5, (u - 16u) * jc);
+        h1 = P.tw_hi[e1 >> P.log2Lo];
+        l1 = P.tw_lo[e1 & lomask];
+        const uint32_t base = addr::sym2_load_base(N2, blk, tid, LL1, LL2);
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
-        t2[s] = P.tw_sj[(s << (LL2 + 1)) + jc];                // w_{16 N2}^{-s jc} (row stride N2/16)
-        t3[s] = root_of(P.tw, P.log2L, 9, uint32_t(s * rr));  // w_512^{-s rr}
-    }
-    dft_regs<4>(v);
-    const float2 t1 = cmul(h1, l1);
+        for (int r = 0; r < 16; ++r) v[r] = ld2_last(off32(P.src, base + addr::sym2_load_off(r)));  // last use
+    };
+    // stage A of tile tc into the exchange buffer, then the next tile's loads
+    auto stage_a = [&](uint32_t tc) {
+        const uint32_t rr = opaque(uint32_t(tid)) >> 4;
+        if (tid < 48) tjc[tid] = tu;
+        dft_regs<4>(v);
+        const float2 t1 = cmul(h1, l1);  // w_N^{-k c}
 #pragma unroll
-    for (int s = 0; s < 16; ++s) lds[s * 512 + rr * 16 + kk] = cmul(v[s], cmul(t1, cmul(t2[s], t3[s])));
+        for (int s = 0; s < 16; ++s)
+            lds[s * 512 + rr * 16 + kk] = cmul(v[s], cmul(t1, tw512[(s * rr) & 511]));  // w_512^{-s rr}
+        load(tc + gridDim.x < tiles ? tc + gridDim.x : tc);
+        __syncthreads();
+    };
+    load(t < tiles ? t : 0);  // (the launch gives every workgroup a tile)
+    tw512[tid] = P.tw[uint32_t(tid) << (P.log2L - 9)];
     __syncthreads();
-    const int p = (tid >> 4) & 1, s2 = tid >> 5;
-    float2 tb[16], t4[16];
+    if (t < tiles) stage_a(t);
+    while (t < tiles) {
+        const uint32_t blk = addr::sym2_block(t, LL1, LL2);
+        const uint32_t tt = opaque(uint32_t(tid));
+        const uint32_t p = (tt >> 4) & 1u, s2 = tt >> 5;
+        float2 u[16], tb[16];
 #pragma unroll
-    for (int m = 0; m < 16; ++m) v[m] = lds[s2 * 512 + (p + 2 * m) * 16 + kk];
+        for (int m = 0; m < 16; ++m) u[m] = lds[s2 * 512 + (p + 2 * m) * 16 + kk];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        tb[i] = root_of(P.tw, P.log2L, 5, uint32_t(p * i));                     // w_32^{-p i}
-        t4[i] = root_of(P.tw, P.log2L, LL2 + 5, uint32_t(i + 16 * p) * jc);  // w_N2^{-q0 jc}
+        for (int i = 1; i < 16; ++i) tb[i] = tw512[(16 * p * i) & 511];  // w_32^{-p i}
+        stage_b<2>(u, tb, int(p));
+        const float2 g = tjc[s2];  // w_{16 N2}^{-s jc}
+        const uint32_t dbase = addr::sym2w_store_base(N1, blk, tid, LL1);
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            *off32(P.dst, dbase + addr::sym2w_store_off(N1, i)) = cmul(u[i], cmul(g, tjc[16 + i + 16 * p]));
+        __syncthreads();
+        t += gridDim.x;
+        if (t < tiles) stage_a(t);
     }
-    stage_b<2>(v, tb, p);
-    float2 *dst = P.dst + addr::sym2w_store_base(N1, blk, tid, LL1);
-#pragma unroll
-    for (int i = 0; i < 16; ++i) dst[addr::sym2w_store_off(N1, i)] = cmul(v[i], t4[i]);
 }
 
 bool sym_shape_ok(const SymPass &p, int &ll1, int &ll2, int &lr2)
@@ -495,6 +521,8 @@ uint32_t sym_resident_groups(int pass, const SymPass &p)
 {
     int ll1 = 0, ll2 = 0, lr2 = 0;
     if (!sym_children(p, ll1, ll2, lr2)) return 0;
+    if (pass == 2)
+        return lr2 != 5 ? 0 : ll1 == 8 ? resident(sym_middle_wide_kernel<8, 10>, 512) : resident(sym_middle_wide_kernel<9, 10>, 512);
     if (pass == 1) {
         switch (ll1) {
         case 9: return resident(sym_first_long_kernel<true, 9>, 512);
@@ -530,9 +558,9 @@ hipError_t launch_sym_middle(const SymPass &p, hipStream_t s)
     if (lr2 == 5) {
         const dim3 grid(addr::sym2w_groups(uint32_t(p.N1), uint32_t(p.N2)));
         if (ll1 == 8)
-            hipLaunchKernelGGL((sym_middle_wide_kernel<8, 10>), grid, dim3(512), 0, s, p);
+            hipLaunchKernelGGL((sym_middle_wide_kernel<8, 10>), persistent(grid, p.resident2), dim3(512), 0, s, p, grid.x);
         else
-            hipLaunchKernelGGL((sym_middle_wide_kernel<9, 10>), grid, dim3(512), 0, s, p);
+            hipLaunchKernelGGL((sym_middle_wide_kernel<9, 10>), persistent(grid, p.resident2), dim3(512), 0, s, p, grid.x);
         return hipGetLastError();
     }
     const dim3 grid(addr::sym2_groups(uint32_t(p.N1), uint32_t(p.N2)));
