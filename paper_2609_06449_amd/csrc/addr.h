@@ -125,9 +125,14 @@ namespace addr {
 //            against 262 / 276 / 243 (0.756) with jc fastest.
 //   L = 1024 (16384^2): r (q0) fastest in passes 1 (3), kb fastest in pass 2:
 //            1215 / 879 / 1328, 3.43 ms, against 1309 / 922 / 1399 (3.67).
+//   L1 = 512 with N2 = 2^15 (8192 x 32768, the wide form): r fastest in
+//            pass 1 (974-1014 against 1012-1037 us; at 8192^2 it measured
+//            247 against 220 us), vb fastest in pass 3 (sym3r_block: 1157-
+//            1172 against 1172-1181 us).
 PACO_HD uint32_t sym1_block(uint32_t g, uint32_t N2, uint32_t ll = 8)
 {
-    return ll >= 10 ? (g & 15u) * (N2 >> 4) + (g >> 4) : g;  // r fastest : cb fastest
+    const bool r_fastest = ll >= 10 || (ll == 9 && N2 >= 32768u);
+    return r_fastest ? (g & 15u) * (N2 >> 4) + (g >> 4) : g;  // r fastest : cb fastest
 }
 PACO_HD uint32_t sym3_block(uint32_t g, uint32_t N1, uint32_t ll = 8)
 {
@@ -215,11 +220,11 @@ PACO_HD uint32_t sym2w_store_base(uint32_t N1, uint32_t blk, uint32_t tid, uint3
 }
 PACO_HD uint32_t sym2w_store_off(uint32_t N1, uint32_t i) { return i * N1; }
 PACO_HD uint32_t sym2w_groups(uint32_t N1, uint32_t N2) { return (N2 >> 5) * (N1 >> 8); }
-// Pass 3 at L = 2^ll >= 512 (the persistent kernels): tile (q0, vb),
-// q0 < R fastest at ll >= 10 as in sym3_block
+// Pass 3 at L = 2^ll >= 512 (the persistent kernels): tile (q0, vb), q0
+// fastest at ll >= 10 for R = 16 as in sym3_block, vb fastest otherwise
 PACO_HD uint32_t sym3r_block(uint32_t g, uint32_t N1, uint32_t ll, uint32_t lr)
 {
-    return ll >= 10 ? (g & ((1u << lr) - 1u)) * (N1 >> 4) + (g >> lr) : g;
+    return ll >= 10 && lr == 4 ? (g & 15u) * (N1 >> 4) + (g >> 4) : g;
 }
 // thread (cl, jl) loads row R (jl + (L/16) i) + q0, column 16 vb + cl
 PACO_HD uint32_t sym3r_load_base(uint32_t N1, uint32_t blk, uint32_t tid, uint32_t lr)
