@@ -122,3 +122,21 @@ def test_stage_hooks_compose_to_execute_and_in_place(N1, N2, p, b):
     assert np.array_equal(buf.cpu().numpy().view(np.uint64), y.view(np.uint64))
     plan.close()
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("p,b,mixed", [(2, 2, False), (512, 8, False), (32, 16, True)])
+def test_wide_output_independent_of_b_and_p(p, b, mixed):
+    # the digit reversals of the layouts cancel in the symmetric form, so
+    # neither b nor p reaches an address: every (b, p) runs the same passes
+    N1, N2 = 4096, 32768
+    x = inputs.normal(N1 * N2, seed=13)
+    xd = _dev(x)
+    base = paco.Plan(N1, N2, 64, 8)
+    want = _execute(base, xd).cpu().numpy()
+    base.close()
+    plan = paco.Plan(N1, N2, p, b, mixed=mixed)
+    assert plan.has_split == 2 and plan.launches == 3, plan.description
+    got = _execute(plan, xd).cpu().numpy()
+    assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+    plan.close()
+    torch.cuda.empty_cache()
